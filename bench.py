@@ -1,0 +1,237 @@
+#!/usr/bin/env python3
+"""Benchmark of the real-fluid property path on one MI355X.
+
+Workload: the 128^3 = 2,097,152-cell supercritical CH4/O2 Taylor-Green flame field
+(8 species, dense synthetic k_ij), state given as (rho, e, Y) with a previous-iterate
+temperature guess, evaluated by props_pr in FP64: Newton T-inversion, Peng-Robinson
+departures, h, cp, sound speed, Chung viscosity and conductivity.  One step = one
+props_pr call over the whole field.  Inputs are resident in HBM; three copies of the
+input and output fields are rotated so the 256 MB last-level cache cannot serve them.
+
+Prints one JSON line.  Extra keys report the mixed-precision path (throughput and error
+against the FP64 path), and the CPU oracle timed on a sample of the same field.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 VALU cost of each special function in the gfx950 build of this library
+# (instructions of the device-library routine).
+SP_COST = {"div": 10, "sqrt": 20, "cbrt": 30, "exp": 40, "expm1": 51, "log": 96}
+# MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops (FMA).
+FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+def ops_per_cell(ns, evals, transport=True):
+    """Algorithmic FP64 work of one (rho, e, Y) cell in VALU lane-operations: every add,
+    multiply or fused multiply-add of the method's formulas counts 1, each special
+    function its instruction cost (SP_COST).  `evals` = e(T) evaluations of the inversion."""
+    sp = lambda **k: sum(SP_COST[n] * c for n, c in k.items())  # noqa: E731
+    ops = 5 * ns + sp(div=1)                       # composition, X, W, b_m
+    ops += 25 * ns                                 # NASA-7 mixture coefficients (2 ranges)
+    ops += 7 + sp(div=3, log=1)                    # v, departure log L at fixed v
+    per_eval = 2 * ns * ns + 8 * ns + 29 + sp(div=3, sqrt=1)
+    ops += evals * per_eval
+    ops += per_eval + 40 + sp(div=15, log=1, sqrt=1)   # final state, P, h, e, cp, c
+    if transport:
+        ops += 1 + sp(sqrt=1, log=1, exp=1)
+        ops += ns * (7 + SP_COST["div"] + 2 * SP_COST["exp"])   # species low-pressure viscosity
+        ops += 6 * (ns * (ns + 1) // 2 + ns)       # six pseudo-mixture quadratic forms
+        ops += 22 + sp(div=5, cbrt=1)              # pseudo-critical constants
+        ops += 50 + sp(div=4, exp=2, expm1=1, sqrt=1)    # viscosity
+        ops += 57 + sp(div=7, sqrt=2, exp=1, expm1=1)    # conductivity
+    return ops
+
+
+def bytes_per_cell(ns, guess=True, status=True):
+    """Algorithmic HBM bytes: each input read once, each output written once."""
+    inputs = (2 + ns + (1 if guess else 0)) * 8     # rho, e, Y[ns], T_guess
+    outputs = 10 * 8 + (1 if status else 0)         # T P Z rho h e cp c mu lambda + status
+    return inputs + outputs
+
+
+def cpu_baseline(res, target_s=15.0):
+    """The CPU oracle, as it stands, on a strided sample of the same field (all host cores)."""
+    import oracle
+    import synth
+    sp = synth.load_species(synth.FLAME_SPECIES)
+    kij = synth.synthetic_kij(8)
+    P, T, Y = synth.flame_field(res, seed=1)
+    om = oracle.Mech(sp, kij)
+    threads = oracle.max_threads()
+    # calibrate on a small sample, then size the timed sample to ~target_s
+    idx = np.arange(0, T.size, 997)
+    st = om.state_PT(P[idx], T[idx], np.ascontiguousarray(Y[:, idx]), transport=False)
+    t0 = time.perf_counter()
+    om.state_rhoe(st["rho"], st["e"], np.ascontiguousarray(Y[:, idx]))
+    per_cell = (time.perf_counter() - t0) / idx.size
+    m = int(min(T.size, max(idx.size, target_s / max(per_cell, 1e-9))))
+    stride = max(1, T.size // m)
+    idx = np.arange(0, T.size, stride)
+    Ys = np.ascontiguousarray(Y[:, idx])
+    st = om.state_PT(P[idx], T[idx], Ys, transport=False)
+    t0 = time.perf_counter()
+    om.state_rhoe(st["rho"], st["e"], Ys)
+    dt = time.perf_counter() - t0
+    return {"value": idx.size / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": f"every {stride}th cell of the {res}^3 field ({idx.size} cells), FP64 (rho,e,Y) "
+                      f"by bisection + Chung transport, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--res", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+              "cells are independent, so N GPUs would each evaluate their own field slab.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2312_04830_amd as props
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    sp = synth.load_species(synth.FLAME_SPECIES)
+    ns = len(sp)
+    kij = synth.synthetic_kij(ns)
+    P, T, Y = synth.flame_field(args.res, seed=1)
+    n = T.size
+    Tg = synth.temperature_guess(T)
+    mech = props.Mechanism(sp, kij)
+
+    def dt(a):
+        return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+    # the solver state (rho, e) of this field, from the library's own (P,T,Y) path
+    Pd, Td, Yd = dt(P), dt(T), dt(Y)
+    rho0 = torch.empty(n, dtype=torch.float64, device=dev)
+    e0 = torch.empty_like(rho0)
+    props.pr(mech, props.PTY, props.FP64, {"P": Pd, "T": Td, "Y": Yd}, {"rho": rho0, "e": e0}, n)
+    torch.cuda.synchronize()
+    del Pd, Td
+
+    NCOPY = 3
+    ins, outs, stats = [], [], []
+    for _ in range(NCOPY):
+        ins.append({"rho": rho0.clone(), "e": e0.clone(), "Y": Yd.clone(), "T_guess": dt(Tg)})
+        outs.append({k: torch.empty(n, dtype=torch.float64, device=dev)
+                     for k in ("T", "P", "Z", "rho", "h", "e", "cp", "c", "mu", "lambda")})
+        stats.append(torch.empty(n, dtype=torch.uint8, device=dev))
+
+    def step(i, prec=props.FP64):
+        c = i % NCOPY
+        props.pr(mech, props.RHOEY, prec, ins[c], outs[c], n, status=stats[c], stream=stream)
+
+    def timed(prec, steps, warmup):
+        for i in range(warmup):
+            step(i, prec)
+        torch.cuda.synchronize()
+        e0_, e1_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0_.record(stream)
+        for i in range(steps):
+            step(i, prec)
+        e1_.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return e0_.elapsed_time(e1_) / steps, wall
+
+    ms, wall = timed(props.FP64, args.steps, args.warmup)
+    value = n / (ms * 1e-3)
+
+    # diagnostics outside the timed region: status and Newton evaluations of this field
+    it = torch.empty(n, dtype=torch.uint8, device=dev)
+    o_ref = {k: torch.empty(n, dtype=torch.float64, device=dev)
+             for k in ("T", "P", "Z", "rho", "h", "e", "cp", "c", "mu", "lambda")}
+    o_ref["iters"] = it
+    st_ref = torch.empty(n, dtype=torch.uint8, device=dev)
+    props.pr(mech, props.RHOEY, props.FP64, ins[0], o_ref, n, status=st_ref, stream=stream)
+    torch.cuda.synchronize()
+    mean_evals = float(it.double().mean().item())
+    flagged = int((st_ref != 0).sum().item())
+    t_err = float(((o_ref["T"] / dt(T)) - 1).abs().max().item())
+
+    ops = ops_per_cell(ns, mean_evals)
+    achieved = 2.0 * ops * n / (ms * 1e-3) / 1e12        # TFLOP/s (FMA = 2 flops)
+    bpc = bytes_per_cell(ns)
+    hbm = bpc * n / (ms * 1e-3) / 1e9
+    rec = {
+        "metric": "cells/s property eval: FP64 PR vs mixed/DNN at stated err; p50/p99 latency",
+        "value": value,
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.res}^3 supercritical CH4/O2 Taylor-Green flame field, 8 species, "
+                               "(rho,e,Y)->T Newton + PR departures + Chung mu/lambda, FP64, T_guess",
+                   "cells": n, "species": ns, "mode": "RHOEY", "precision": "FP64",
+                   "kij": "dense synthetic U[0,0.1]"},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "ops_per_cell": ops, "mean_newton_evals": mean_evals,
+                     "hbm_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS, "bytes_per_cell": bpc,
+                     "kernel": "pr_kernel<8, RHOEY, FP64, transport>"},
+        "flagged_cells": flagged,
+        "max_rel_T_error_vs_field": t_err,
+        "timed_wall_s": wall,
+    }
+
+    if not args.no_extras:
+        # mixed precision on the same field, error against the FP64 path
+        ms_mx, _ = timed(props.MIXED, max(10, args.steps // 2), 3)
+        o_mx = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in o_ref if k != "iters"}
+        props.pr(mech, props.RHOEY, props.MIXED, ins[0], o_mx, n, stream=stream)
+        torch.cuda.synchronize()
+        err = {}
+        for k in ("T", "rho", "h", "cp", "c", "mu", "lambda", "P"):
+            ref = o_ref[k]
+            if k == "h":
+                scale = ref.abs() + 1e5
+            else:
+                scale = ref.abs()
+            r = ((o_mx[k] - ref).abs() / scale)
+            err[k] = {"max": float(r.max().item()), "rms": float(r.pow(2).mean().sqrt().item())}
+        rec["mixed"] = {"value": n / (ms_mx * 1e-3), "unit": "cells/s", "ms_per_step": ms_mx,
+                        "speedup_vs_fp64": ms / ms_mx, "rel_err_vs_fp64": err}
+        # no temperature guess: Newton starts from the top of the bracket
+        ins_ng = [{k: v for k, v in d.items() if k != "T_guess"} for d in ins]
+        save = ins
+        ins = ins_ng
+        ms_ng, _ = timed(props.FP64, max(10, args.steps // 2), 2)
+        ins = save
+        rec["fp64_no_guess"] = {"value": n / (ms_ng * 1e-3), "ms_per_step": ms_ng}
+
+    if not args.no_cpu_baseline:
+        cb = cpu_baseline(args.res)
+        rec["cpu_baseline"] = cb
+        rec["gpu_over_cpu_oracle"] = value / cb["value"]
+    rec["paper_context"] = ("paper: 13x thermophysical-property speed-up, DNN inference on one extra GPU "
+                            "vs Cantera on 16 CPU cores (models not stated); context only")
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

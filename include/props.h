@@ -1,0 +1,130 @@
+/*
+ * props.h — C ABI of the MI355X real-fluid property library (libprops.so).
+ *
+ * Per-cell thermophysical properties of a supercritical multi-species mixture, as a
+ * pressure-based reacting-flow solver requests them once per pressure-correction loop
+ * (Section 2 of "Detailed simulation of LOX/GCH4 flame-vortex interaction in
+ * supercritical Taylor-Green flows with machine learning"), and the neural-network
+ * surrogate that replaces them (Section 4).
+ *
+ * Conventions for every call:
+ *   - SI units.  h and e are mass-specific and absolute (they include the enthalpy of
+ *     formation), cp in J/(kg K), sound speed c in m/s, mu in Pa s, lambda in W/(m K).
+ *   - Arrays are structure-of-arrays device pointers (hipMalloc'd or any device tensor),
+ *     unless the argument says "host".  Y is species-major: Y[i * n + k] is the mass
+ *     fraction of species i in cell k.  The caller owns every array; the library owns only
+ *     its handles and the device copies of tables and weights it builds.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Property calls are
+ *     asynchronous on that stream and never synchronise the host.
+ *   - Return codes: 0 = OK, negative = PROPS_E*; props_last_error() then describes the
+ *     failure (thread-local, valid until the next failing call on the same thread).
+ *   - Per-cell outcome flags go to an optional uint8 status array (PROPS_ST_*).
+ */
+#ifndef PROPS_H
+#define PROPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ error codes */
+enum {
+    PROPS_OK = 0,
+    PROPS_EINVAL = -1,    /* bad argument (null handle, n < 0, unsupported mode ...) */
+    PROPS_ENOMEM = -2,    /* device or host allocation failed */
+    PROPS_EHIP = -3,      /* a HIP runtime call failed (message names it) */
+    PROPS_ETOOBIG = -4,   /* request exceeds a fixed limit (species count, budget) */
+    PROPS_ETIMEDOUT = -5, /* serve_wait ran out of time */
+    PROPS_ENOTREADY = -6  /* object not in a usable state (e.g. network not trained) */
+};
+
+/* ------------------------------------------------------------------ per-cell status bits */
+enum {
+    PROPS_ST_NONPHYS = 1,      /* NaN input, Y_i < -1e-12, |sum Y - 1| > 1e-6, rho/T/P <= 0,
+                                  v <= b_m, or no root above B; outputs are NaN */
+    PROPS_ST_NEWTON_MAXIT = 2, /* T inversion hit the iteration limit; outputs at last iterate */
+    PROPS_ST_BRACKET = 4,      /* the temperature solving e(T) = e* is outside [60, 5000] K;
+                                  outputs are NaN */
+    PROPS_ST_THREE_ROOT = 8,   /* (P,T,Y): the cubic had three roots above B */
+    PROPS_ST_GIBBS_TIE = 16,   /* liquid- and vapour-like roots tie in Gibbs energy to 1e-12;
+                                  the larger Z was taken */
+    PROPS_ST_CV_NONPOS = 32,   /* c_v <= 0 at the solution (mechanically odd state) */
+    PROPS_ST_OUT_OF_HULL = 64, /* surrogate: input outside the training box */
+    PROPS_ST_FALLBACK = 128    /* surrogate: cell recomputed by the PR path */
+};
+
+/* ------------------------------------------------------------------ mechanism */
+/* Raw constants of one species (host struct).  W kg/mol, Tc K, Pc Pa, Vc m^3/mol,
+ * omega acentric factor, dipole debye, kappa Chung association factor, Tmid K (NASA-7
+ * range switch; every species of a mechanism must share one), nasa_lo/nasa_hi the seven
+ * NASA coefficients below/above Tmid (a7 is not used). */
+typedef struct {
+    double W, Tc, Pc, Vc, omega, dipole, kappa, Tmid;
+    double nasa_lo[7], nasa_hi[7];
+} props_species_desc;
+
+typedef struct props_mech_s *props_mech_t;
+
+#define PROPS_MAX_SPECIES 8
+
+/* Build the device tables of a mechanism: Peng-Robinson a_c, b, kappa(omega) of
+ * Section 2 / Eq. (1) with the exact critical-point Omega constants, the van der Waals
+ * mixing matrix 1 - k_ij, NASA-7 coefficients, and Chung's per-species and pair constants.
+ * sp: host array of ns descriptors (copied).  kij: host ns*ns row-major binary-interaction
+ * matrix (symmetric, zero diagonal) or NULL for all zero.  ns in 1..PROPS_MAX_SPECIES.
+ * On success *out holds a handle bound to the current device. */
+int props_mech_create(const props_species_desc *sp, int ns, const double *kij,
+                      props_mech_t *out);
+void props_mech_destroy(props_mech_t m);
+int props_mech_num_species(props_mech_t m);
+
+/* Newton options of the (rho, e, Y) inversion: max_iter >= 1 (default 100) and the
+ * relative step size below which one last Newton step is taken (default 1e-10). */
+int props_mech_set_newton(props_mech_t m, int max_iter, double rtol);
+
+/* ------------------------------------------------------------------ property evaluation */
+enum { PROPS_PTY = 0, PROPS_RHOEY = 1 };
+enum { PROPS_FP64 = 0, PROPS_MIXED = 1 };
+
+/* Device input arrays, n cells each (Y: ns*n). Unused members may be NULL. */
+typedef struct {
+    const double *P;       /* Pa       (PROPS_PTY) */
+    const double *T;       /* K        (PROPS_PTY) */
+    const double *rho;     /* kg/m^3   (PROPS_RHOEY) */
+    const double *e;       /* J/kg     (PROPS_RHOEY) */
+    const double *Y;       /* [ns][n]  (both) */
+    const double *T_guess; /* K, optional start of the T inversion (PROPS_RHOEY) */
+} props_in;
+
+/* Device output arrays, n cells each.  A NULL member is not computed or written; with
+ * mu and lambda both NULL the transport model is skipped entirely.  iters (optional,
+ * PROPS_RHOEY only) receives the number of e(T) evaluations the inversion took, saturated
+ * at 255. */
+typedef struct {
+    double *T, *P, *Z, *rho, *h, *e, *cp, *c, *mu, *lambda;
+    uint8_t *iters;
+} props_out;
+
+/* Evaluate the Peng-Robinson property path on n independent cells.
+ *   PROPS_PTY:   given P, T, Y: solve the cubic of Eq. (1) for Z, choose among physical
+ *                roots (Z > B) by minimum Gibbs energy, then rho, h, e, cp, c (+ mu, lambda).
+ *   PROPS_RHOEY: given rho, e, Y: find T with e(T; v = W/rho, Y) = e* by bracketed Newton
+ *                iteration on [60, 5000] K, then P from Eq. (1) and every property.
+ *   PROPS_FP64:  every step in double precision.
+ *   PROPS_MIXED: mixing sums, departure functions and transport in single precision;
+ *                the cubic (discriminant and root polish), the ideal-gas energy and the
+ *                Newton residual stay in double.  Inputs and outputs are double either way.
+ * status: optional device uint8[n] (PROPS_ST_* bits).  Asynchronous on hip_stream. */
+int props_pr(props_mech_t m, int mode, int prec, const props_in *in, const props_out *out,
+             int64_t n, uint8_t *status, void *hip_stream);
+
+/* ------------------------------------------------------------------ errors */
+const char *props_last_error(void);
+const char *props_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PROPS_H */

@@ -1,0 +1,560 @@
+// Peng-Robinson property kernels for gfx950 (one lane per cell).
+//
+// What a lane computes (paper, Section 2; Eq. (1) is the Peng-Robinson equation):
+//   composition      W = 1/sum(Y_i/W_i), X_i = Y_i W / W_i, b_m = sum X_i b_i
+//   alpha / mixing   g_i = sqrt(a_c,i) |1 + kappa_i (1 - sqrt(T/Tc_i))|,
+//                    a_m = sum_ij X_i X_j (1 - k_ij) g_i g_j and its first two T-derivatives
+//                    as two mat-vecs with the (1 - k_ij) matrix
+//   ideal gas        per-cell NASA-7 mixture coefficients, one Horner each for h, cp
+//   (P,T,Y)          cubic in Z (closed form + Newton polish, double), physical roots Z > B,
+//                    minimum residual Gibbs energy between the liquid- and vapour-like root
+//   (rho,e,Y)        bracketed Newton on e(T; v, Y) = e* (v fixed, so the departure log is
+//                    computed once), bisection whenever a step leaves the bracket
+//   departures       e, h, cv, cp, (dP/dT)_v, (dP/dv)_T, sound speed
+//   transport        Chung's high-pressure viscosity and conductivity on the pseudo-mixture,
+//                    with the mole-fraction-averaged low-pressure viscosity (Section 2)
+//
+// Memory: every per-cell array is structure-of-arrays in HBM, read or written once with
+// unit stride across a wavefront.  Mechanism tables (a few KB) are read with
+// wave-uniform addresses, so they come through the scalar data cache into SGPRs and feed
+// the VALU as scalar operands; no LDS is needed for them.
+#include <cmath>
+#include <type_traits>
+
+#include "props_internal.hpp"
+
+namespace props {
+
+// ------------------------------------------------------------------ precision policies
+struct P64 {
+    using R = double;
+    static __device__ __forceinline__ R sqrt_(R x) { return sqrt(x); }
+    static __device__ __forceinline__ R log_(R x) { return log(x); }
+    static __device__ __forceinline__ R exp_(R x) { return exp(x); }
+    static __device__ __forceinline__ R expm1_(R x) { return expm1(x); }
+    static __device__ __forceinline__ R cbrt_(R x) { return cbrt(x); }
+    static __device__ __forceinline__ R div(R a, R b) { return a / b; }
+};
+
+// Single precision with the hardware transcendental unit (v_exp_f32, v_log_f32, v_rcp_f32).
+struct P32 {
+    using R = float;
+    static __device__ __forceinline__ R sqrt_(R x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ R log_(R x) { return __logf(x); }
+    static __device__ __forceinline__ R exp_(R x) { return __expf(x); }
+    static __device__ __forceinline__ R expm1_(R x) { return expm1f(x); }
+    static __device__ __forceinline__ R cbrt_(R x) { return cbrtf(x); }
+    static __device__ __forceinline__ R div(R a, R b) { return a * __builtin_amdgcn_rcpf(b); }
+};
+
+// ------------------------------------------------------------------ kernel arguments
+struct PRArgs {
+    const double *in0, *in1, *Y, *Tg;
+    double *oT, *oP, *oZ, *orho, *oh, *oe, *ocp, *oc, *omu, *olam;
+    uint8_t *status, *iters;
+    int64_t n;
+    int ns, maxit;
+    double rtol;
+};
+
+// ------------------------------------------------------------------ mixing sums
+// a_m, da_m/dT, d2a_m/dT2 at temperature T (sT = sqrt(T)).  With u_i = X_i g_i and
+// q_i = sign(f_i) X_i sqrt(a_c,i) kappa_i / sqrt(Tc_i), the derivative vector is
+// u'_i = -q_i / (2 sqrt T) and u''_i = -u'_i / (2T), so
+//   a_m = u.K.u,  a_m' = 2 u'.K.u,  a_m'' = -a_m'/(2T) + 2 u'.K.u'.
+template <class PM, int NS>
+__device__ __forceinline__ void mix_a(const MixTab<typename PM::R, NS> *__restrict__ t,
+                                      const typename PM::R (&X)[NS], typename PM::R T,
+                                      typename PM::R sT, typename PM::R &am,
+                                      typename PM::R &am1, typename PM::R &am2)
+{
+    using R = typename PM::R;
+    R u[NS], q[NS];
+#pragma unroll
+    for (int i = 0; i < NS; i++) {
+        R f = t->k1[i] - t->k2[i] * sT;
+        R xs = X[i] * t->sqac[i];
+        u[i] = xs * fabs(f);
+        q[i] = copysign(xs * t->k2[i], f);
+    }
+    R a = 0, aq = 0, qq = 0;
+#pragma unroll
+    for (int i = 0; i < NS; i++) {
+        R w = 0, wq = 0;
+#pragma unroll
+        for (int j = 0; j < NS; j++) {
+            w += t->K[i][j] * u[j];
+            wq += t->K[i][j] * q[j];
+        }
+        a += u[i] * w;
+        aq += q[i] * w;
+        qq += q[i] * wq;
+    }
+    R c1 = PM::div(R(-0.5), sT);
+    am = a;
+    am1 = R(2) * c1 * aq;
+    am2 = PM::div(-am1, R(2) * T) + R(2) * c1 * c1 * qq;
+}
+
+// ------------------------------------------------------------------ NASA-7 mixture
+struct Nasa {
+    double c[2][5];  // sum_i Y_i R/W_i a_k,i  (cp polynomial), per range
+    double a6[2];    // sum_i Y_i R/W_i a6,i
+    double rw;       // R/W of the mixture
+    double Tmid;
+    // mass-specific ideal-gas h and cp at T
+    __device__ __forceinline__ void eval(double T, double &h, double &cp) const
+    {
+        const int r = (T >= Tmid) ? 1 : 0;
+        const double c0 = c[r][0], c1 = c[r][1], c2 = c[r][2], c3 = c[r][3], c4 = c[r][4];
+        cp = c0 + T * (c1 + T * (c2 + T * (c3 + T * c4)));
+        h = T * (c0 + T * (c1 * 0.5 + T * (c2 * (1.0 / 3.0) + T * (c3 * 0.25 + T * (c4 * 0.2))))) + a6[r];
+    }
+};
+
+// ------------------------------------------------------------------ Chung transport
+// Chung et al. (1988) viscosity coefficients E_i = a + b omega + c mu_r^4 + d kappa.
+__constant__ double kChungE[10][4] = {
+    {6.324, 50.412, -51.680, 1189.0},      {1.210e-3, -1.154e-3, -6.257e-3, 0.03728},
+    {5.283, 254.209, -168.48, 3898.0},     {6.623, 38.096, -8.464, 31.42},
+    {19.745, 7.630, -14.354, 31.53},       {-1.900, -12.537, 4.985, -18.15},
+    {24.275, 3.450, -11.291, 69.35},       {0.7972, 1.117, 0.01235, -4.117},
+    {-0.2382, 0.06770, -0.8163, 4.025},    {0.06863, 0.3479, 0.5926, -0.727}};
+// Chung et al. (1988) conductivity coefficients B_i.
+__constant__ double kChungB[7][4] = {
+    {2.4166, 0.74824, -0.91858, 121.72},   {-0.50924, -1.5094, -49.991, 69.983},
+    {6.6107, 5.6207, 64.760, 27.039},      {14.543, -8.9139, -5.6379, 74.344},
+    {0.79274, 0.82019, -0.69369, 6.3173},  {-5.8634, 12.801, 9.5893, 65.529},
+    {91.089, 128.11, -54.217, 523.81}};
+
+// Chung's density function G2 for coefficients c1..c5 (c = pointer to the 5 values).
+template <class PM>
+__device__ __forceinline__ typename PM::R chung_G2(typename PM::R y, typename PM::R G1,
+                                                   typename PM::R iy, const typename PM::R *c)
+{
+    using R = typename PM::R;
+    R t1 = c[0] * (-PM::expm1_(-c[3] * y)) * iy;
+    R num = t1 + c[1] * G1 * PM::exp_(c[4] * y) + c[2] * G1;
+    return PM::div(num, c[0] * c[3] + c[1] + c[2]);
+}
+
+template <class PM, int NS>
+__device__ __forceinline__ typename PM::R qform(const typename PM::R (&C)[NS][NS],
+                                                const typename PM::R (&X)[NS])
+{
+    using R = typename PM::R;
+    R s = 0;
+#pragma unroll
+    for (int i = 0; i < NS; i++) {
+        R w = 0;
+#pragma unroll
+        for (int j = i; j < NS; j++) w += C[i][j] * X[j];
+        s += X[i] * w;
+    }
+    return s;
+}
+
+// mu [Pa s] and lambda [W/(m K)] at T, molar density rhom [mol/m^3], ideal-gas molar Cv.
+template <class PM, int NS>
+__device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restrict__ t,
+                                      const typename PM::R (&X)[NS], typename PM::R T,
+                                      typename PM::R rhom, typename PM::R Cv, bool want_mu,
+                                      bool want_lam, double *omu, double *olam)
+{
+    using R = typename PM::R;
+    // mole-fraction-averaged low-pressure viscosity; T*^-0.14874 shared by all species
+    const R sT = PM::sqrt_(T);
+    const R Tp = PM::exp_(R(-0.14874) * PM::log_(T));
+    R eta0 = 0;
+#pragma unroll
+    for (int i = 0; i < NS; i++) {
+        R ts = t->tsc[i] * T;
+        R om = t->tsp[i] * Tp + R(0.52487) * PM::exp_(R(-0.77320) * ts) +
+               R(2.16178) * PM::exp_(R(-2.43787) * ts);
+        eta0 += PM::div(X[i] * t->mu0A[i], om);
+    }
+    eta0 *= sT;
+    // pseudo-mixture parameters (Chung's mixing rules)
+    const R s3 = qform<PM, NS>(t->S3, X);
+    const R es3 = qform<PM, NS>(t->ES3, X);
+    const R ws3 = qform<PM, NS>(t->WS3, X);
+    const R esm = qform<PM, NS>(t->ESM, X);
+    const R mu4 = qform<PM, NS>(t->MU4, X);
+    const R km = qform<PM, NS>(t->KAP, X);
+    const R is3 = PM::div(R(1), s3);
+    const R sm = PM::cbrt_(s3);
+    const R em = es3 * is3;                       // (eps/k)_m
+    const R mq = PM::div(esm, em * sm * sm);
+    const R Mm = mq * mq;                         // g/mol
+    const R wm = ws3 * is3;
+    const R vs = sm * R(1.0 / 0.809);
+    const R Vc23 = vs * vs;                       // Vc_m^(2/3), cm^2/mol^(2/3)
+    const R Vcm = Vc23 * vs;                      // cm^3/mol
+    const R Tcm = R(1.2593) * em;
+    // mu_rm^4 = (131.3 mu_m)^4 / (Vcm Tcm)^2, mu_m^4 = s3 * mu4
+    const R vt = Vcm * Tcm;
+    const R c131 = R(131.3 * 131.3 * 131.3 * 131.3);
+    const R mr4 = PM::div(c131 * s3 * mu4, vt * vt);
+    const R y = rhom * R(1e-6) * Vcm * R(1.0 / 6.0);
+    const R iy = PM::div(R(1), y);
+    const R om1 = R(1) - y;
+    const R G1 = PM::div(R(1) - R(0.5) * y, om1 * om1 * om1);
+    if (want_mu) {
+        R E[10];
+#pragma unroll
+        for (int i = 0; i < 10; i++)
+            E[i] = R(kChungE[i][0]) + R(kChungE[i][1]) * wm + R(kChungE[i][2]) * mr4 + R(kChungE[i][3]) * km;
+        const R G2 = chung_G2<PM>(y, G1, iy, E);
+        const R its = PM::div(em, T);  // 1/T*, T* = T/(eps/k)_m
+        const R muss = E[6] * y * y * G2 * PM::exp_(E[7] + E[8] * its + E[9] * its * its);
+        const R mu = eta0 * (PM::div(R(1), G2) + E[5] * y) +
+                     PM::div(R(36.344e-7) * muss * PM::sqrt_(Mm * Tcm), Vc23);
+        *omu = (double)mu;
+    }
+    if (want_lam) {
+        R Bc[7];
+#pragma unroll
+        for (int i = 0; i < 7; i++)
+            Bc[i] = R(kChungB[i][0]) + R(kChungB[i][1]) * wm + R(kChungB[i][2]) * mr4 + R(kChungB[i][3]) * km;
+        const R G2 = chung_G2<PM>(y, G1, iy, Bc);
+        const R Tr = PM::div(T, Tcm);
+        const R al = Cv * R(1.0 / kR) - R(1.5);
+        const R be = R(0.7862) - R(0.7109) * wm + R(1.3168) * wm * wm;
+        const R Zr = R(2.0) + R(10.5) * Tr * Tr;
+        const R psi = R(1) + al * PM::div(R(0.215) + R(0.28288) * al - R(1.061) * be + R(0.26665) * Zr,
+                                          R(0.6366) + be * Zr + R(1.061) * al * be);
+        const R Mkg = Mm * R(1e-3);
+        const R q = PM::div(R(3.586e-3) * PM::sqrt_(PM::div(Tcm, Mkg)), Vc23);
+        const R lam = PM::div(R(31.2) * eta0 * psi, Mkg) * (PM::div(R(1), G2) + Bc[5] * y) +
+                      q * Bc[6] * y * y * PM::sqrt_(Tr) * G2;
+        *olam = (double)lam;
+    }
+}
+
+// ------------------------------------------------------------------ cubic (double)
+// Real roots of Z^3 + c2 Z^2 + c1 Z + c0 for Eq. (1) in Z, ascending; returns the count.
+__device__ __forceinline__ int cubic_roots(double A, double B, double z[3])
+{
+    const double c2 = B - 1.0;
+    const double c1 = A - 3.0 * B * B - 2.0 * B;
+    const double c0 = -(A * B - B * B - B * B * B);
+    const double sh = c2 * (1.0 / 3.0);
+    const double p = c1 - c2 * sh;
+    const double q = (2.0 * c2 * c2 * c2 - 9.0 * c2 * c1) * (1.0 / 27.0) + c0;
+    const double D = 0.25 * q * q + p * p * p * (1.0 / 27.0);
+    int nr;
+    if (D > 0.0) {
+        const double C = -0.5 * q - copysign(sqrt(D), q);
+        const double t = cbrt(C);
+        const double t1 = (t != 0.0) ? t - p / (3.0 * t) : 0.0;
+        z[0] = t1 - sh;
+        nr = 1;
+    } else {
+        const double r = sqrt(-p * (1.0 / 3.0));
+        double arg = (r > 0.0) ? -0.5 * q / (r * r * r) : 0.0;
+        arg = fmin(1.0, fmax(-1.0, arg));
+        const double ph = acos(arg) * (1.0 / 3.0);
+        const double tpi3 = 2.0943951023931957;  // 2 pi / 3
+        z[0] = 2.0 * r * cos(ph + tpi3) - sh;
+        z[1] = 2.0 * r * cos(ph - tpi3) - sh;
+        z[2] = 2.0 * r * cos(ph) - sh;
+        nr = 3;
+    }
+    // Newton polish on the cubic itself
+    for (int k = 0; k < nr; k++) {
+#pragma unroll
+        for (int it = 0; it < 2; it++) {
+            const double x = z[k];
+            const double f = ((x + c2) * x + c1) * x + c0;
+            const double fp = (3.0 * x + 2.0 * c2) * x + c1;
+            if (fp != 0.0) {
+                const double dx = f / fp;
+                if (fabs(dx) < 1e-3 * fabs(x) + 1e-12) z[k] = x - dx;
+            }
+        }
+    }
+    return nr;
+}
+
+__device__ __forceinline__ double gdep_RT(double Z, double A, double B)
+{
+    return Z - 1.0 - log(Z - B) -
+           A / (2.0 * kSqrt2 * B) * log((Z + (1.0 + kSqrt2) * B) / (Z + (1.0 - kSqrt2) * B));
+}
+
+// ------------------------------------------------------------------ the kernel
+template <int NS, int MODE, int PREC, bool TRANSPORT>
+__global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict__ tt,
+                                                 const MixTab<double, NS> *__restrict__ tmd,
+                                                 const MixTab<float, NS> *__restrict__ tmf,
+                                                 PRArgs a)
+{
+    using PM = typename std::conditional<PREC == PROPS_FP64, P64, P32>::type;
+    using R = typename PM::R;
+    const MixTab<R, NS> *__restrict__ tm;
+    if constexpr (PREC == PROPS_FP64) tm = tmd; else tm = tmf;
+
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    const int64_t n = a.n;
+
+    // ---- composition and input checks
+    double y[NS];
+    double sy = 0.0, syw = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < NS; i++) {
+        y[i] = (i < a.ns) ? a.Y[(int64_t)i * n + k] : 0.0;
+        bad |= !(y[i] >= -1e-12);
+        sy += y[i];
+        syw += y[i] * tt->invW[i];
+    }
+    bad |= !(fabs(sy - 1.0) <= 1e-6);
+    const double in0 = a.in0[k], in1 = a.in1[k];
+    if (MODE == PROPS_PTY) bad |= !(in0 > 0.0) || !(in1 > 0.0);
+    else bad |= !(in0 > 0.0) || !(in1 == in1);
+    const double W = 1.0 / syw;
+    double X[NS];
+    R Xr[NS];
+    double bm = 0.0;
+#pragma unroll
+    for (int i = 0; i < NS; i++) {
+        X[i] = y[i] * tt->invW[i] * W;
+        Xr[i] = (R)X[i];
+        bm += X[i] * tt->b[i];
+    }
+
+    uint8_t st = 0;
+    const double nan = __builtin_nan("");
+    double T = nan, P = nan, v = nan;
+    double am = 0, am1 = 0, am2 = 0;
+    Nasa ig;
+
+    if (!bad) {
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+#pragma unroll
+            for (int c = 0; c < 5; c++) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < NS; i++) s += y[i] * tt->RW[i] * tt->cp[r][c][i];
+                ig.c[r][c] = s;
+            }
+            double s6 = 0.0;
+#pragma unroll
+            for (int i = 0; i < NS; i++) s6 += y[i] * tt->RW[i] * tt->a6[r][i];
+            ig.a6[r] = s6;
+        }
+        double rw = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; i++) rw += y[i] * tt->RW[i];
+        ig.rw = rw;
+        ig.Tmid = tt->Tmid;
+    }
+
+    if (MODE == PROPS_PTY && !bad) {
+        // ---- (P, T, Y): cubic in Z with Gibbs selection
+        P = in0;
+        T = in1;
+        R ram, ram1, ram2;
+        mix_a<PM, NS>(tm, Xr, (R)T, (R)sqrt(T), ram, ram1, ram2);
+        am = ram, am1 = ram1, am2 = ram2;
+        const double RT = kR * T;
+        const double A = am * P / (RT * RT);
+        const double B = bm * P / RT;
+        double z[3];
+        const int nr = cubic_roots(A, B, z);
+        double zl = nan, zv = nan;
+        int np = 0;
+        for (int r = 0; r < nr; r++) {
+            if (z[r] > B) {
+                if (np == 0) zl = z[r];
+                zv = z[r];
+                np++;
+            }
+        }
+        double Z = nan;
+        if (np == 0) {
+            bad = true;
+        } else if (np == 1) {
+            Z = zv;
+        } else {
+            if (np == 3) st |= PROPS_ST_THREE_ROOT;
+            const double gl = gdep_RT(zl, A, B), gv = gdep_RT(zv, A, B);
+            const double tie = 1e-12 * fmax(1.0, fmax(fabs(gl), fabs(gv)));
+            if (fabs(gl - gv) <= tie) {
+                Z = zv;
+                st |= PROPS_ST_GIBBS_TIE;
+            } else {
+                Z = (gl < gv) ? zl : zv;
+            }
+        }
+        v = Z * RT / P;
+    } else if (MODE == PROPS_RHOEY && !bad) {
+        // ---- (rho, e, Y): bracketed Newton on e(T) at fixed v
+        v = W / in0;
+        if (!(v > bm)) {
+            bad = true;
+        } else {
+            const double estar = in1;
+            const double L = log((v + (1.0 + kSqrt2) * bm) / (v + (1.0 - kSqrt2) * bm));
+            const R Lw = (R)(L / (2.0 * kSqrt2 * bm * W));  // departure (per mole) -> J/kg factor
+            double lo = kTlo, hi = kThi;
+            T = kThi;
+            if (a.Tg) {
+                const double g = a.Tg[k];
+                if (g > kTlo && g < kThi) T = g;
+            }
+            bool fin = false, conv = false;
+            int it = 0;
+            for (; it < a.maxit; it++) {
+                R ram, ram1, ram2;
+                mix_a<PM, NS>(tm, Xr, (R)T, (R)sqrt(T), ram, ram1, ram2);
+                double h_ig, cp_ig;
+                ig.eval(T, h_ig, cp_ig);
+                const double edep = (double)(((R)T * ram1 - ram) * Lw);
+                const double cvdep = (double)((R)T * ram2 * Lw);
+                const double r = h_ig - ig.rw * T + edep - estar;
+                const double rp = cp_ig - ig.rw + cvdep;
+                if (r > 0.0) hi = T;
+                else if (r < 0.0) lo = T;
+                else { conv = true; break; }
+                double Tn = T - r / rp;
+                if (!(rp > 0.0) || !(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
+                const double dT = Tn - T;
+                T = Tn;
+                if (fin) { conv = true; break; }
+                if (fabs(dT) <= a.rtol * T) fin = true;
+            }
+            if (a.iters) a.iters[k] = (uint8_t)min(it + (conv ? 1 : 0), 255);
+            if (!conv) st |= PROPS_ST_NEWTON_MAXIT;
+            if (T <= kTlo * (1.0 + 1e-9) || T >= kThi * (1.0 - 1e-9)) {
+                st |= PROPS_ST_BRACKET;
+                bad = true;
+            } else {
+                R ram, ram1, ram2;
+                mix_a<PM, NS>(tm, Xr, (R)T, (R)sqrt(T), ram, ram1, ram2);
+                am = ram, am1 = ram1, am2 = ram2;
+                const double den = v * v + 2.0 * bm * v - bm * bm;
+                P = kR * T / (v - bm) - am / den;
+            }
+        }
+    }
+
+    if (bad) {
+        if (!(st & PROPS_ST_BRACKET)) st |= PROPS_ST_NONPHYS;
+        st &= (PROPS_ST_NONPHYS | PROPS_ST_BRACKET | PROPS_ST_NEWTON_MAXIT);
+        if (a.oT) a.oT[k] = nan;
+        if (a.oP) a.oP[k] = nan;
+        if (a.oZ) a.oZ[k] = nan;
+        if (a.orho) a.orho[k] = nan;
+        if (a.oh) a.oh[k] = nan;
+        if (a.oe) a.oe[k] = nan;
+        if (a.ocp) a.ocp[k] = nan;
+        if (a.oc) a.oc[k] = nan;
+        if (a.omu) a.omu[k] = nan;
+        if (a.olam) a.olam[k] = nan;
+        if (a.status) a.status[k] = st;
+        return;
+    }
+
+    // ---- departure functions and derived properties at (v, T)
+    double h_ig, cp_ig;
+    ig.eval(T, h_ig, cp_ig);
+    const double RT = kR * T;
+    const double den = v * v + 2.0 * bm * v - bm * bm;
+    const double vb = v - bm;
+    double h, e, cp, c;
+    {
+        const R rv = (R)v, rb = (R)bm, rT = (R)T, rden = (R)den, rvb = (R)vb;
+        const R ram = (R)am, ram1 = (R)am1, ram2 = (R)am2;
+        const R L = PM::log_(PM::div(rv + R(1.0 + kSqrt2) * rb, rv + R(1.0 - kSqrt2) * rb));
+        const R Lb = PM::div(L, R(2.0 * kSqrt2) * rb);
+        const R edep = (rT * ram1 - ram) * Lb;                 // J/mol
+        const R cvdep = rT * ram2 * Lb;                        // J/(mol K)
+        const R dPdT = PM::div(R(kR), rvb) - PM::div(ram1, rden);
+        const R dPdv = -PM::div((R)RT, rvb * rvb) + PM::div(R(2) * ram * (rv + rb), rden * rden);
+        const R cvm = (R)(W * (cp_ig - ig.rw)) + cvdep;
+        const R cpm = cvm - PM::div(rT * dPdT * dPdT, dPdv);
+        const R c2 = -PM::div(rv * rv, (R)W) * PM::div(cpm, cvm) * dPdv;
+        const double hdep = (double)edep + P * v - RT;
+        h = h_ig + hdep / W;
+        e = h_ig - ig.rw * T + (double)edep / W;
+        cp = (double)cpm / W;
+        c = (c2 > R(0)) ? (double)PM::sqrt_(c2) : nan;
+        if (!(cvm > R(0))) st |= PROPS_ST_CV_NONPOS;
+    }
+    if (a.oT) a.oT[k] = T;
+    if (a.oP) a.oP[k] = P;
+    if (a.oZ) a.oZ[k] = P * v / RT;
+    if (a.orho) a.orho[k] = W / v;
+    if (a.oh) a.oh[k] = h;
+    if (a.oe) a.oe[k] = e;
+    if (a.ocp) a.ocp[k] = cp;
+    if (a.oc) a.oc[k] = c;
+    if constexpr (TRANSPORT) {
+        double mu = 0, lam = 0;
+        chung<PM, NS>(tm, Xr, (R)T, (R)(1.0 / v), (R)(W * (cp_ig - ig.rw)), a.omu != nullptr,
+                      a.olam != nullptr, &mu, &lam);
+        if (a.omu) a.omu[k] = mu;
+        if (a.olam) a.olam[k] = lam;
+    }
+    if (a.status) a.status[k] = st;
+}
+
+// ------------------------------------------------------------------ host launch
+template <int NS, int MODE, int PREC, bool TR>
+static int launch_one(const props_mech_s *m, const PRArgs &a, hipStream_t s)
+{
+    const auto *base = static_cast<const unsigned char *>(m->d_tab);
+    const auto *tt = reinterpret_cast<const ThermoTab<NS> *>(base);
+    const auto *tmd = reinterpret_cast<const MixTab<double, NS> *>(base + m->off_mixd);
+    const auto *tmf = reinterpret_cast<const MixTab<float, NS> *>(base + m->off_mixf);
+    const int64_t blocks = (a.n + 255) / 256;
+    if (blocks > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_pr: n = %lld too large", (long long)a.n);
+    hipLaunchKernelGGL((pr_kernel<NS, MODE, PREC, TR>), dim3((unsigned)blocks), dim3(256), 0, s, tt, tmd, tmf, a);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
+}
+
+template <int NS>
+static int dispatch_ns(const props_mech_s *m, int mode, int prec, bool tr, const PRArgs &a, hipStream_t s)
+{
+    if (mode == PROPS_PTY) {
+        if (prec == PROPS_FP64) return tr ? launch_one<NS, PROPS_PTY, PROPS_FP64, true>(m, a, s)
+                                          : launch_one<NS, PROPS_PTY, PROPS_FP64, false>(m, a, s);
+        return tr ? launch_one<NS, PROPS_PTY, PROPS_MIXED, true>(m, a, s)
+                  : launch_one<NS, PROPS_PTY, PROPS_MIXED, false>(m, a, s);
+    }
+    if (prec == PROPS_FP64) return tr ? launch_one<NS, PROPS_RHOEY, PROPS_FP64, true>(m, a, s)
+                                      : launch_one<NS, PROPS_RHOEY, PROPS_FP64, false>(m, a, s);
+    return tr ? launch_one<NS, PROPS_RHOEY, PROPS_MIXED, true>(m, a, s)
+              : launch_one<NS, PROPS_RHOEY, PROPS_MIXED, false>(m, a, s);
+}
+
+int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
+              const props_out *out, int64_t n, uint8_t *status, hipStream_t stream)
+{
+    PRArgs a{};
+    a.in0 = (mode == PROPS_PTY) ? in->P : in->rho;
+    a.in1 = (mode == PROPS_PTY) ? in->T : in->e;
+    a.Y = in->Y;
+    a.Tg = (mode == PROPS_RHOEY) ? in->T_guess : nullptr;
+    a.oT = out->T, a.oP = out->P, a.oZ = out->Z, a.orho = out->rho, a.oh = out->h;
+    a.oe = out->e, a.ocp = out->cp, a.oc = out->c, a.omu = out->mu, a.olam = out->lambda;
+    a.status = status;
+    a.iters = (mode == PROPS_RHOEY) ? out->iters : nullptr;
+    a.n = n;
+    a.ns = m->ns;
+    a.maxit = m->maxit;
+    a.rtol = m->rtol;
+    const bool tr = out->mu || out->lambda;
+    switch (m->nsp) {
+        case 1: return dispatch_ns<1>(m, mode, prec, tr, a, stream);
+        case 2: return dispatch_ns<2>(m, mode, prec, tr, a, stream);
+        case 4: return dispatch_ns<4>(m, mode, prec, tr, a, stream);
+        default: return dispatch_ns<8>(m, mode, prec, tr, a, stream);
+    }
+}
+
+}  // namespace props

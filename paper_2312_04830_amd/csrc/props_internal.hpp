@@ -1,0 +1,96 @@
+// Internal declarations of libprops: device table layouts, error plumbing, handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "../../include/props.h"
+
+namespace props {
+
+// ---------------------------------------------------------------- constants
+// Universal gas constant J/(mol K) (SI exact).
+constexpr double kR = 8.31446261815324;
+// Peng-Robinson Omega constants at their exact critical-point values (the roots of the
+// critical conditions dP/dv = d2P/dv2 = 0 of Eq. (1)); the paper prints them rounded to
+// 0.45724 and 0.07780 (Section 2).
+constexpr double kOmegaA = 0.45723552892138219;
+constexpr double kOmegaB = 0.077796073903888456;
+constexpr double kSqrt2 = 1.4142135623730951;
+
+// Temperature bracket of the (rho, e, Y) inversion, K.
+constexpr double kTlo = 60.0;
+constexpr double kThi = 5000.0;
+
+// ---------------------------------------------------------------- errors
+void set_error(const char *fmt, ...);
+int fail(int code, const char *fmt, ...);
+
+#define PROPS_HIP_TRY(expr)                                                              \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return ::props::fail(PROPS_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// ---------------------------------------------------------------- device tables
+// Species count the kernels are compiled for; a mechanism with ns species runs the
+// smallest NSP >= ns, the extra slots holding inert zero entries.
+constexpr int kPadSizes[4] = {1, 2, 4, 8};
+
+// Thermochemistry: always double (the ideal-gas energy carries the Newton residual).
+template <int NS>
+struct ThermoTab {
+    double invW[NS];      // 1/W_i [mol/kg]
+    double RW[NS];        // R/W_i [J/(kg K)]
+    double b[NS];         // PR co-volume b_i [m^3/mol]
+    double cp[2][5][NS];  // NASA a1..a5 per range (0: T < Tmid, 1: T >= Tmid)
+    double a6[2][NS];     // NASA a6 per range
+    double Tmid;
+};
+
+// Mixing and transport constants, in the working precision R of the algebra.
+// Symmetric pair matrices are stored upper-triangular with doubled off-diagonals, so a
+// quadratic form x^T C x is sum_i x_i sum_{j >= i} C'_ij x_j.
+template <typename R, int NS>
+struct MixTab {
+    R sqac[NS];      // sqrt(a_c,i), a_c = Omega_a R^2 Tc^2 / Pc
+    R k1[NS];        // 1 + kappa_i   (alpha_i = (k1 - k2 sqrt(T))^2)
+    R k2[NS];        // kappa_i / sqrt(Tc_i)
+    R K[NS][NS];     // 1 - k_ij (full, symmetric)
+    // Chung (1988) per species
+    R mu0A[NS];      // 40.785e-7 Fc_i sqrt(M_i) / Vc_i^(2/3): dilute mu_i = mu0A_i sqrt(T) / Omega_v
+    R tsc[NS];       // 1.2593 / Tc_i  (T*_i = tsc_i T)
+    R tsp[NS];       // 1.16145 tsc_i^-0.14874
+    // Chung pseudo-mixture pair matrices (upper-triangular, doubled off-diagonal)
+    R S3[NS][NS];    // sigma_ij^3
+    R ES3[NS][NS];   // eps_ij sigma_ij^3
+    R WS3[NS][NS];   // omega_ij sigma_ij^3
+    R ESM[NS][NS];   // eps_ij sigma_ij^2 sqrt(M_ij)
+    R MU4[NS][NS];   // mu_i^2 mu_j^2 / sigma_ij^3
+    R KAP[NS][NS];   // sqrt(kappa_i kappa_j)
+};
+
+}  // namespace props
+
+// ---------------------------------------------------------------- handles
+struct props_mech_s {
+    int ns = 0;
+    int nsp = 0;          // padded species count the kernels run with
+    int device = 0;
+    int maxit = 100;
+    double rtol = 1e-10;
+    void *d_tab = nullptr;  // one allocation: ThermoTab | MixTab<double> | MixTab<float>
+    size_t off_mixd = 0, off_mixf = 0, bytes = 0;
+    props_species_desc sp[PROPS_MAX_SPECIES];
+    double kij[PROPS_MAX_SPECIES * PROPS_MAX_SPECIES];
+};
+
+namespace props {
+// Launch the PR property kernel for a mechanism (defined in pr_kernel.hip).
+int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
+              const props_out *out, int64_t n, uint8_t *status, hipStream_t stream);
+}  // namespace props

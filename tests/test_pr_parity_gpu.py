@@ -1,0 +1,259 @@
+"""GPU parity of the Peng-Robinson property path (props_pr) against the CPU oracle.
+
+Every input is seeded and synthetic (synth), every expected value comes from the oracle.
+FP64 bar: relative 1e-12 scaled by each cell's condition number (cell_kappa).
+"""
+import numpy as np
+import pytest
+
+import synth
+from parity_util import FIELDS, compare, rel_err_stats, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+FP64_RTOL = 1e-12
+
+
+@pytest.fixture(scope="module")
+def props():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2312_04830_amd as P
+    P.lib()
+    return P
+
+
+@pytest.fixture(scope="module")
+def sp8():
+    return synth.load_species(synth.FLAME_SPECIES)
+
+
+@pytest.fixture(scope="module")
+def kij8():
+    return synth.synthetic_kij(8)
+
+
+def _report(name, worst):
+    print(f"\n[{name}] worst err/tol: " + ", ".join(f"{k}={v:.3g}" for k, v in worst.items()), flush=True)
+
+
+# ------------------------------------------------------------------ (P, T, Y), 2 species
+
+@pytest.mark.parametrize("n", [4096, 4095, 1, 257])
+def test_pty_fp64_two_species_uniform_cells(props, orc, n):
+    sp = synth.load_species(["CH4", "O2"])
+    P, T, Y = synth.cells_uniform(4096, seed=0)
+    P, T, Y = P[:n], T[:n], np.ascontiguousarray(Y[:, :n])
+    om = orc.Mech(sp)
+    ref = om.state_PT(P, T, Y)
+    gm = props.Mechanism(sp)
+    g = run_gpu(props, gm, props.PTY, props.FP64, n, {"P": P, "T": T, "Y": Y})
+    worst = compare(g, ref, 0, FP64_RTOL)
+    _report(f"pty fp64 n={n}", worst)
+    assert max(worst.values()) <= 1.0, worst
+    assert np.array_equal(g["status"], ref["status"])
+
+
+def test_pty_fp64_kij_two_species(props, orc):
+    sp = synth.load_species(["CH4", "O2"])
+    kij = [[0.0, 0.05], [0.05, 0.0]]
+    P, T, Y = synth.cells_uniform(4096, seed=10)
+    ref = orc.Mech(sp, kij).state_PT(P, T, Y)
+    g = run_gpu(props, props.Mechanism(sp, kij), props.PTY, props.FP64, 4096, {"P": P, "T": T, "Y": Y})
+    worst = compare(g, ref, 0, FP64_RTOL)
+    _report("pty fp64 kij", worst)
+    assert max(worst.values()) <= 1.0, worst
+
+
+# ------------------------------------------------------------------ (P, T, Y), 8 species flame field
+
+def test_pty_fp64_flame_field(props, orc, sp8, kij8):
+    P, T, Y = synth.flame_field(23, seed=1)      # 12167 cells: ragged tail
+    n = T.size
+    ref = orc.Mech(sp8, kij8).state_PT(P, T, Y)
+    g = run_gpu(props, props.Mechanism(sp8, kij8), props.PTY, props.FP64, n, {"P": P, "T": T, "Y": Y})
+    worst = compare(g, ref, 0, FP64_RTOL)
+    _report("pty fp64 flame", worst)
+    assert max(worst.values()) <= 1.0, worst
+    assert np.array_equal(g["status"], ref["status"])
+
+
+# ------------------------------------------------------------------ (rho, e, Y) Newton
+
+@pytest.mark.parametrize("guess", [True, False])
+def test_rhoey_fp64_flame_field(props, orc, sp8, kij8, guess):
+    P, T, Y = synth.flame_field(23, seed=1)
+    n = T.size
+    om = orc.Mech(sp8, kij8)
+    st = om.state_PT(P, T, Y, transport=False)
+    rho, e = st["rho"], st["e"]
+    ref = om.state_rhoe(rho, e, Y)
+    Tg = synth.temperature_guess(T) if guess else None
+    g = run_gpu(props, props.Mechanism(sp8, kij8), props.RHOEY, props.FP64, n,
+                {"rho": rho, "e": e, "Y": Y, "T_guess": Tg})
+    worst = compare(g, ref, 1, FP64_RTOL)
+    _report(f"rhoey fp64 guess={guess}", worst)
+    assert max(worst.values()) <= 1.0, worst
+    assert np.array_equal(g["status"], ref["status"])
+    assert np.max(np.abs(g["T"] / T - 1)) < 1e-11
+
+
+def test_rhoey_fp64_full_field_sampled(props, orc, sp8, kij8):
+    """The 128^3 flame field in the benchmark's launch configuration; a seeded sample of
+    cells is recomputed by the oracle one by one."""
+    import torch
+    P, T, Y = synth.flame_field(128, seed=1)
+    n = T.size
+    om = orc.Mech(sp8, kij8)
+    st = om.state_PT(P, T, Y, transport=False)
+    Tg = synth.temperature_guess(T)
+    g = run_gpu(props, props.Mechanism(sp8, kij8), props.RHOEY, props.FP64, n,
+                {"rho": st["rho"], "e": st["e"], "Y": Y, "T_guess": Tg})
+    idx = np.random.default_rng(123).choice(n, 3000, replace=False)
+    idx = np.concatenate([idx, [0, n - 1]])
+    ref = om.state_rhoe(st["rho"][idx], st["e"][idx], np.ascontiguousarray(Y[:, idx]))
+    gs = {k: v[idx] for k, v in g.items()}
+    worst = compare(gs, ref, 1, FP64_RTOL)
+    _report("rhoey fp64 128^3 sampled", worst)
+    assert max(worst.values()) <= 1.0, worst
+    # properties that hold at every cell of the field
+    assert np.all(g["status"] == 0)
+    assert np.max(np.abs(g["T"] / T - 1)) < 1e-10
+    assert np.all(np.isfinite(g["mu"])) and np.all(g["mu"] > 0) and np.all(g["lambda"] > 0)
+    del g
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ mixed precision
+
+def test_mixed_precision_error_report(props, orc, sp8, kij8):
+    P, T, Y = synth.flame_field(24, seed=1)
+    n = T.size
+    om = orc.Mech(sp8, kij8)
+    st = om.state_PT(P, T, Y, transport=False)
+    ref = om.state_rhoe(st["rho"], st["e"], Y)
+    gm = props.Mechanism(sp8, kij8)
+    g = run_gpu(props, gm, props.RHOEY, props.MIXED, n,
+                {"rho": st["rho"], "e": st["e"], "Y": Y, "T_guess": synth.temperature_guess(T)})
+    stats = rel_err_stats(g, ref)
+    print("\n[mixed rhoey] max/rms rel err: " + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in stats.items()))
+    for f in ("rho", "h", "cp"):
+        assert stats[f][0] <= 1e-3, (f, stats[f])
+    for f in ("T", "P", "Z", "e", "c", "mu", "lambda"):
+        assert stats[f][0] <= 1e-3, (f, stats[f])
+    gp = run_gpu(props, gm, props.PTY, props.MIXED, n, {"P": P, "T": T, "Y": Y})
+    refp = om.state_PT(P, T, Y)
+    statsp = rel_err_stats(gp, refp)
+    print("[mixed pty] max/rms rel err: " + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in statsp.items()))
+    for f in ("rho", "h", "cp", "c", "mu", "lambda"):
+        assert statsp[f][0] <= 1e-3, (f, statsp[f])
+
+
+# ------------------------------------------------------------------ edge cases
+
+def test_three_root_gibbs_selection(props, orc):
+    """Subcritical O2 and CH4 around their PR saturation pressure: three physical roots,
+    vapour root below P_sat, liquid root above (both sides agree cell by cell)."""
+    for name, T0, ps in (("O2", 120.0, 1.02678e6), ("CH4", 150.0, 1.04691e6)):
+        sp = synth.load_species([name])
+        P = ps * np.array([0.5, 0.9, 0.99, 0.999, 1.001, 1.01, 1.1, 1.5])
+        T = np.full(P.size, T0)
+        Y = np.ones((1, P.size))
+        ref = orc.Mech(sp).state_PT(P, T, Y)
+        g = run_gpu(props, props.Mechanism(sp), props.PTY, props.FP64, P.size, {"P": P, "T": T, "Y": Y})
+        assert np.array_equal(g["status"], ref["status"]), (g["status"], ref["status"])
+        assert np.any(ref["status"] & 8)
+        worst = compare(g, ref, 0, FP64_RTOL)
+        assert max(worst.values()) <= 1.0, worst
+
+
+def test_nonphysical_and_bracket_flags(props, orc, sp8, kij8):
+    n = 8
+    Y = np.zeros((8, n))
+    Y[1] = 1.0
+    rho = np.array([100.0, 100.0, -1.0, 100.0, 100.0, 100.0, 1e6, 100.0])
+    e = np.array([5e7, -5e7, 0.0, 0.0, np.nan, 0.0, 0.0, -1e5])
+    Y[:, 5] = 0.0
+    Y[1, 5] = 0.9          # sum Y != 1
+    Y[:, 7] = 0.0
+    Y[0, 7], Y[1, 7] = -0.5, 1.5   # negative mass fraction
+    ref = orc.Mech(sp8, kij8).state_rhoe(rho, e, Y)
+    g = run_gpu(props, props.Mechanism(sp8, kij8), props.RHOEY, props.FP64, n, {"rho": rho, "e": e, "Y": Y})
+    assert np.array_equal(g["status"], ref["status"]), (g["status"], ref["status"])
+    for f in FIELDS:
+        assert np.array_equal(np.isnan(g[f]), np.isnan(ref[f])), f
+    P = np.array([1e7, -1.0, 1e7, np.nan])
+    T = np.array([300.0, 300.0, 0.0, 300.0])
+    Yp = np.zeros((8, 4))
+    Yp[0] = 1.0
+    refp = orc.Mech(sp8, kij8).state_PT(P, T, Yp)
+    gp = run_gpu(props, props.Mechanism(sp8, kij8), props.PTY, props.FP64, 4, {"P": P, "T": T, "Y": Yp})
+    assert np.array_equal(gp["status"], refp["status"])
+
+
+def test_newton_iteration_limit_flag(props, orc, sp8, kij8):
+    P, T, Y = synth.flame_field(6, seed=3)
+    st = orc.Mech(sp8, kij8).state_PT(P, T, Y, transport=False)
+    m = props.Mechanism(sp8, kij8)
+    m.set_newton(max_iter=1)
+    g = run_gpu(props, m, props.RHOEY, props.FP64, T.size, {"rho": st["rho"], "e": st["e"], "Y": Y})
+    assert np.all(g["status"] & 2)
+    m.set_newton(100, 1e-10)
+    g = run_gpu(props, m, props.RHOEY, props.FP64, T.size, {"rho": st["rho"], "e": st["e"], "Y": Y})
+    assert np.all(g["status"] == 0)
+
+
+@pytest.mark.parametrize("ns", [1, 3, 5, 8])
+def test_species_counts_and_padding(props, orc, sp8, ns):
+    sp = sp8[:ns]
+    rng = np.random.default_rng(ns)
+    n = 1000
+    Y = rng.dirichlet(np.ones(ns), n).T.copy()
+    P = rng.uniform(1e6, 2e7, n)
+    T = rng.uniform(200.0, 2500.0, n)
+    kij = synth.synthetic_kij(ns, seed=ns)
+    ref = orc.Mech(sp, kij).state_PT(P, T, Y)
+    g = run_gpu(props, props.Mechanism(sp, kij), props.PTY, props.FP64, n, {"P": P, "T": T, "Y": Y})
+    worst = compare(g, ref, 0, FP64_RTOL)
+    assert max(worst.values()) <= 1.0, worst
+
+
+def test_null_outputs_and_empty_launch(props, orc, sp8, kij8):
+    import torch
+    P, T, Y = synth.flame_field(5, seed=2)
+    n = T.size
+    ref = orc.Mech(sp8, kij8).state_PT(P, T, Y)
+    m = props.Mechanism(sp8, kij8)
+    g = run_gpu(props, m, props.PTY, props.FP64, n, {"P": P, "T": T, "Y": Y},
+                fields=("rho", "h"), want_status=False)
+    worst = compare(g, ref, 0, FP64_RTOL, fields=("rho", "h"))
+    assert max(worst.values()) <= 1.0
+    props.pr(m, props.PTY, props.FP64, {"P": None, "T": None, "Y": torch.zeros(1, device="cuda:0", dtype=torch.float64)}, {}, 0)
+
+
+def test_invalid_arguments_raise(props, sp8):
+    with pytest.raises(props.PropsError):
+        props.Mechanism(sp8 + sp8[:1])           # 9 species > PROPS_MAX_SPECIES
+    bad = [dict(s) for s in sp8[:2]]
+    bad[1]["Tmid"] = 1200.0
+    with pytest.raises(props.PropsError):
+        props.Mechanism(bad)
+    with pytest.raises(props.PropsError):
+        props.Mechanism(sp8[:2], [[0.0, 0.1], [0.2, 0.0]])   # asymmetric k_ij
+    m = props.Mechanism(sp8[:2])
+    with pytest.raises(props.PropsError):
+        props.pr(m, props.PTY, props.FP64, {}, {}, 10)        # missing inputs
+    with pytest.raises(props.PropsError):
+        props.pr(m, 7, props.FP64, {}, {}, 10)
+
+
+def test_deterministic_bitwise(props, sp8, kij8, orc):
+    P, T, Y = synth.flame_field(16, seed=5)
+    st = orc.Mech(sp8, kij8).state_PT(P, T, Y, transport=False)
+    m = props.Mechanism(sp8, kij8)
+    inp = {"rho": st["rho"], "e": st["e"], "Y": Y, "T_guess": synth.temperature_guess(T)}
+    a = run_gpu(props, m, props.RHOEY, props.FP64, T.size, inp)
+    b = run_gpu(props, m, props.RHOEY, props.FP64, T.size, inp)
+    for f in FIELDS:
+        assert np.array_equal(a[f].view(np.int64), b[f].view(np.int64)), f
