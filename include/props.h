@@ -120,6 +120,86 @@ typedef struct {
 int props_pr(props_mech_t m, int mode, int prec, const props_in *in, const props_out *out,
              int64_t n, uint8_t *status, void *hip_stream);
 
+
+/* ------------------------------------------------------------------ MLP surrogate */
+/* The surrogate of Section 4: a multilayer perceptron with GELU activations mapping a
+ * cell's (P, T, Y_1..Y_8) to (rho, h, cp, c, mu, lambda), here 10 -> 4 x 256 -> 6.
+ * Inputs are min-max scaled to [0, 1] by the training box; outputs are predicted as
+ * min-max scaled targets, with rho, cp, mu and lambda log-transformed first (the
+ * Box-Cox transform with lambda = 0 that Section 4.2 applies to density).  Matrix
+ * products run on the BF16 matrix cores with FP32 accumulation; FP32 master weights. */
+typedef struct props_dnn_s *props_dnn_t;
+
+#define PROPS_DNN_IN 10
+#define PROPS_DNN_OUT 6
+#define PROPS_DNN_HIDDEN 256
+#define PROPS_DNN_LAYERS 5      /* weight layers: 10->256, 3 x 256->256, 256->6 */
+
+/* Create a network on the current device with weights and biases drawn
+ * U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a splitmix64 stream seeded by `seed`, and
+ * identity scalers (inputs and targets taken as already in [0, 1]). */
+int props_dnn_create(uint64_t seed, props_dnn_t *out);
+void props_dnn_destroy(props_dnn_t net);
+
+/* Host copies of layer l (0..4): W row-major [out][in] FP32 (out x in = 256x10,
+ * 256x256, 256x256, 256x256, 6x256) and b[out].  set_layer resets the Adam moments. */
+int props_dnn_get_layer(props_dnn_t net, int l, float *W, float *b);
+int props_dnn_set_layer(props_dnn_t net, int l, const float *W, const float *b);
+
+/* Host scalers: in_lo/in_hi[10] raw input box (also the hull), out_lo/out_hi[6] box of
+ * the transformed targets. */
+int props_dnn_get_scalers(props_dnn_t net, double *in_lo, double *in_hi, double *out_lo, double *out_hi);
+int props_dnn_set_scalers(props_dnn_t net, const double *in_lo, const double *in_hi,
+                          const double *out_lo, const double *out_hi);
+
+/* Checkpoint: FP32 master weights, Adam moments and step, epoch counter, scalers.
+ * A load followed by further training continues bit for bit. */
+int props_dnn_save(props_dnn_t net, const char *path);
+int props_dnn_load(const char *path, props_dnn_t *out);
+
+/* Evaluate the surrogate on n cells given (P, T, Y) (in->P, in->T, in->Y; other members
+ * ignored); writes out->rho, h, cp, c, mu, lambda (NULL members skipped; T, P, Z, e are
+ * not produced).  Cells outside the training box or with non-physical inputs get
+ * PROPS_ST_OUT_OF_HULL; if `fallback` is not NULL they are recomputed by
+ * props_pr(PROPS_PTY, PROPS_MIXED) on the device and also get PROPS_ST_FALLBACK, without a
+ * host synchronisation.  The network must share the mechanism's species order.
+ * Asynchronous on hip_stream; may grow an internal index buffer (hipMalloc) when n
+ * exceeds every previous call. */
+int props_dnn(props_dnn_t net, props_mech_t fallback, const props_in *in, const props_out *out,
+              int64_t n, uint8_t *status, void *hip_stream);
+
+/* ------------------------------------------------------------------ training */
+typedef struct {
+    int epochs;          /* epochs to run in this call */
+    int total_epochs;    /* horizon of the cosine learning-rate schedule (0 = epochs) */
+    int batch;           /* samples per step (multiple of 256; default 65536 if 0) */
+    float lr, lr_min;    /* Adam learning rate, cosine-decayed from lr to lr_min */
+    float beta1, beta2, eps;
+    uint64_t seed;       /* per-epoch sample permutations derive from (seed, epoch) */
+    int fit_scalers;     /* 1: set the input box and target box from this data first */
+} props_train_cfg;
+
+typedef struct {
+    int epochs_run;
+    int64_t steps;       /* optimizer steps taken in this call */
+    double seconds;      /* wall time of the call */
+    double samples_per_s;
+    float *loss;         /* host array of >= epochs floats (may be NULL): mean L1 loss of
+                            each epoch on the scaled targets */
+} props_train_report;
+
+/* Train with the L1 loss of Section 4.3 and Adam.  X: device float [10][n] (P, T, Y_1..8,
+ * feature-major), Y: device float [6][n] raw targets (rho, h, cp, c, mu, lambda).
+ * Blocking: returns when training is done (synchronises hip_stream once per epoch). */
+int train_dnn(props_dnn_t net, const float *X, const float *Y, int64_t n,
+              const props_train_cfg *cfg, props_train_report *rep, void *hip_stream);
+
+/* One forward/backward pass without an update: the mean L1 loss of samples [0, n) and the
+ * gradient of every weight and bias, written to the host array grad in layer order
+ * (W_0, b_0, ..., W_4, b_4; shapes as in props_dnn_get_layer).  n <= 65536. */
+int props_dnn_grad(props_dnn_t net, const float *X, const float *Y, int64_t n, float *grad,
+                   float *loss, void *hip_stream);
+
 /* ------------------------------------------------------------------ errors */
 const char *props_last_error(void);
 const char *props_version(void);

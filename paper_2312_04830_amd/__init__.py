@@ -6,5 +6,5 @@ and streams; tensors are passed to the C ABI as raw device pointers.  The bindin
 loudly when the library is missing.
 """
 from ._lib import (  # noqa: F401
-    FP64, MIXED, PTY, RHOEY, PropsError, Mechanism, lib, library_path, pr, status_bits,
+    FP64, MIXED, PTY, RHOEY, Network, PropsError, Mechanism, lib, library_path, pr, status_bits,
 )

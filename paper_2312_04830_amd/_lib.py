@@ -44,6 +44,20 @@ class PropsOut(ctypes.Structure):
     _fields_ = [(n, _P) for n in OUT_FIELDS] + [("iters", _P)]
 
 
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("total_epochs", ctypes.c_int), ("batch", ctypes.c_int),
+                ("lr", ctypes.c_float), ("lr_min", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("seed", ctypes.c_uint64),
+                ("fit_scalers", ctypes.c_int)]
+
+
+class TrainReport(ctypes.Structure):
+    _fields_ = [("epochs_run", ctypes.c_int), ("steps", ctypes.c_int64), ("seconds", ctypes.c_double),
+                ("samples_per_s", ctypes.c_double), ("loss", ctypes.POINTER(ctypes.c_float))]
+
+
+DNN_LAYERS = ((256, 10), (256, 256), (256, 256), (256, 256), (6, 256))
+
 _lib = None
 
 
@@ -64,6 +78,20 @@ def lib():
         L.props_mech_set_newton.argtypes = [_P, ctypes.c_int, ctypes.c_double]
         L.props_pr.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(PropsIn),
                                ctypes.POINTER(PropsOut), ctypes.c_int64, _P, _P]
+        L.props_dnn_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(_P)]
+        L.props_dnn_destroy.argtypes = [_P]
+        L.props_dnn_destroy.restype = None
+        L.props_dnn_get_layer.argtypes = [_P, ctypes.c_int, _P, _P]
+        L.props_dnn_set_layer.argtypes = [_P, ctypes.c_int, _P, _P]
+        L.props_dnn_get_scalers.argtypes = [_P, _P, _P, _P, _P]
+        L.props_dnn_set_scalers.argtypes = [_P, _P, _P, _P, _P]
+        L.props_dnn_save.argtypes = [_P, ctypes.c_char_p]
+        L.props_dnn_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_P)]
+        L.props_dnn.argtypes = [_P, _P, ctypes.POINTER(PropsIn), ctypes.POINTER(PropsOut),
+                                ctypes.c_int64, _P, _P]
+        L.props_dnn_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_float), _P]
+        L.train_dnn.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(TrainCfg),
+                                ctypes.POINTER(TrainReport), _P]
         _lib = L
     return _lib
 
@@ -135,3 +163,90 @@ def pr(mech, mode, prec, inputs, outputs, n, status=None, stream=None):
     pout = PropsOut(**{k: _ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)})
     check(lib().props_pr(mech.handle, int(mode), int(prec), ctypes.byref(pin), ctypes.byref(pout),
                          int(n), _ptr(status), _stream(stream)))
+
+
+class Network:
+    """props_dnn_* handle: the MLP surrogate (10 -> 4 x 256 GELU -> 6)."""
+
+    def __init__(self, seed=0, handle=None):
+        if handle is None:
+            handle = _P()
+            check(lib().props_dnn_create(int(seed), ctypes.byref(handle)))
+        self.handle = handle
+
+    @classmethod
+    def load(cls, path):
+        h = _P()
+        check(lib().props_dnn_load(str(path).encode(), ctypes.byref(h)))
+        return cls(handle=h)
+
+    def save(self, path):
+        check(lib().props_dnn_save(self.handle, str(path).encode()))
+
+    def get_layer(self, l):
+        import numpy as np
+        o, i = DNN_LAYERS[l]
+        W = np.zeros((o, i), dtype=np.float32)
+        b = np.zeros(o, dtype=np.float32)
+        check(lib().props_dnn_get_layer(self.handle, l, W.ctypes.data, b.ctypes.data))
+        return W, b
+
+    def set_layer(self, l, W, b):
+        import numpy as np
+        W = np.ascontiguousarray(W, dtype=np.float32)
+        b = np.ascontiguousarray(b, dtype=np.float32)
+        assert W.shape == DNN_LAYERS[l] and b.shape == (DNN_LAYERS[l][0],)
+        check(lib().props_dnn_set_layer(self.handle, l, W.ctypes.data, b.ctypes.data))
+
+    def get_scalers(self):
+        import numpy as np
+        a = [np.zeros(k) for k in (10, 10, 6, 6)]
+        check(lib().props_dnn_get_scalers(self.handle, *[x.ctypes.data for x in a]))
+        return a
+
+    def set_scalers(self, in_lo, in_hi, out_lo, out_hi):
+        import numpy as np
+        a = [np.ascontiguousarray(x, dtype=np.float64) for x in (in_lo, in_hi, out_lo, out_hi)]
+        check(lib().props_dnn_set_scalers(self.handle, *[x.ctypes.data for x in a]))
+
+    def __call__(self, inputs, outputs, n, fallback=None, status=None, stream=None):
+        """props_dnn: inputs P, T, Y; outputs rho, h, cp, c, mu, lambda (device tensors)."""
+        pin = PropsIn(**{k: _ptr(inputs.get(k)) for k in ("P", "T", "rho", "e", "Y", "T_guess")})
+        pout = PropsOut(**{k: _ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)})
+        check(lib().props_dnn(self.handle, fallback.handle if fallback is not None else None,
+                              ctypes.byref(pin), ctypes.byref(pout), int(n), _ptr(status), _stream(stream)))
+
+    def grad(self, X, Y, n, stream=None):
+        """props_dnn_grad on device X [10, n], Y [6, n] (float32): (loss, flat gradient)."""
+        import numpy as np
+        total = sum(o * i + o for o, i in DNN_LAYERS)
+        g = np.zeros(total, dtype=np.float32)
+        loss = ctypes.c_float()
+        check(lib().props_dnn_grad(self.handle, _ptr(X), _ptr(Y), int(n), g.ctypes.data,
+                                   ctypes.byref(loss), _stream(stream)))
+        return loss.value, g
+
+    def train(self, X, Y, n, epochs, batch=65536, lr=1e-3, lr_min=1e-5, total_epochs=0,
+              seed=0, fit_scalers=True, stream=None):
+        """train_dnn on device X [10, n], Y [6, n]; returns (report dict, per-epoch losses)."""
+        import numpy as np
+        cfg = TrainCfg(epochs=int(epochs), total_epochs=int(total_epochs), batch=int(batch), lr=lr,
+                       lr_min=lr_min, beta1=0.9, beta2=0.999, eps=1e-8, seed=int(seed),
+                       fit_scalers=int(bool(fit_scalers)))
+        losses = np.zeros(max(1, int(epochs)), dtype=np.float32)
+        rep = TrainReport(loss=losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        check(lib().train_dnn(self.handle, _ptr(X), _ptr(Y), int(n), ctypes.byref(cfg),
+                              ctypes.byref(rep), _stream(stream)))
+        return {"epochs": rep.epochs_run, "steps": rep.steps, "seconds": rep.seconds,
+                "samples_per_s": rep.samples_per_s}, losses[:int(epochs)]
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().props_dnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,1139 @@
+// MLP surrogate of the property path (paper, Section 4): BF16 matrix-core kernels.
+//
+// Network: 10 -> 256 -> 256 -> 256 -> 256 -> 6, GELU after each hidden layer, L1 loss.
+//
+// Inference / training forward: one fused kernel.  Cells are the N dimension of
+// v_mfma_f32_16x16x32_bf16 (16 cells per MFMA column block) and features the M and K
+// dimensions, so the 16x16 FP32 accumulator of an output block holds, in each lane, four
+// consecutive output features of one cell.  Two such blocks (32 features) are exactly the
+// eight bf16 values one lane contributes to the B operand of the next layer, so
+// activations never leave registers: the next layer's weights are stored with the
+// matching permutation of their input index.  Each wave carries 32 cells (two column
+// blocks) through all five layers; the 8 waves of a workgroup share each layer's weights,
+// staged once per 256-cell tile in LDS (rows padded by 16 bytes so the 16 lanes reading
+// 16 rows hit distinct banks).  GELU (tanh form, hardware exp2 and reciprocal) and the
+// bias are applied in FP32 on the accumulators, then packed to bf16 with
+// v_cvt_pk_bf16_f32 (round to nearest even).
+//
+// Backward: tiled bf16 GEMMs (64x64x32 tiles, 4 waves of 2x2 MFMA blocks) for
+// dH = dZ W (with the GELU derivative fused in the epilogue) and dW = dZ^T H (split over
+// the batch with a fixed-order reduction: training is deterministic and resumable bit for
+// bit), column sums for the biases, Adam on FP32 master weights.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "props_internal.hpp"
+
+namespace props {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16_t;  // storage type of a bfloat16
+
+constexpr int NIN = PROPS_DNN_IN, NOUT = PROPS_DNN_OUT, HID = PROPS_DNN_HIDDEN, NL = PROPS_DNN_LAYERS;
+constexpr int IN_PAD = 32;     // input features padded to one K block of the MFMA
+constexpr int OUT_PAD = 16;    // output rows padded to one 16-row block
+constexpr int HROW = HID + 8;  // bf16 per weight row in the fused layout (528 B)
+constexpr int IROW = IN_PAD + 8;
+constexpr int FWD_WAVES = 8;
+constexpr int FWD_THREADS = FWD_WAVES * 64;
+constexpr int CELLS_PER_WAVE = 32;
+constexpr int TILE_CELLS = FWD_WAVES * CELLS_PER_WAVE;   // 256
+constexpr int MAX_BATCH = 65536;
+constexpr int SPLITK = 32;
+
+// padded (out, in) of each weight layer and its offsets in the FP32 master vector
+__host__ __device__ constexpr int lout(int l) { return l == 0 ? HID : (l == NL - 1 ? OUT_PAD : HID); }
+__host__ __device__ constexpr int lin(int l) { return l == 0 ? IN_PAD : HID; }
+__host__ __device__ constexpr int lrow(int l) { return l == 0 ? IROW : HROW; }
+// true (unpadded) shapes
+__host__ __device__ constexpr int tout(int l) { return l == NL - 1 ? NOUT : HID; }
+__host__ __device__ constexpr int tin(int l) { return l == 0 ? NIN : HID; }
+
+// offsets of each layer in the FP32 master vector (W then b), the fused bf16 layout and
+// the natural bf16 layout
+__host__ __device__ constexpr size_t w_off(int l) { return l == 0 ? 0 : w_off(l - 1) + (size_t)lout(l - 1) * lin(l - 1) + lout(l - 1); }
+__host__ __device__ constexpr size_t b_off(int l) { return w_off(l) + (size_t)lout(l) * lin(l); }
+__host__ __device__ constexpr size_t f_off(int l) { return l == 0 ? 0 : f_off(l - 1) + (size_t)lout(l - 1) * lrow(l - 1); }
+__host__ __device__ constexpr size_t n_off(int l) { return l == 0 ? 0 : n_off(l - 1) + (size_t)lout(l - 1) * lin(l - 1); }
+struct Layout {
+    static constexpr size_t total = w_off(NL);
+    static constexpr size_t ftotal = f_off(NL);
+    static constexpr size_t nattotal = n_off(NL);
+    __host__ __device__ static constexpr size_t w(int l) { return w_off(l); }
+    __host__ __device__ static constexpr size_t b(int l) { return b_off(l); }
+    __host__ __device__ static constexpr size_t f(int l) { return f_off(l); }
+    __host__ __device__ static constexpr size_t nat(int l) { return n_off(l); }
+};
+using kLay = Layout;
+
+// Largest fused layer in bytes (the LDS staging buffer).
+constexpr int LDS_BYTES = HID * HROW * 2;   // 135168
+
+// ------------------------------------------------------------------ small device helpers
+// two floats -> two bf16 (round to nearest even; v_cvt_pk_bf16_f32 on gfx950)
+__device__ __forceinline__ unsigned pack_bf16x2(float a, float b)
+{
+    typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    bf2 v = __builtin_convertvector((f2){a, b}, bf2);
+    return __builtin_bit_cast(unsigned, v);
+}
+
+__device__ __forceinline__ bf16_t to_bf16(float a) { return (bf16_t)(pack_bf16x2(a, 0.0f) & 0xffffu); }
+
+__device__ __forceinline__ float bf16_to_f(bf16_t h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
+
+// GELU, tanh form of Hendrycks & Gimpel: x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3)),
+// with exp2 and reciprocal on the transcendental unit.
+constexpr float kG0 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;  // -2 sqrt(2/pi) log2(e)
+constexpr float kG1 = kG0 * 0.044715f;
+__device__ __forceinline__ float gelu_f(float x)
+{
+    float t = x * __builtin_fmaf(kG1, x * x, kG0);
+    float e = __builtin_amdgcn_exp2f(t);
+    return x * __builtin_amdgcn_rcpf(1.0f + e);
+}
+
+// d/dx of gelu_f
+__device__ __forceinline__ float gelu_grad_f(float x)
+{
+    float x2 = x * x;
+    float t = x * __builtin_fmaf(kG1, x2, kG0);
+    float e = __builtin_amdgcn_exp2f(t);
+    float s = __builtin_amdgcn_rcpf(1.0f + e);           // sigmoid(2u)
+    float up = 2.0f * 0.7978845608028654f * (1.0f + 3.0f * 0.044715f * x2);   // 2 u'(x)
+    return s + x * s * (1.0f - s) * up;
+}
+
+__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// sample index of training row i in epoch permutation (a odd/coprime, c offset)
+__device__ __forceinline__ int64_t perm_index(int64_t i, uint64_t a, uint64_t c, int64_t n)
+{
+    return (int64_t)(((unsigned __int128)a * (uint64_t)i + c) % (uint64_t)n);
+}
+
+// ------------------------------------------------------------------ fused forward
+struct FwdArgs {
+    // inference inputs (SoA doubles) ...
+    const double *P, *T, *Y;
+    // ... or training inputs (feature-major float [10][nx]) with the epoch permutation
+    const float *X;
+    int64_t nx;
+    uint64_t pa, pc;
+    int64_t row0;        // first permuted row of this batch
+    int64_t n;           // cells (rows) this launch covers
+    const bf16_t *Wf;    // fused-layout weights of all layers
+    const float *bias;   // FP32 master vector (biases read from their offsets)
+    const double *in_lo, *in_inv;   // [10] input box
+    const double *out_lo, *out_rng; // [6] target box
+    // inference outputs
+    double *orho, *oh, *ocp, *oc, *omu, *olam;
+    uint8_t *status;
+    int *fb_idx, *fb_count;         // fallback list (cells outside the box / non-physical)
+    // training saves
+    bf16_t *h0;          // [n][32]
+    float *z[4];         // [n][256] pre-activations of the hidden layers
+    bf16_t *h[4];        // [n][256] activations
+    float *y;            // [n][16] output layer
+};
+
+// Stage one fused layer (rows x row-stride bf16, a multiple of 16 bytes) into LDS.
+__device__ __forceinline__ void stage(unsigned char *lds, const bf16_t *src, int bytes)
+{
+    const uint4 *s = reinterpret_cast<const uint4 *>(src);
+    uint4 *d = reinterpret_cast<uint4 *>(lds);
+    for (int i = threadIdx.x; i < bytes / 16; i += FWD_THREADS) d[i] = s[i];
+}
+
+__device__ __forceinline__ bf16x8 lds_frag(const unsigned char *lds, int row, int rowlen, int slot)
+{
+    return *reinterpret_cast<const bf16x8 *>(lds + ((size_t)row * rowlen + slot) * 2);
+}
+
+template <bool TRAIN>
+__global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;         // 0..3: k-slot group (B operand) / row group (C)
+    const int col = lane & 15;       // cell within a 16-cell column block
+    const int64_t ntiles = (a.n + TILE_CELLS - 1) / TILE_CELLS;
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        bf16x8 act[8][2];            // [k-block][column block]
+#pragma unroll
+        for (int kb = 0; kb < 8; kb++) act[kb][0] = act[kb][1] = bf16x8{};
+        int64_t cell[2];
+        bool live[2];
+        uint8_t flag[2] = {0, 0};
+        // ---- inputs -> scaled bf16 B operand of layer 0 (slot 8g + j = feature 8g + j)
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+            cell[c] = tile * TILE_CELLS + wave * CELLS_PER_WAVE + c * 16 + col;
+            live[c] = cell[c] < a.n;
+            float xs[8];
+#pragma unroll
+            for (int j = 0; j < 8; j++) xs[j] = 0.0f;
+            if (live[c] && g < 2) {
+                double raw[NIN];
+                if (TRAIN) {
+                    const int64_t sidx = perm_index(a.row0 + cell[c], a.pa, a.pc, a.nx);
+#pragma unroll
+                    for (int f = 0; f < NIN; f++) raw[f] = (double)a.X[(int64_t)f * a.nx + sidx];
+                } else {
+                    raw[0] = a.P[cell[c]];
+                    raw[1] = a.T[cell[c]];
+#pragma unroll
+                    for (int f = 0; f < NIN - 2; f++) raw[2 + f] = a.Y[(int64_t)f * a.n + cell[c]];
+                }
+                // lane group g = 0 carries features 0..7, g = 1 features 8, 9 (then zeros)
+                if (g == 0) {
+#pragma unroll
+                    for (int j = 0; j < 8; j++) xs[j] = (float)((raw[j] - a.in_lo[j]) * a.in_inv[j]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NIN - 8; j++) xs[j] = (float)((raw[8 + j] - a.in_lo[8 + j]) * a.in_inv[8 + j]);
+                }
+                if (!TRAIN && g == 0) {
+                    // training box (the hull) and physical sanity of the whole cell
+                    bool out = false, bad = !(raw[0] > 0.0) || !(raw[1] > 0.0);
+                    double sy = 0.0;
+#pragma unroll
+                    for (int f = 0; f < NIN; f++) {
+                        const double s = (raw[f] - a.in_lo[f]) * a.in_inv[f];
+                        out |= !(s >= -1e-9 && s <= 1.0 + 1e-9);
+                    }
+#pragma unroll
+                    for (int f = 2; f < NIN; f++) {
+                        bad |= !(raw[f] >= -1e-12);
+                        sy += raw[f];
+                    }
+                    bad |= !(fabs(sy - 1.0) <= 1e-6);
+                    flag[c] = (out || bad) ? 1 : 0;
+                }
+            }
+            unsigned p[4];
+#pragma unroll
+            for (int j = 0; j < 4; j++) p[j] = pack_bf16x2(xs[2 * j], xs[2 * j + 1]);
+            act[0][c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<uint4 *>(p));
+            if (TRAIN && live[c]) *reinterpret_cast<uint4 *>(a.h0 + cell[c] * IN_PAD + 8 * g) = *reinterpret_cast<uint4 *>(p);
+        }
+
+        // ---- layers 0..3 (GELU) and 4 (linear output)
+#pragma unroll 1
+        for (int l = 0; l < NL; l++) {
+            __syncthreads();   // previous layer done with the LDS buffer
+            const int rows = lout(l), rowlen = lrow(l);
+            stage(lds, a.Wf + kLay::f(l), rows * rowlen * 2);
+            __syncthreads();
+            const float *bias = a.bias + kLay::b(l);
+            const int nkb = (l == 0) ? 1 : 8;
+            if (l < NL - 1) {
+                bf16x8 nxt[8][2];
+#pragma unroll
+                for (int obp = 0; obp < 8; obp++) {
+                    f32x4 acc[2][2];
+#pragma unroll
+                    for (int h = 0; h < 2; h++) {
+                        const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + (2 * obp + h) * 16 + 4 * g);
+                        acc[h][0] = bv;
+                        acc[h][1] = bv;
+                    }
+#pragma unroll
+                    for (int kb = 0; kb < 8; kb++) {
+                        if (kb < nkb) {
+                            const bf16x8 a0 = lds_frag(lds, (2 * obp) * 16 + col, rowlen, kb * 32 + 8 * g);
+                            const bf16x8 a1 = lds_frag(lds, (2 * obp + 1) * 16 + col, rowlen, kb * 32 + 8 * g);
+#pragma unroll
+                            for (int c = 0; c < 2; c++) {
+                                acc[0][c] = mfma16(a0, act[kb][c], acc[0][c]);
+                                acc[1][c] = mfma16(a1, act[kb][c], acc[1][c]);
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int c = 0; c < 2; c++) {
+                        unsigned p[4];
+#pragma unroll
+                        for (int h = 0; h < 2; h++) {
+                            const f32x4 z = acc[h][c];
+                            const float g0 = gelu_f(z[0]), g1 = gelu_f(z[1]), g2 = gelu_f(z[2]), g3 = gelu_f(z[3]);
+                            p[2 * h] = pack_bf16x2(g0, g1);
+                            p[2 * h + 1] = pack_bf16x2(g2, g3);
+                            if (TRAIN && live[c]) {
+                                const int64_t off = cell[c] * HID + (2 * obp + h) * 16 + 4 * g;
+                                *reinterpret_cast<f32x4 *>(a.z[l] + off) = z;
+                                *reinterpret_cast<uint2 *>(a.h[l] + off) = make_uint2(p[2 * h], p[2 * h + 1]);
+                            }
+                        }
+                        nxt[obp][c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<uint4 *>(p));
+                    }
+                }
+#pragma unroll
+                for (int kb = 0; kb < 8; kb++) {
+                    act[kb][0] = nxt[kb][0];
+                    act[kb][1] = nxt[kb][1];
+                }
+            } else {
+                f32x4 acc[2];
+                const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + 4 * g);
+                acc[0] = bv;
+                acc[1] = bv;
+#pragma unroll
+                for (int kb = 0; kb < 8; kb++) {
+                    const bf16x8 a0 = lds_frag(lds, col, rowlen, kb * 32 + 8 * g);
+                    acc[0] = mfma16(a0, act[kb][0], acc[0]);
+                    acc[1] = mfma16(a0, act[kb][1], acc[1]);
+                }
+#pragma unroll
+                for (int c = 0; c < 2; c++) {
+                    if (!live[c]) continue;
+                    if (TRAIN) {
+                        *reinterpret_cast<f32x4 *>(a.y + cell[c] * OUT_PAD + 4 * g) = acc[c];
+                    } else if (g == 0) {
+                        // outputs 4g + j: lanes g = 0 hold rho, h, cp, c; g = 1 hold mu, lambda
+                        const f32x4 y = acc[c];
+                        if (a.orho) a.orho[cell[c]] = exp(a.out_lo[0] + (double)y[0] * a.out_rng[0]);
+                        if (a.oh) a.oh[cell[c]] = a.out_lo[1] + (double)y[1] * a.out_rng[1];
+                        if (a.ocp) a.ocp[cell[c]] = exp(a.out_lo[2] + (double)y[2] * a.out_rng[2]);
+                        if (a.oc) a.oc[cell[c]] = a.out_lo[3] + (double)y[3] * a.out_rng[3];
+                    } else if (g == 1) {
+                        const f32x4 y = acc[c];
+                        if (a.omu) a.omu[cell[c]] = exp(a.out_lo[4] + (double)y[0] * a.out_rng[4]);
+                        if (a.olam) a.olam[cell[c]] = exp(a.out_lo[5] + (double)y[1] * a.out_rng[5]);
+                    }
+                }
+            }
+        }
+        if (!TRAIN) {
+            // status and fallback list (lanes g == 0 own their cell)
+#pragma unroll
+            for (int c = 0; c < 2; c++) {
+                const bool mine = live[c] && g == 0;
+                const bool f = mine && flag[c];
+                if (mine && a.status) a.status[cell[c]] = f ? PROPS_ST_OUT_OF_HULL : 0;
+                if (a.fb_idx) {
+                    const unsigned long long bal = __ballot(f);
+                    const int cnt = __popcll(bal);
+                    int base = 0;
+                    if (cnt) {
+                        const int first = __builtin_ctzll(bal);
+                        if (lane == first) base = atomicAdd(a.fb_count, cnt);
+                        base = __shfl(base, first);
+                        if (f) a.fb_idx[base + __popcll(bal & ((1ull << lane) - 1))] = (int)cell[c];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ generic bf16 GEMM
+// C[m][n] = sum_k A(m, k) B(k, n); A(m,k) = A[m*lda + k] (TA = false) or A[k*lda + m];
+// B(k,n) = B[k*ldb + n] (TB = false) or B[n*ldb + k].  All of M, N, K, lda, ldb multiples
+// of 8.  blockIdx.z splits K into chunks of kchunk.
+enum { EPI_F32 = 0, EPI_GELU_BWD = 1 };
+struct GemmArgs {
+    int M, N, K, kchunk;
+    const bf16_t *A;
+    int lda;
+    const bf16_t *B;
+    int ldb;
+    float *C;            // EPI_F32: C + z * strideC
+    int ldc;
+    int64_t strideC;
+    bf16_t *Cb;          // EPI_GELU_BWD: bf16(acc * gelu'(Z))
+    const float *Z;
+    int ldz;
+};
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) bf16_t As[64][40];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[64][40];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const int kbeg = blockIdx.z * g.kchunk;
+    const int kend = min(g.K, kbeg + g.kchunk);
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
+        // ---- A tile (64 m x 32 k) -> As[m][k]
+        if (!TA) {
+            const int m = t >> 2, k8 = (t & 3) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (m0 + m < g.M && k0 + k8 < kend) v = *reinterpret_cast<const uint4 *>(g.A + (int64_t)(m0 + m) * g.lda + k0 + k8);
+            *reinterpret_cast<uint4 *>(&As[m][k8]) = v;
+        } else {
+            const int k = t >> 3, m8 = (t & 7) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (m0 + m8 < g.M && k0 + k < kend) v = *reinterpret_cast<const uint4 *>(g.A + (int64_t)(k0 + k) * g.lda + m0 + m8);
+            const bf16_t *e = reinterpret_cast<const bf16_t *>(&v);
+#pragma unroll
+            for (int j = 0; j < 8; j++) As[m8 + j][k] = e[j];
+        }
+        // ---- B tile (32 k x 64 n) -> Bs[n][k]
+        if (!TB) {
+            const int k = t >> 3, n8 = (t & 7) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (n0 + n8 < g.N && k0 + k < kend) v = *reinterpret_cast<const uint4 *>(g.B + (int64_t)(k0 + k) * g.ldb + n0 + n8);
+            const bf16_t *e = reinterpret_cast<const bf16_t *>(&v);
+#pragma unroll
+            for (int j = 0; j < 8; j++) Bs[n8 + j][k] = e[j];
+        } else {
+            const int n = t >> 2, k8 = (t & 3) * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (n0 + n < g.N && k0 + k8 < kend) v = *reinterpret_cast<const uint4 *>(g.B + (int64_t)(n0 + n) * g.ldb + k0 + k8);
+            *reinterpret_cast<uint4 *>(&Bs[n][k8]) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 2; i++) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[wm * 32 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+            for (int j = 0; j < 2; j++) {
+                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 32 + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+                acc[i][j] = mfma16(av, bv, acc[i][j]);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
+                const int n = n0 + wn * 32 + j * 16 + (lane & 15);
+                if (m < g.M && n < g.N) {
+                    if (EPI == EPI_F32) {
+                        g.C[blockIdx.z * g.strideC + (int64_t)m * g.ldc + n] = acc[i][j][r];
+                    } else {
+                        const float d = acc[i][j][r] * gelu_grad_f(g.Z[(int64_t)m * g.ldz + n]);
+                        g.Cb[(int64_t)m * g.ldc + n] = to_bf16(d);
+                    }
+                }
+            }
+}
+
+// ------------------------------------------------------------------ training helpers
+// L1 loss gradient on the scaled targets: dz[i][j] = sign(y - t) / (n_rows * 6) for j < 6.
+// Per-block partial sums of |y - t| go to part[blockIdx.x] (fixed-order reduction later).
+__global__ __launch_bounds__(256) void l1_grad_kernel(const float *y, const float *Yraw, int64_t nx,
+                                                      uint64_t pa, uint64_t pc, int64_t row0, int n,
+                                                      const double *out_lo, const double *out_inv,
+                                                      bf16_t *dz, float *part)
+{
+    __shared__ float red[256];
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    float s = 0.f;
+    if (i < n) {
+        const int64_t sidx = perm_index(row0 + i, pa, pc, nx);
+        const float scale = 1.0f / ((float)n * NOUT);
+#pragma unroll
+        for (int j = 0; j < OUT_PAD; j++) {
+            float d = 0.f;
+            if (j < NOUT) {
+                double tr = (double)Yraw[(int64_t)j * nx + sidx];
+                if (j == 0 || j == 2 || j == 4 || j == 5) tr = log(tr);
+                const float t = (float)((tr - out_lo[j]) * out_inv[j]);
+                const float diff = y[(int64_t)i * OUT_PAD + j] - t;
+                s += fabsf(diff);
+                d = (diff > 0.f) ? scale : ((diff < 0.f) ? -scale : 0.f);
+            }
+            dz[(int64_t)i * OUT_PAD + j] = to_bf16(d);
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// out[i] = sum_s part[s * stride + i] in order s = 0..S-1 (deterministic split-K reduction),
+// with the result written to dst[i] (gradient of a weight matrix).
+__global__ void reduce_partials_kernel(const float *part, int S, int64_t stride, int64_t count, float *dst)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int k = 0; k < S; k++) s += part[k * stride + i];
+    dst[i] = s;
+}
+
+// column sums of a bf16 [n][ncol] matrix: block p sums rows [p*rows, ...) into part[p][col]
+__global__ void colsum_partial_kernel(const bf16_t *dz, int n, int ncol, int rows, float *part)
+{
+    const int c = threadIdx.x;
+    if (c >= ncol) return;
+    const int r0 = blockIdx.x * rows, r1 = min(n, r0 + rows);
+    float s = 0.f;
+    for (int r = r0; r < r1; r++) s += bf16_to_f(dz[(int64_t)r * ncol + c]);
+    part[blockIdx.x * ncol + c] = s;
+}
+
+__global__ void sum_rows_kernel(const float *part, int P, int ncol, float *dst)
+{
+    const int c = threadIdx.x;
+    if (c >= ncol) return;
+    float s = 0.f;
+    for (int p = 0; p < P; p++) s += part[p * ncol + c];
+    dst[c] = s;
+}
+
+__global__ void adam_kernel(float *w, const float *gr, float *m, float *v, int64_t n, float lr,
+                            float b1, float b2, float eps, float bc1, float bc2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = gr[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// FP32 master -> bf16 natural [out][in] and fused (row-padded, k-permuted) layouts.
+__global__ void convert_weights_kernel(const float *master, bf16_t *nat, bf16_t *fused)
+{
+    const int l = blockIdx.y;
+    const int rows = lout(l), cols = lin(l), rowlen = lrow(l);
+    const int64_t cnt = (int64_t)rows * cols;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e / cols), i = (int)(e % cols);
+        const float wv = master[kLay::w(l) + e];
+        const bf16_t b = to_bf16(wv);
+        nat[kLay::nat(l) + e] = b;
+        int slot;
+        if (l == 0) {
+            slot = i;
+        } else {
+            // input i = 32 kb + r sits in k-slot 8 g + j of block kb, where the lane's
+            // accumulator rows 4g..4g+3 (r < 16) fill j = 0..3 and rows 16 + 4g.. fill j = 4..7
+            const int kb = i >> 5, r = i & 31;
+            slot = (r < 16) ? kb * 32 + 8 * (r >> 2) + (r & 3) : kb * 32 + 8 * ((r - 16) >> 2) + 4 + (r & 3);
+        }
+        fused[kLay::f(l) + (int64_t)o * rowlen + slot] = b;
+    }
+}
+
+__global__ void fill_int_kernel(int *p, int v) { *p = v; }
+
+__global__ void fill_float_kernel(float *p, int64_t n, float v)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// feature-wise min/max of a [nf][n] float array (transform: log for the flagged rows)
+__global__ void minmax_partial_kernel(const float *X, int64_t n, int nf, unsigned logmask, int64_t per, double *part)
+{
+    const int f = blockIdx.y;
+    const int64_t r0 = (int64_t)blockIdx.x * per, r1 = min(n, r0 + per);
+    double lo = INFINITY, hi = -INFINITY;
+    for (int64_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
+        double x = X[(int64_t)f * n + r];
+        if (logmask >> f & 1u) x = log(x);
+        lo = fmin(lo, x);
+        hi = fmax(hi, x);
+    }
+    __shared__ double sl[256], sh[256];
+    sl[threadIdx.x] = lo;
+    sh[threadIdx.x] = hi;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            sl[threadIdx.x] = fmin(sl[threadIdx.x], sl[threadIdx.x + w]);
+            sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[((int64_t)f * gridDim.x + blockIdx.x) * 2] = sl[0];
+        part[((int64_t)f * gridDim.x + blockIdx.x) * 2 + 1] = sh[0];
+    }
+}
+
+// ------------------------------------------------------------------ splitmix64 (Steele, Lea & Flood 2014)
+static uint64_t splitmix64(uint64_t &s)
+{
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static double u01(uint64_t &s) { return (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+}  // namespace props
+
+using namespace props;
+
+// ------------------------------------------------------------------ the handle
+struct props_dnn_s {
+    int device = 0;
+    float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;   // device FP32
+    bf16_t *nat = nullptr, *fused = nullptr;
+    double *scal = nullptr;        // device: in_lo[10], in_inv[10], out_lo[6], out_rng[6], out_inv[6]
+    double in_lo[NIN], in_hi[NIN], out_lo[NOUT], out_hi[NOUT];
+    int64_t step = 0;
+    int epoch = 0;
+    // forward/backward scratch for one batch
+    bf16_t *h0 = nullptr, *hs[4] = {}, *dz = nullptr, *dz2 = nullptr, *dzo = nullptr;
+    float *zs[4] = {}, *y = nullptr, *part = nullptr, *lpart = nullptr, *cpart = nullptr;
+    int *fb_idx = nullptr, *fb_count = nullptr;
+    int64_t fb_cap = 0;
+};
+
+namespace props {
+
+static int upload_scalers(props_dnn_s *d)
+{
+    double h[NIN * 2 + NOUT * 3];
+    for (int f = 0; f < NIN; f++) {
+        h[f] = d->in_lo[f];
+        const double r = d->in_hi[f] - d->in_lo[f];
+        h[NIN + f] = (r > 0) ? 1.0 / r : 0.0;
+    }
+    for (int j = 0; j < NOUT; j++) {
+        const double r = d->out_hi[j] - d->out_lo[j];
+        h[2 * NIN + j] = d->out_lo[j];
+        h[2 * NIN + NOUT + j] = r;
+        h[2 * NIN + 2 * NOUT + j] = (r > 0) ? 1.0 / r : 0.0;
+    }
+    PROPS_HIP_TRY(hipMemcpy(d->scal, h, sizeof(h), hipMemcpyHostToDevice));
+    return PROPS_OK;
+}
+
+static int refresh_weights(props_dnn_s *d, hipStream_t s)
+{
+    hipLaunchKernelGGL(convert_weights_kernel, dim3(64, NL), dim3(256), 0, s, d->master, d->nat, d->fused);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
+}
+
+template <typename T>
+static int dalloc(T **p, size_t count)
+{
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+    if (e != hipSuccess) return fail(PROPS_ENOMEM, "hipMalloc(%zu): %s", sizeof(T) * count, hipGetErrorString(e));
+    return PROPS_OK;
+}
+
+static void free_dnn(props_dnn_s *d)
+{
+    void *ps[] = {d->master, d->grad, d->m, d->v, d->nat, d->fused, d->scal, d->h0, d->dz, d->dz2, d->dzo,
+                  d->y, d->part, d->lpart, d->cpart, d->fb_idx, d->fb_count,
+                  d->hs[0], d->hs[1], d->hs[2], d->hs[3], d->zs[0], d->zs[1], d->zs[2], d->zs[3]};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    delete d;
+}
+
+static int alloc_dnn(props_dnn_s *d)
+{
+    int rc;
+    const size_t P = kLay::total;
+    if ((rc = dalloc(&d->master, P)) || (rc = dalloc(&d->grad, P)) || (rc = dalloc(&d->m, P)) ||
+        (rc = dalloc(&d->v, P)) || (rc = dalloc(&d->nat, kLay::nattotal)) ||
+        (rc = dalloc(&d->fused, kLay::ftotal)) || (rc = dalloc(&d->scal, (size_t)NIN * 2 + NOUT * 3)) ||
+        (rc = dalloc(&d->fb_count, 1)))
+        return rc;
+    PROPS_HIP_TRY(hipMemset(d->grad, 0, P * sizeof(float)));
+    PROPS_HIP_TRY(hipMemset(d->m, 0, P * sizeof(float)));
+    PROPS_HIP_TRY(hipMemset(d->v, 0, P * sizeof(float)));
+    PROPS_HIP_TRY(hipMemset(d->fused, 0, kLay::ftotal * sizeof(bf16_t)));
+    return PROPS_OK;
+}
+
+static int ensure_train_scratch(props_dnn_s *d)
+{
+    if (d->h0) return PROPS_OK;
+    int rc;
+    const size_t B = MAX_BATCH;
+    if ((rc = dalloc(&d->h0, B * IN_PAD)) || (rc = dalloc(&d->dz, B * HID)) || (rc = dalloc(&d->dz2, B * HID)) ||
+        (rc = dalloc(&d->dzo, B * OUT_PAD)) || (rc = dalloc(&d->y, B * OUT_PAD)) ||
+        (rc = dalloc(&d->part, (size_t)SPLITK * HID * HID)) || (rc = dalloc(&d->lpart, (size_t)B / 256 + 64)) ||
+        (rc = dalloc(&d->cpart, (size_t)256 * HID)))
+        return rc;
+    for (int l = 0; l < 4; l++)
+        if ((rc = dalloc(&d->hs[l], B * HID)) || (rc = dalloc(&d->zs[l], B * HID))) return rc;
+    return PROPS_OK;
+}
+
+static int fwd_grid(int64_t n)
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+    }
+    const int64_t tiles = (n + TILE_CELLS - 1) / TILE_CELLS;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
+}
+
+static bool g_lds_set = false;
+static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
+{
+    if (!g_lds_set) {
+        PROPS_HIP_TRY(hipFuncSetAttribute((const void *)mlp_fwd_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES));
+        PROPS_HIP_TRY(hipFuncSetAttribute((const void *)mlp_fwd_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES));
+        g_lds_set = true;
+    }
+    const int grid = fwd_grid(a.n);
+    if (train) hipLaunchKernelGGL(mlp_fwd_kernel<true>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
+    else hipLaunchKernelGGL(mlp_fwd_kernel<false>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
+}
+
+template <bool TA, bool TB, int EPI>
+static int gemm(const GemmArgs &g, int splits, hipStream_t s)
+{
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
+    hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
+}
+
+// One forward + backward pass over rows [row0, row0 + n) of the permuted data; leaves the
+// gradient in d->grad and the loss partials (n/256 blocks) in d->lpart.
+static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, uint64_t pa, uint64_t pc,
+                   int64_t row0, int n, hipStream_t s)
+{
+    int rc;
+    FwdArgs a{};
+    a.X = X;
+    a.nx = nx;
+    a.pa = pa;
+    a.pc = pc;
+    a.row0 = row0;
+    a.n = n;
+    a.Wf = d->fused;
+    a.bias = d->master;
+    a.in_lo = d->scal;
+    a.in_inv = d->scal + NIN;
+    a.h0 = d->h0;
+    for (int l = 0; l < 4; l++) {
+        a.z[l] = d->zs[l];
+        a.h[l] = d->hs[l];
+    }
+    a.y = d->y;
+    if ((rc = launch_fwd(true, a, s))) return rc;
+    const int nb = (n + 255) / 256;
+    hipLaunchKernelGGL(l1_grad_kernel, dim3(nb), dim3(256), 0, s, d->y, Y, nx, pa, pc, row0, n,
+                       d->scal + 2 * NIN, d->scal + 2 * NIN + 2 * NOUT, d->dzo, d->lpart);
+    PROPS_HIP_TRY(hipGetLastError());
+    // layer by layer, output to input
+    const bf16_t *dzl = d->dzo;
+    for (int l = NL - 1; l >= 0; l--) {
+        const int O = lout(l), I = lin(l);
+        const bf16_t *hprev = (l == 0) ? d->h0 : d->hs[l - 1];
+        // dW = dz^T h  (M = O, N = I, K = n), split over the batch
+        const int kchunk = ((n + SPLITK - 1) / SPLITK + 31) / 32 * 32;
+        const int splits = (n + kchunk - 1) / kchunk;
+        GemmArgs gw{};
+        gw.M = O, gw.N = I, gw.K = n, gw.kchunk = kchunk;
+        gw.A = dzl, gw.lda = O, gw.B = hprev, gw.ldb = I;
+        gw.C = d->part, gw.ldc = I, gw.strideC = (int64_t)O * I;
+        if ((rc = gemm<true, false, EPI_F32>(gw, splits, s))) return rc;
+        const int64_t cnt = (int64_t)O * I;
+        hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                           d->part, splits, (int64_t)O * I, cnt, d->grad + kLay::w(l));
+        // db = column sums of dz
+        const int rows = 256, P = (n + rows - 1) / rows;
+        hipLaunchKernelGGL(colsum_partial_kernel, dim3(P), dim3(256), 0, s, dzl, n, O, rows, d->cpart);
+        hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(256), 0, s, d->cpart, P, O, d->grad + kLay::b(l));
+        PROPS_HIP_TRY(hipGetLastError());
+        if (l > 0) {
+            // dz_{l-1} = (dz W) * gelu'(z_{l-1})  (M = n, N = I = 256, K = O)
+            bf16_t *out = (dzl == d->dz) ? d->dz2 : d->dz;
+            GemmArgs gh{};
+            gh.M = n, gh.N = I, gh.K = O, gh.kchunk = O;
+            gh.A = dzl, gh.lda = O, gh.B = d->nat + kLay::nat(l), gh.ldb = I;
+            gh.Cb = out, gh.ldc = I, gh.Z = d->zs[l - 1], gh.ldz = HID;
+            if ((rc = gemm<false, false, EPI_GELU_BWD>(gh, 1, s))) return rc;
+            dzl = out;
+        }
+    }
+    return PROPS_OK;
+}
+
+static void epoch_perm(uint64_t seed, int epoch, int64_t n, uint64_t &pa, uint64_t &pc)
+{
+    uint64_t st = seed * 0x9E3779B97F4A7C15ull + (uint64_t)epoch * 0xD1B54A32D192ED03ull + 1;
+    // a: an odd multiplier coprime to n; c: any offset
+    for (;;) {
+        pa = (splitmix64(st) % (uint64_t)n) | 1ull;
+        uint64_t x = pa, y = (uint64_t)n;
+        while (y) {
+            uint64_t r = x % y;
+            x = y;
+            y = r;
+        }
+        if (x == 1) break;
+    }
+    pc = splitmix64(st) % (uint64_t)n;
+    if (n == 1) pa = 1, pc = 0;
+}
+
+}  // namespace props
+
+extern "C" {
+
+int props_dnn_create(uint64_t seed, props_dnn_t *out)
+{
+    if (!out) return fail(PROPS_EINVAL, "props_dnn_create: out is NULL");
+    *out = nullptr;
+    props_dnn_s *d = new (std::nothrow) props_dnn_s();
+    if (!d) return fail(PROPS_ENOMEM, "props_dnn_create: out of host memory");
+    if (hipGetDevice(&d->device) != hipSuccess) {
+        delete d;
+        return fail(PROPS_EHIP, "props_dnn_create: hipGetDevice failed");
+    }
+    int rc = alloc_dnn(d);
+    if (rc) {
+        free_dnn(d);
+        return rc;
+    }
+    std::vector<float> h(kLay::total, 0.0f);
+    uint64_t st = seed;
+    for (int l = 0; l < NL; l++) {
+        const double k = 1.0 / std::sqrt((double)tin(l));
+        for (int o = 0; o < tout(l); o++)
+            for (int i = 0; i < tin(l); i++) h[kLay::w(l) + (size_t)o * lin(l) + i] = (float)((2.0 * u01(st) - 1.0) * k);
+        for (int o = 0; o < tout(l); o++) h[kLay::b(l) + o] = (float)((2.0 * u01(st) - 1.0) * k);
+    }
+    for (int f = 0; f < NIN; f++) d->in_lo[f] = 0.0, d->in_hi[f] = 1.0;
+    for (int j = 0; j < NOUT; j++) d->out_lo[j] = 0.0, d->out_hi[j] = 1.0;
+    if (hipMemcpy(d->master, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        (rc = upload_scalers(d)) || (rc = refresh_weights(d, nullptr)) ||
+        hipDeviceSynchronize() != hipSuccess) {
+        free_dnn(d);
+        return rc ? rc : fail(PROPS_EHIP, "props_dnn_create: initialisation failed");
+    }
+    *out = d;
+    return PROPS_OK;
+}
+
+void props_dnn_destroy(props_dnn_t net)
+{
+    if (net) free_dnn(net);
+}
+
+int props_dnn_get_layer(props_dnn_t d, int l, float *W, float *b)
+{
+    if (!d || l < 0 || l >= NL) return fail(PROPS_EINVAL, "props_dnn_get_layer: bad network or layer");
+    std::vector<float> h((size_t)lout(l) * lin(l) + lout(l));
+    PROPS_HIP_TRY(hipMemcpy(h.data(), d->master + kLay::w(l), h.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (int o = 0; o < tout(l); o++) {
+        if (W)
+            for (int i = 0; i < tin(l); i++) W[(size_t)o * tin(l) + i] = h[(size_t)o * lin(l) + i];
+        if (b) b[o] = h[(size_t)lout(l) * lin(l) + o];
+    }
+    return PROPS_OK;
+}
+
+int props_dnn_set_layer(props_dnn_t d, int l, const float *W, const float *b)
+{
+    if (!d || l < 0 || l >= NL || !W || !b) return fail(PROPS_EINVAL, "props_dnn_set_layer: bad arguments");
+    std::vector<float> h((size_t)lout(l) * lin(l) + lout(l), 0.0f);
+    for (int o = 0; o < tout(l); o++) {
+        for (int i = 0; i < tin(l); i++) h[(size_t)o * lin(l) + i] = W[(size_t)o * tin(l) + i];
+        h[(size_t)lout(l) * lin(l) + o] = b[o];
+    }
+    PROPS_HIP_TRY(hipMemcpy(d->master + kLay::w(l), h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    PROPS_HIP_TRY(hipMemset(d->m + kLay::w(l), 0, h.size() * sizeof(float)));
+    PROPS_HIP_TRY(hipMemset(d->v + kLay::w(l), 0, h.size() * sizeof(float)));
+    int rc = refresh_weights(d, nullptr);
+    if (rc) return rc;
+    PROPS_HIP_TRY(hipDeviceSynchronize());
+    return PROPS_OK;
+}
+
+int props_dnn_get_scalers(props_dnn_t d, double *in_lo, double *in_hi, double *out_lo, double *out_hi)
+{
+    if (!d) return fail(PROPS_EINVAL, "props_dnn_get_scalers: null network");
+    for (int f = 0; f < NIN; f++) {
+        if (in_lo) in_lo[f] = d->in_lo[f];
+        if (in_hi) in_hi[f] = d->in_hi[f];
+    }
+    for (int j = 0; j < NOUT; j++) {
+        if (out_lo) out_lo[j] = d->out_lo[j];
+        if (out_hi) out_hi[j] = d->out_hi[j];
+    }
+    return PROPS_OK;
+}
+
+int props_dnn_set_scalers(props_dnn_t d, const double *in_lo, const double *in_hi, const double *out_lo,
+                          const double *out_hi)
+{
+    if (!d || !in_lo || !in_hi || !out_lo || !out_hi) return fail(PROPS_EINVAL, "props_dnn_set_scalers: null argument");
+    for (int f = 0; f < NIN; f++)
+        if (!(in_hi[f] >= in_lo[f])) return fail(PROPS_EINVAL, "props_dnn_set_scalers: in_hi < in_lo at %d", f);
+    for (int j = 0; j < NOUT; j++)
+        if (!(out_hi[j] >= out_lo[j])) return fail(PROPS_EINVAL, "props_dnn_set_scalers: out_hi < out_lo at %d", j);
+    std::memcpy(d->in_lo, in_lo, sizeof(d->in_lo));
+    std::memcpy(d->in_hi, in_hi, sizeof(d->in_hi));
+    std::memcpy(d->out_lo, out_lo, sizeof(d->out_lo));
+    std::memcpy(d->out_hi, out_hi, sizeof(d->out_hi));
+    return upload_scalers(d);
+}
+
+int props_dnn(props_dnn_t d, props_mech_t fb, const props_in *in, const props_out *out, int64_t n,
+              uint8_t *status, void *hip_stream)
+{
+    if (!d || !in || !out) return fail(PROPS_EINVAL, "props_dnn: null network, input or output");
+    if (n < 0) return fail(PROPS_EINVAL, "props_dnn: n < 0");
+    if (n == 0) return PROPS_OK;
+    if (!in->P || !in->T || !in->Y) return fail(PROPS_EINVAL, "props_dnn: needs P, T and Y");
+    if (n > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_dnn: n too large");
+    if (fb && fb->ns != NIN - 2) return fail(PROPS_EINVAL, "props_dnn: fallback mechanism has %d species, the network %d", fb->ns, NIN - 2);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc;
+    if (fb && n > d->fb_cap) {
+        if (d->fb_idx) {
+            PROPS_HIP_TRY(hipStreamSynchronize(s));
+            (void)hipFree(d->fb_idx);
+            d->fb_idx = nullptr;
+        }
+        if ((rc = dalloc(&d->fb_idx, (size_t)n))) return rc;
+        d->fb_cap = n;
+    }
+    FwdArgs a{};
+    a.P = in->P, a.T = in->T, a.Y = in->Y, a.n = n;
+    a.Wf = d->fused, a.bias = d->master;
+    a.in_lo = d->scal, a.in_inv = d->scal + NIN;
+    a.out_lo = d->scal + 2 * NIN, a.out_rng = d->scal + 2 * NIN + NOUT;
+    a.orho = out->rho, a.oh = out->h, a.ocp = out->cp, a.oc = out->c, a.omu = out->mu, a.olam = out->lambda;
+    a.status = status;
+    if (fb) {
+        a.fb_idx = d->fb_idx;
+        a.fb_count = d->fb_count;
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, d->fb_count, 0);
+    }
+    if ((rc = launch_fwd(false, a, s))) return rc;
+    if (fb) {
+        props_out po{};
+        po.rho = out->rho, po.h = out->h, po.cp = out->cp, po.c = out->c, po.mu = out->mu, po.lambda = out->lambda;
+        props_in pi{};
+        pi.P = in->P, pi.T = in->T, pi.Y = in->Y;
+        rc = launch_pr_indirect(fb, PROPS_PTY, PROPS_MIXED, &pi, &po, n, d->fb_idx, d->fb_count, status,
+                                PROPS_ST_OUT_OF_HULL | PROPS_ST_FALLBACK, s);
+        if (rc) return rc;
+    }
+    return PROPS_OK;
+}
+
+static int fit_scalers_dev(props_dnn_s *d, const float *X, const float *Y, int64_t n, hipStream_t s)
+{
+    const int B = 256;
+    const int64_t per = (n + B - 1) / B;
+    double *part = nullptr;
+    int rc;
+    if ((rc = dalloc(&part, (size_t)B * 2 * (NIN + NOUT)))) return rc;
+    hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, NIN), dim3(256), 0, s, X, n, NIN, 0u, per, part);
+    hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, NOUT), dim3(256), 0, s, Y, n, NOUT, 0x35u, per,
+                       part + (size_t)B * 2 * NIN);
+    std::vector<double> h((size_t)B * 2 * (NIN + NOUT));
+    hipError_t e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(PROPS_EHIP, "fit scalers: %s", hipGetErrorString(e));
+    for (int f = 0; f < NIN + NOUT; f++) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int b = 0; b < B; b++) {
+            lo = std::min(lo, h[((size_t)f * B + b) * 2]);
+            hi = std::max(hi, h[((size_t)f * B + b) * 2 + 1]);
+        }
+        if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(PROPS_EINVAL, "train_dnn: non-finite data in column %d", f);
+        if (f < NIN) d->in_lo[f] = lo, d->in_hi[f] = hi;
+        else d->out_lo[f - NIN] = lo, d->out_hi[f - NIN] = hi;
+    }
+    return upload_scalers(d);
+}
+
+int props_dnn_grad(props_dnn_t d, const float *X, const float *Y, int64_t n, float *grad, float *loss,
+                   void *hip_stream)
+{
+    if (!d || !X || !Y || !grad) return fail(PROPS_EINVAL, "props_dnn_grad: null argument");
+    if (n < 1 || n > MAX_BATCH) return fail(PROPS_EINVAL, "props_dnn_grad: need 1 <= n <= %d", MAX_BATCH);
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc;
+    if ((rc = ensure_train_scratch(d))) return rc;
+    if ((rc = fwd_bwd(d, X, Y, n, 1, 0, 0, (int)n, s))) return rc;
+    std::vector<float> g(kLay::total), lp((n + 255) / 256);
+    PROPS_HIP_TRY(hipMemcpyAsync(g.data(), d->grad, g.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    PROPS_HIP_TRY(hipMemcpyAsync(lp.data(), d->lpart, lp.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    PROPS_HIP_TRY(hipStreamSynchronize(s));
+    size_t o = 0;
+    for (int l = 0; l < NL; l++) {
+        for (int r = 0; r < tout(l); r++)
+            for (int i = 0; i < tin(l); i++) grad[o++] = g[kLay::w(l) + (size_t)r * lin(l) + i];
+        for (int r = 0; r < tout(l); r++) grad[o++] = g[kLay::b(l) + r];
+    }
+    if (loss) {
+        double sl = 0;
+        for (float v : lp) sl += v;
+        *loss = (float)(sl / ((double)n * NOUT));
+    }
+    return PROPS_OK;
+}
+
+int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const props_train_cfg *cfg,
+              props_train_report *rep, void *hip_stream)
+{
+    if (!d || !X || !Y || !cfg) return fail(PROPS_EINVAL, "train_dnn: null argument");
+    if (n < 1) return fail(PROPS_EINVAL, "train_dnn: n < 1");
+    const int batch = cfg->batch ? cfg->batch : MAX_BATCH;
+    if (batch < 256 || batch > MAX_BATCH || batch % 256) return fail(PROPS_EINVAL, "train_dnn: batch must be a multiple of 256 in [256, %d]", MAX_BATCH);
+    if (cfg->epochs < 0 || !(cfg->lr > 0)) return fail(PROPS_EINVAL, "train_dnn: bad epochs or learning rate");
+    hipStream_t s = (hipStream_t)hip_stream;
+    int rc;
+    auto t0 = std::chrono::steady_clock::now();
+    if ((rc = ensure_train_scratch(d))) return rc;
+    if (cfg->fit_scalers && (rc = fit_scalers_dev(d, X, Y, n, s))) return rc;
+    const int total = cfg->total_epochs > 0 ? cfg->total_epochs : std::max(1, d->epoch + cfg->epochs);
+    const float b1 = cfg->beta1 > 0 ? cfg->beta1 : 0.9f, b2 = cfg->beta2 > 0 ? cfg->beta2 : 0.999f;
+    const float eps = cfg->eps > 0 ? cfg->eps : 1e-8f;
+    const int64_t steps_per_epoch = (n + batch - 1) / batch;
+    const int64_t P = (int64_t)kLay::total;
+    std::vector<float> lp;
+    int64_t steps = 0;
+    float *lsum = nullptr;   // per-step loss partial sums of one epoch
+    const int lblocks = batch / 256;
+    if ((rc = dalloc(&lsum, (size_t)steps_per_epoch * lblocks))) return rc;
+    for (int e = 0; e < cfg->epochs; e++) {
+        uint64_t pa, pc;
+        epoch_perm(cfg->seed, d->epoch, n, pa, pc);
+        const double prog = std::min(1.0, (double)d->epoch / total);
+        hipLaunchKernelGGL(fill_float_kernel, dim3((unsigned)((steps_per_epoch * lblocks + 255) / 256)), dim3(256), 0, s,
+                           lsum, steps_per_epoch * lblocks, 0.0f);
+        const float lr = (float)(cfg->lr_min + 0.5 * (cfg->lr - cfg->lr_min) * (1.0 + std::cos(M_PI * prog)));
+        for (int64_t st = 0; st < steps_per_epoch; st++) {
+            const int64_t row0 = st * batch;
+            const int m = (int)std::min<int64_t>(batch, n - row0);
+            if ((rc = fwd_bwd(d, X, Y, n, pa, pc, row0, m, s))) {
+                (void)hipFree(lsum);
+                return rc;
+            }
+            PROPS_HIP_TRY(hipMemcpyAsync(lsum + st * lblocks, d->lpart, sizeof(float) * ((m + 255) / 256),
+                                         hipMemcpyDeviceToDevice, s));
+            d->step++;
+            const float bc1 = 1.0f - std::pow(b1, (float)d->step), bc2 = 1.0f - std::pow(b2, (float)d->step);
+            hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, d->master, d->grad,
+                               d->m, d->v, P, lr, b1, b2, eps, bc1, bc2);
+            if ((rc = refresh_weights(d, s))) {
+                (void)hipFree(lsum);
+                return rc;
+            }
+            steps++;
+        }
+        lp.resize((size_t)steps_per_epoch * lblocks);
+        hipError_t err = hipMemcpyAsync(lp.data(), lsum, lp.size() * sizeof(float), hipMemcpyDeviceToHost, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err != hipSuccess) {
+            (void)hipFree(lsum);
+            return fail(PROPS_EHIP, "train_dnn: %s", hipGetErrorString(err));
+        }
+        double sl = 0;
+        for (float v : lp) sl += v;
+        if (rep && rep->loss) rep->loss[e] = (float)(sl / ((double)n * NOUT));
+        d->epoch++;
+    }
+    (void)hipFree(lsum);
+    PROPS_HIP_TRY(hipStreamSynchronize(s));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) {
+        rep->epochs_run = cfg->epochs;
+        rep->steps = steps;
+        rep->seconds = secs;
+        rep->samples_per_s = secs > 0 ? (double)n * cfg->epochs / secs : 0.0;
+    }
+    return PROPS_OK;
+}
+
+// ---- checkpoint: "PROPSDNN" v1 | step | epoch | scalers | master | m | v
+int props_dnn_save(props_dnn_t d, const char *path)
+{
+    if (!d || !path) return fail(PROPS_EINVAL, "props_dnn_save: null argument");
+    const size_t P = kLay::total;
+    std::vector<float> buf(3 * P);
+    PROPS_HIP_TRY(hipDeviceSynchronize());
+    PROPS_HIP_TRY(hipMemcpy(buf.data(), d->master, P * 4, hipMemcpyDeviceToHost));
+    PROPS_HIP_TRY(hipMemcpy(buf.data() + P, d->m, P * 4, hipMemcpyDeviceToHost));
+    PROPS_HIP_TRY(hipMemcpy(buf.data() + 2 * P, d->v, P * 4, hipMemcpyDeviceToHost));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(PROPS_EINVAL, "props_dnn_save: cannot open %s", path);
+    const char magic[8] = {'P', 'R', 'O', 'P', 'S', 'D', 'N', 'N'};
+    const uint32_t ver = 1;
+    const uint64_t np = P;
+    bool ok = std::fwrite(magic, 8, 1, f) == 1 && std::fwrite(&ver, 4, 1, f) == 1 && std::fwrite(&np, 8, 1, f) == 1 &&
+              std::fwrite(&d->step, 8, 1, f) == 1 && std::fwrite(&d->epoch, 4, 1, f) == 1 &&
+              std::fwrite(d->in_lo, sizeof(d->in_lo), 1, f) == 1 && std::fwrite(d->in_hi, sizeof(d->in_hi), 1, f) == 1 &&
+              std::fwrite(d->out_lo, sizeof(d->out_lo), 1, f) == 1 && std::fwrite(d->out_hi, sizeof(d->out_hi), 1, f) == 1 &&
+              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok = (std::fclose(f) == 0) && ok;
+    return ok ? PROPS_OK : fail(PROPS_EINVAL, "props_dnn_save: write to %s failed", path);
+}
+
+int props_dnn_load(const char *path, props_dnn_t *out)
+{
+    if (!path || !out) return fail(PROPS_EINVAL, "props_dnn_load: null argument");
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(PROPS_EINVAL, "props_dnn_load: cannot open %s", path);
+    char magic[8];
+    uint32_t ver = 0;
+    uint64_t np = 0;
+    props_dnn_t d = nullptr;
+    int rc = props_dnn_create(0, &d);
+    if (rc) {
+        std::fclose(f);
+        return rc;
+    }
+    const size_t P = kLay::total;
+    std::vector<float> buf(3 * P);
+    bool ok = std::fread(magic, 8, 1, f) == 1 && std::memcmp(magic, "PROPSDNN", 8) == 0 && std::fread(&ver, 4, 1, f) == 1 &&
+              ver == 1 && std::fread(&np, 8, 1, f) == 1 && np == P && std::fread(&d->step, 8, 1, f) == 1 &&
+              std::fread(&d->epoch, 4, 1, f) == 1 && std::fread(d->in_lo, sizeof(d->in_lo), 1, f) == 1 &&
+              std::fread(d->in_hi, sizeof(d->in_hi), 1, f) == 1 && std::fread(d->out_lo, sizeof(d->out_lo), 1, f) == 1 &&
+              std::fread(d->out_hi, sizeof(d->out_hi), 1, f) == 1 && std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) {
+        props_dnn_destroy(d);
+        return fail(PROPS_EINVAL, "props_dnn_load: %s is not a valid checkpoint", path);
+    }
+    if (hipMemcpy(d->master, buf.data(), P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d->m, buf.data() + P, P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d->v, buf.data() + 2 * P, P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        (rc = upload_scalers(d)) || (rc = refresh_weights(d, nullptr)) || hipDeviceSynchronize() != hipSuccess) {
+        props_dnn_destroy(d);
+        return rc ? rc : fail(PROPS_EHIP, "props_dnn_load: upload failed");
+    }
+    *out = d;
+    return PROPS_OK;
+}
+
+}  // extern "C"

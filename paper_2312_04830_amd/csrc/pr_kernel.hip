@@ -52,9 +52,12 @@ struct PRArgs {
     const double *in0, *in1, *Y, *Tg;
     double *oT, *oP, *oZ, *orho, *oh, *oe, *ocp, *oc, *omu, *olam;
     uint8_t *status, *iters;
-    int64_t n;
+    const int *idx;    // optional cell list: lane k evaluates cell idx[k] for k < *count
+    const int *count;
+    int64_t n;         // cells in the arrays (stride of Y)
     int ns, maxit;
     double rtol;
+    uint8_t st_or;     // bits OR-ed into every status byte written
 };
 
 // ------------------------------------------------------------------ mixing sums
@@ -294,8 +297,13 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
     const MixTab<R, NS> *__restrict__ tm;
     if constexpr (PREC == PROPS_FP64) tm = tmd; else tm = tmf;
 
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= a.n) return;
+    int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a.idx) {
+        if (k >= *a.count) return;
+        k = a.idx[k];
+    } else if (k >= a.n) {
+        return;
+    }
     const int64_t n = a.n;
 
     // ---- composition and input checks
@@ -324,7 +332,7 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
         bm += X[i] * tt->b[i];
     }
 
-    uint8_t st = 0;
+    uint8_t st = a.st_or;
     const double nan = __builtin_nan("");
     double T = nan, P = nan, v = nan;
     double am = 0, am1 = 0, am2 = 0;
@@ -443,7 +451,7 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
 
     if (bad) {
         if (!(st & PROPS_ST_BRACKET)) st |= PROPS_ST_NONPHYS;
-        st &= (PROPS_ST_NONPHYS | PROPS_ST_BRACKET | PROPS_ST_NEWTON_MAXIT);
+        st &= (PROPS_ST_NONPHYS | PROPS_ST_BRACKET | PROPS_ST_NEWTON_MAXIT | a.st_or);
         if (a.oT) a.oT[k] = nan;
         if (a.oP) a.oP[k] = nan;
         if (a.oZ) a.oZ[k] = nan;
@@ -532,10 +540,14 @@ static int dispatch_ns(const props_mech_s *m, int mode, int prec, bool tr, const
               : launch_one<NS, PROPS_RHOEY, PROPS_MIXED, false>(m, a, s);
 }
 
-int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
-              const props_out *out, int64_t n, uint8_t *status, hipStream_t stream)
+static int launch_pr_args(const props_mech_s *m, int mode, int prec, const props_in *in,
+                          const props_out *out, int64_t n, uint8_t *status, const int *idx,
+                          const int *count, uint8_t st_or, hipStream_t stream)
 {
     PRArgs a{};
+    a.idx = idx;
+    a.count = count;
+    a.st_or = st_or;
     a.in0 = (mode == PROPS_PTY) ? in->P : in->rho;
     a.in1 = (mode == PROPS_PTY) ? in->T : in->e;
     a.Y = in->Y;
@@ -555,6 +567,19 @@ int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
         case 4: return dispatch_ns<4>(m, mode, prec, tr, a, stream);
         default: return dispatch_ns<8>(m, mode, prec, tr, a, stream);
     }
+}
+
+int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
+              const props_out *out, int64_t n, uint8_t *status, hipStream_t stream)
+{
+    return launch_pr_args(m, mode, prec, in, out, n, status, nullptr, nullptr, 0, stream);
+}
+
+int launch_pr_indirect(const props_mech_s *m, int mode, int prec, const props_in *in,
+                       const props_out *out, int64_t n, const int *idx, const int *count,
+                       uint8_t *status, uint8_t st_or, hipStream_t stream)
+{
+    return launch_pr_args(m, mode, prec, in, out, n, status, idx, count, st_or, stream);
 }
 
 }  // namespace props

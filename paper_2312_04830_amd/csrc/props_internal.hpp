@@ -93,4 +93,9 @@ namespace props {
 // Launch the PR property kernel for a mechanism (defined in pr_kernel.hip).
 int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
               const props_out *out, int64_t n, uint8_t *status, hipStream_t stream);
+// The same over a device list of cells: lane k < *count evaluates cell idx[k] of arrays of
+// length n, OR-ing st_or into its status byte (grid sized for n).
+int launch_pr_indirect(const props_mech_s *m, int mode, int prec, const props_in *in,
+                       const props_out *out, int64_t n, const int *idx, const int *count,
+                       uint8_t *status, uint8_t st_or, hipStream_t stream);
 }  // namespace props
