@@ -30,6 +30,11 @@ FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def ops_per_cell(ns, evals, transport=True):
     """Algorithmic FP64 work of one (rho, e, Y) cell in VALU lane-operations: every add,
     multiply or fused multiply-add of the method's formulas counts 1, each special
@@ -86,6 +91,143 @@ def cpu_baseline(res, target_s=15.0):
                       f"by bisection + Chung transport, {dt:.1f} s"}
 
 
+def _rel_stats(pred, ref, key):
+    """max / RMS relative error and R^2 of one output (h relative to its magnitude + 1e5 J/kg)."""
+    import torch
+    scale = ref.abs() + (1e5 if key == "h" else 0.0)
+    rel = (pred - ref).abs() / scale
+    ok = torch.isfinite(rel)
+    rel = rel[ok]
+    r2 = 1.0 - float(((pred - ref)[ok] ** 2).sum() / ((ref[ok] - ref[ok].mean()) ** 2).sum())
+    return {"max": float(rel.max()), "rms": float(rel.pow(2).mean().sqrt()), "r2": r2}
+
+
+def dnn_section(props, synth, mech, sp, epochs, n_train, res, reps=5):
+    """Surrogate: PR-labelled training set, training with the library's own kernels, then
+    inference with PR fallback on a res^3 field; errors against the FP64 PR path."""
+    import torch
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    P, T, Y = synth.training_states(n_train, seed=3)
+    t_gen = time.perf_counter() - t0
+    Pd, Td, Yd = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (P, T, Y))
+    keys = ("rho", "h", "cp", "c", "mu", "lambda")
+    lab = {k: torch.empty(n_train, dtype=torch.float64, device=dev) for k in keys}
+    st = torch.empty(n_train, dtype=torch.uint8, device=dev)
+    props.pr(mech, props.PTY, props.FP64, {"P": Pd, "T": Td, "Y": Yd}, lab, n_train, status=st)
+    torch.cuda.synchronize()
+    X = torch.cat([Pd[None], Td[None], Yd]).float().contiguous()
+    L = torch.stack([lab[k] for k in keys]).float().contiguous()
+    bad_labels = int((st != 0).sum())
+    del Pd, Td, Yd, lab
+    net = props.Network(seed=2024)
+    log(f"training {epochs} epochs on {n_train} samples")
+    rep, losses = net.train(X, L, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=5)
+    log(f"trained in {rep['seconds']:.1f} s, loss {losses[0]:.4f} -> {losses[-1]:.5f}")
+    del X, L
+    # inference field
+    Pf, Tf, Yf = synth.flame_field(res, seed=4)
+    n = Tf.size
+    ins = {"P": torch.from_numpy(Pf).to(dev), "T": torch.from_numpy(Tf).to(dev),
+           "Y": torch.from_numpy(np.ascontiguousarray(Yf)).to(dev)}
+    del Pf, Tf, Yf
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys}
+    sd = torch.empty(n, dtype=torch.uint8, device=dev)
+    ref = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys}
+    mx = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys}
+
+    def timeit(fn, k=reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    ms_dnn = timeit(lambda: net(ins, out, n, fallback=mech, status=sd))
+    ms_dnn_nofb = timeit(lambda: net(ins, mx, n))
+    ms_fp64 = timeit(lambda: props.pr(mech, props.PTY, props.FP64, ins, ref, n))
+    ms_mixed = timeit(lambda: props.pr(mech, props.PTY, props.MIXED, ins, mx, n))
+    fallback = int(((sd & 128) != 0).sum())
+    err = {k: _rel_stats(out[k], ref[k], k) for k in keys}
+    err_mixed = {k: _rel_stats(mx[k], ref[k], k) for k in keys}
+    return net, {
+        "workload": f"{res}^3 flame field ({n} cells), (P,T,Y) -> rho,h,cp,c,mu,lambda",
+        "value": n / (ms_dnn * 1e-3), "unit": "cells/s", "ms": ms_dnn,
+        "no_fallback_cells_per_s": n / (ms_dnn_nofb * 1e-3),
+        "mfma_tflops_no_fallback": 401408.0 * n / (ms_dnn_nofb * 1e-3) / 1e12,
+        "fallback_cells": fallback, "fallback_frac": fallback / n,
+        "pr_fp64_cells_per_s": n / (ms_fp64 * 1e-3), "pr_mixed_cells_per_s": n / (ms_mixed * 1e-3),
+        "speedup_vs_pr_fp64": ms_fp64 / ms_dnn, "speedup_vs_pr_mixed": ms_mixed / ms_dnn,
+        "rel_err_vs_fp64": err, "mixed_rel_err_vs_fp64": err_mixed,
+        "train": {"samples": n_train, "epochs": epochs, "seconds": rep["seconds"],
+                  "samples_per_s": rep["samples_per_s"], "loss_first": float(losses[0]),
+                  "loss_last": float(losses[-1]), "label_flags": bad_labels, "state_gen_s": t_gen},
+    }
+
+
+def serving_section(props, synth, mech, net, n_sub=64, reqs_per_sub=6, load=0.8):
+    """Concurrent subdomains with log-uniform sizes submit requests with exponential think
+    times (closed loop per subdomain); half of them route to the surrogate."""
+    import threading
+    import torch
+    reqs, sizes = synth.serving_trace(n_sub=n_sub, reqs_per_sub=1, seed=5)
+    nmax = int(sizes.max())
+    res = int(np.ceil(nmax ** (1 / 3)))
+    Pf, Tf, Yf = synth.flame_field(res, seed=6)
+    pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()  # noqa: E731
+    hP, hT, hY = pin(Pf), pin(Tf), pin(Yf)
+    server = props.Server(mech, net, mem_budget=1 << 30, chunk_cells=262144, streams=4)
+    keys = ("rho", "h", "cp", "c", "mu", "lambda")
+    outs = [{k: torch.empty(int(n), dtype=torch.float64).pin_memory() for k in keys} for n in sizes]
+    ins = []
+    for n in sizes:
+        n = int(n)
+        Ys = hY[:, :n].contiguous().pin_memory() if n != hY.shape[1] else hY
+        ins.append({"P": hP[:n], "T": hT[:n], "Y": Ys})
+    route = [props.ROUTE_PR_MIXED if k % 2 == 0 else props.ROUTE_DNN for k in range(n_sub)]
+    # capacity: every subdomain submits once, all at the same time
+    t0 = time.perf_counter()
+    tk = [server.submit(props.PTY, route[k], int(sizes[k]), ins[k], outs[k]) for k in range(n_sub)]
+    for t in tk:
+        server.wait(t)
+    cap = float(sizes.sum()) / (time.perf_counter() - t0)
+    mean_gap = n_sub * float(sizes.mean()) / (load * cap)
+    server.close()
+    server = props.Server(mech, net, mem_budget=1 << 30, chunk_cells=262144, streams=4)
+    lat = []
+    lock = threading.Lock()
+
+    def client(k):
+        rng = np.random.default_rng(1000 + k)
+        for _ in range(reqs_per_sub):
+            time.sleep(rng.exponential(mean_gap))
+            t = server.submit(props.PTY, route[k], int(sizes[k]), ins[k], outs[k])
+            r = server.wait(t)
+            with lock:
+                lat.append(r["latency_s"])
+
+    th = [threading.Thread(target=client, args=(k,)) for k in range(n_sub)]
+    t0 = time.perf_counter()
+    for x in th:
+        x.start()
+    for x in th:
+        x.join()
+    wall = time.perf_counter() - t0
+    st = server.stats()
+    server.close()
+    return {"subdomains": n_sub, "requests": n_sub * reqs_per_sub, "mean_cells": float(sizes.mean()),
+            "capacity_cells_per_s": cap, "offered_load": load, "mean_think_s": mean_gap,
+            "cells_per_s": st["cells_per_s"], "p50_ms": st["p50_s"] * 1e3, "p99_ms": st["p99_s"] * 1e3,
+            "mean_ms": st["mean_s"] * 1e3, "max_ms": st["max_s"] * 1e3, "wall_s": wall,
+            "slots": st["slots"], "routes": "even subdomains PR mixed, odd DNN with PR fallback",
+            "io": "host (pinned) -> device -> host per request; latency includes PCIe copies"}
+
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,6 +236,11 @@ def main():
     ap.add_argument("--res", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-dnn", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--dnn-epochs", type=int, default=30)
+    ap.add_argument("--dnn-train", type=int, default=8_388_608)
+    ap.add_argument("--dnn-res", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
@@ -153,8 +300,10 @@ def main():
         wall = time.perf_counter() - t0
         return e0_.elapsed_time(e1_) / steps, wall
 
+    log(f"field ready: {n} cells; timing FP64 (rho,e,Y)")
     ms, wall = timed(props.FP64, args.steps, args.warmup)
     value = n / (ms * 1e-3)
+    log(f"FP64: {ms:.4f} ms/step, {value:.3e} cells/s")
 
     # diagnostics outside the timed region: status and Newton evaluations of this field
     it = torch.empty(n, dtype=torch.uint8, device=dev)
@@ -214,6 +363,7 @@ def main():
                 scale = ref.abs()
             r = ((o_mx[k] - ref).abs() / scale)
             err[k] = {"max": float(r.max().item()), "rms": float(r.pow(2).mean().sqrt().item())}
+        log(f"mixed: {ms_mx:.4f} ms/step")
         rec["mixed"] = {"value": n / (ms_mx * 1e-3), "unit": "cells/s", "ms_per_step": ms_mx,
                         "speedup_vs_fp64": ms / ms_mx, "rel_err_vs_fp64": err}
         # no temperature guess: Newton starts from the top of the bracket
@@ -224,7 +374,23 @@ def main():
         ins = save
         rec["fp64_no_guess"] = {"value": n / (ms_ng * 1e-3), "ms_per_step": ms_ng}
 
+    net = None
+    if not args.no_extras and not args.no_dnn:
+        del ins, outs, stats
+        torch.cuda.empty_cache()
+        log("surrogate: labels, training, inference")
+        net, rec["dnn"] = dnn_section(props, synth, mech, sp, args.dnn_epochs, args.dnn_train, args.dnn_res)
+    if not args.no_extras and not args.no_serving:
+        if net is None:
+            net = props.Network(seed=77)
+            Pq, Tq, Yq = synth.flame_field(64, seed=8)
+            net.set_scalers([Pq.min(), Tq.min()] + list(Yq.min(1)), [Pq.max(), Tq.max()] + list(Yq.max(1)),
+                            [2.0, -1e7, 7.0, 200.0, -11.5, -3.9], [7.0, 2e6, 9.5, 1500.0, -8.0, -1.0])
+        log("serving trace")
+        rec["serving"] = serving_section(props, synth, mech, net)
+
     if not args.no_cpu_baseline:
+        log("CPU oracle baseline")
         cb = cpu_baseline(args.res)
         rec["cpu_baseline"] = cb
         rec["gpu_over_cpu_oracle"] = value / cb["value"]

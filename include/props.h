@@ -200,6 +200,72 @@ int train_dnn(props_dnn_t net, const float *X, const float *Y, int64_t n,
 int props_dnn_grad(props_dnn_t net, const float *X, const float *Y, int64_t n, float *grad,
                    float *loss, void *hip_stream);
 
+
+/* ------------------------------------------------------------------ serving */
+/* A request loop for concurrent solver subdomains (paper, Section 4.4: property inference
+ * served by a GPU beside a CPU solver).  Requests carry HOST arrays (pinned memory,
+ * e.g. hipHostMalloc, makes the copies asynchronous).  The server owns a device arena of
+ * `mem_budget` bytes cut into slots of `chunk_cells` cells; each request is split into
+ * chunks that are admitted as slots free up, round-robin across the active requests
+ * (a small request never waits for a large one to finish), copied in, evaluated and
+ * copied out on a pool of streams so chunks of different requests overlap on the device.
+ * Mechanism tables and network weights stay resident.  A cell's result does not depend
+ * on which chunk, slot or stream carried it. */
+typedef struct props_server_s *props_server_t;
+
+enum { PROPS_ROUTE_PR_FP64 = 0, PROPS_ROUTE_PR_MIXED = 1, PROPS_ROUTE_DNN = 2 };
+enum { PROPS_EXEC_GPU = 0, PROPS_EXEC_MOCK = 1 };
+
+typedef struct {
+    int64_t mem_budget;       /* device bytes for chunk slots (>= one slot) */
+    int64_t chunk_cells;      /* cells per slot (default 262144 if 0) */
+    int max_inflight;         /* chunk cap in flight (0 = as many as slots) */
+    int streams;              /* HIP streams in the pool (default 4 if 0) */
+    int executor;             /* PROPS_EXEC_GPU, or PROPS_EXEC_MOCK: host threads stand in
+                                 for the device (scheduler tests without a GPU) */
+    double mock_ns_per_cell;  /* mock executor: simulated evaluation time per cell */
+    int mock_species;         /* mock executor without a mechanism: species count (default 8) */
+} props_serve_cfg;
+
+typedef struct {
+    int mode;                 /* PROPS_PTY or PROPS_RHOEY (PROPS_ROUTE_DNN: PTY only) */
+    int route;                /* PROPS_ROUTE_* */
+    int64_t n;
+    props_in in;              /* HOST arrays (Y: [ns][n]) */
+    props_out out;            /* HOST arrays; NULL members are not returned */
+    uint8_t *status;          /* HOST, optional */
+} props_request;
+
+typedef struct {
+    int rc;                   /* 0 or a negative PROPS_E* code */
+    int64_t n;
+    double t_submit, t_done;  /* seconds since the server started */
+    double latency_s;
+} props_result;
+
+typedef struct {
+    int64_t submitted, completed, failed, queued_requests, inflight_chunks;
+    int64_t cells_done, slots, slot_bytes;
+    double elapsed_s, cells_per_s;   /* since the first submission */
+    double p50_s, p99_s, mean_s, max_s;   /* request latency, completed requests */
+} props_serve_stats;
+
+/* mech is required (except by the mock executor); dnn may be NULL (then PROPS_ROUTE_DNN
+ * is refused).  The server does not own mech or dnn, which must outlive it.  The mock
+ * executor evaluates a fixed function of each cell's inputs on host threads, and fails a
+ * chunk whose first input value is NaN (to exercise failure paths). */
+int serve_create(const props_serve_cfg *cfg, props_mech_t mech, props_dnn_t dnn,
+                 props_server_t *out);
+/* Thread-safe and non-blocking.  The request's host arrays must stay valid until
+ * serve_wait reports it done. */
+int serve_submit(props_server_t s, const props_request *req, uint64_t *ticket);
+/* Wait for a ticket (timeout_us < 0: forever).  PROPS_ETIMEDOUT if not done in time;
+ * otherwise the ticket is retired and res (if not NULL) filled. */
+int serve_wait(props_server_t s, uint64_t ticket, int64_t timeout_us, props_result *res);
+int serve_stats(props_server_t s, props_serve_stats *st);
+/* Drains everything in flight, then frees the server. */
+void serve_destroy(props_server_t s);
+
 /* ------------------------------------------------------------------ errors */
 const char *props_last_error(void);
 const char *props_version(void);

@@ -58,6 +58,31 @@ class TrainReport(ctypes.Structure):
 
 DNN_LAYERS = ((256, 10), (256, 256), (256, 256), (256, 256), (6, 256))
 
+ROUTE_PR_FP64, ROUTE_PR_MIXED, ROUTE_DNN = 0, 1, 2
+EXEC_GPU, EXEC_MOCK = 0, 1
+
+
+class ServeCfg(ctypes.Structure):
+    _fields_ = [("mem_budget", ctypes.c_int64), ("chunk_cells", ctypes.c_int64), ("max_inflight", ctypes.c_int),
+                ("streams", ctypes.c_int), ("executor", ctypes.c_int), ("mock_ns_per_cell", ctypes.c_double),
+                ("mock_species", ctypes.c_int)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("route", ctypes.c_int), ("n", ctypes.c_int64),
+                ("inp", PropsIn), ("out", PropsOut), ("status", _P)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("rc", ctypes.c_int), ("n", ctypes.c_int64), ("t_submit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("latency_s", ctypes.c_double)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("submitted", "completed", "failed", "queued_requests",
+                                              "inflight_chunks", "cells_done", "slots", "slot_bytes")] + \
+               [(k, ctypes.c_double) for k in ("elapsed_s", "cells_per_s", "p50_s", "p99_s", "mean_s", "max_s")]
+
 _lib = None
 
 
@@ -92,6 +117,12 @@ def lib():
         L.props_dnn_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_float), _P]
         L.train_dnn.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(TrainCfg),
                                 ctypes.POINTER(TrainReport), _P]
+        L.serve_create.argtypes = [ctypes.POINTER(ServeCfg), _P, _P, ctypes.POINTER(_P)]
+        L.serve_submit.argtypes = [_P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+        L.serve_wait.argtypes = [_P, ctypes.c_uint64, ctypes.c_int64, ctypes.POINTER(Result)]
+        L.serve_stats.argtypes = [_P, ctypes.POINTER(ServeStats)]
+        L.serve_destroy.argtypes = [_P]
+        L.serve_destroy.restype = None
         _lib = L
     return _lib
 
@@ -244,6 +275,70 @@ class Network:
         if getattr(self, "handle", None):
             lib().props_dnn_destroy(self.handle)
             self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host_ptr(a):
+    """Address of a host array (numpy or CPU tensor); None -> NULL."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        if a.is_cuda or not a.is_contiguous():
+            raise ValueError("serving requests take contiguous host arrays")
+        return a.data_ptr()
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("serving requests take contiguous host arrays")
+    return a.ctypes.data
+
+
+class Server:
+    """serve_*: chunked, memory-admitted, multi-stream property server."""
+
+    def __init__(self, mech, dnn=None, mem_budget=1 << 30, chunk_cells=262144, max_inflight=0,
+                 streams=4, executor=EXEC_GPU, mock_ns_per_cell=0.0, mock_species=8):
+        cfg = ServeCfg(mem_budget=int(mem_budget), chunk_cells=int(chunk_cells), max_inflight=int(max_inflight),
+                       streams=int(streams), executor=int(executor), mock_ns_per_cell=float(mock_ns_per_cell),
+                       mock_species=int(mock_species))
+        h = _P()
+        check(lib().serve_create(ctypes.byref(cfg), mech.handle if mech is not None else None,
+                                 dnn.handle if dnn is not None else None, ctypes.byref(h)))
+        self.handle = h
+        self._keep = {}
+
+    def submit(self, mode, route, n, inputs, outputs, status=None):
+        """Non-blocking; host arrays must stay alive until wait() returns."""
+        req = Request(mode=int(mode), route=int(route), n=int(n),
+                      inp=PropsIn(**{k: _host_ptr(inputs.get(k)) for k in ("P", "T", "rho", "e", "Y", "T_guess")}),
+                      out=PropsOut(**{k: _host_ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)}),
+                      status=_host_ptr(status))
+        t = ctypes.c_uint64()
+        check(lib().serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
+        self._keep[t.value] = (inputs, outputs, status)
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        res = Result()
+        rc = lib().serve_wait(self.handle, int(ticket), int(timeout_us), ctypes.byref(res))
+        if rc != -5:   # not a time-out: the ticket is retired
+            self._keep.pop(ticket, None)
+        check(rc)
+        return {"rc": res.rc, "n": res.n, "t_submit": res.t_submit, "t_done": res.t_done, "latency_s": res.latency_s}
+
+    def stats(self):
+        st = ServeStats()
+        check(lib().serve_stats(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServeStats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().serve_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
 
     def __del__(self):
         try:

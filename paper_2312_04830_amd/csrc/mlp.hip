@@ -24,6 +24,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -693,14 +694,16 @@ static int fwd_grid(int64_t n)
     return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
 }
 
-static bool g_lds_set = false;
+static std::once_flag g_lds_once;
+static hipError_t g_lds_err = hipSuccess;
 static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
 {
-    if (!g_lds_set) {
-        PROPS_HIP_TRY(hipFuncSetAttribute((const void *)mlp_fwd_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES));
-        PROPS_HIP_TRY(hipFuncSetAttribute((const void *)mlp_fwd_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES));
-        g_lds_set = true;
-    }
+    std::call_once(g_lds_once, [] {
+        g_lds_err = hipFuncSetAttribute((const void *)mlp_fwd_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+        if (g_lds_err == hipSuccess)
+            g_lds_err = hipFuncSetAttribute((const void *)mlp_fwd_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+    });
+    if (g_lds_err != hipSuccess) return fail(PROPS_EHIP, "hipFuncSetAttribute(LDS %d B): %s", LDS_BYTES, hipGetErrorString(g_lds_err));
     const int grid = fwd_grid(a.n);
     if (train) hipLaunchKernelGGL(mlp_fwd_kernel<true>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
     else hipLaunchKernelGGL(mlp_fwd_kernel<false>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
@@ -796,6 +799,39 @@ static void epoch_perm(uint64_t seed, int epoch, int64_t n, uint64_t &pa, uint64
     }
     pc = splitmix64(st) % (uint64_t)n;
     if (n == 1) pa = 1, pc = 0;
+}
+
+int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_out *out, int64_t n,
+             uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s)
+{
+    if (!in->P || !in->T || !in->Y) return fail(PROPS_EINVAL, "props_dnn: needs P, T and Y");
+    if (fb && fb->ns != NIN - 2)
+        return fail(PROPS_EINVAL, "props_dnn: fallback mechanism has %d species, the network %d", fb->ns, NIN - 2);
+    if (fb && (!fb_idx || !fb_count)) return fail(PROPS_EINVAL, "props_dnn: fallback needs index scratch");
+    int rc;
+    FwdArgs a{};
+    a.P = in->P, a.T = in->T, a.Y = in->Y, a.n = n;
+    a.Wf = d->fused, a.bias = d->master;
+    a.in_lo = d->scal, a.in_inv = d->scal + NIN;
+    a.out_lo = d->scal + 2 * NIN, a.out_rng = d->scal + 2 * NIN + NOUT;
+    a.orho = out->rho, a.oh = out->h, a.ocp = out->cp, a.oc = out->c, a.omu = out->mu, a.olam = out->lambda;
+    a.status = status;
+    if (fb) {
+        a.fb_idx = fb_idx;
+        a.fb_count = fb_count;
+        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, fb_count, 0);
+    }
+    if ((rc = launch_fwd(false, a, s))) return rc;
+    if (fb) {
+        props_out po{};
+        po.rho = out->rho, po.h = out->h, po.cp = out->cp, po.c = out->c, po.mu = out->mu, po.lambda = out->lambda;
+        props_in pi{};
+        pi.P = in->P, pi.T = in->T, pi.Y = in->Y;
+        rc = launch_pr_indirect(fb, PROPS_PTY, PROPS_MIXED, &pi, &po, n, fb_idx, fb_count, status,
+                                PROPS_ST_OUT_OF_HULL | PROPS_ST_FALLBACK, s);
+        if (rc) return rc;
+    }
+    return PROPS_OK;
 }
 
 }  // namespace props
@@ -907,9 +943,7 @@ int props_dnn(props_dnn_t d, props_mech_t fb, const props_in *in, const props_ou
     if (!d || !in || !out) return fail(PROPS_EINVAL, "props_dnn: null network, input or output");
     if (n < 0) return fail(PROPS_EINVAL, "props_dnn: n < 0");
     if (n == 0) return PROPS_OK;
-    if (!in->P || !in->T || !in->Y) return fail(PROPS_EINVAL, "props_dnn: needs P, T and Y");
     if (n > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_dnn: n too large");
-    if (fb && fb->ns != NIN - 2) return fail(PROPS_EINVAL, "props_dnn: fallback mechanism has %d species, the network %d", fb->ns, NIN - 2);
     hipStream_t s = (hipStream_t)hip_stream;
     int rc;
     if (fb && n > d->fb_cap) {
@@ -917,33 +951,12 @@ int props_dnn(props_dnn_t d, props_mech_t fb, const props_in *in, const props_ou
             PROPS_HIP_TRY(hipStreamSynchronize(s));
             (void)hipFree(d->fb_idx);
             d->fb_idx = nullptr;
+            d->fb_cap = 0;
         }
         if ((rc = dalloc(&d->fb_idx, (size_t)n))) return rc;
         d->fb_cap = n;
     }
-    FwdArgs a{};
-    a.P = in->P, a.T = in->T, a.Y = in->Y, a.n = n;
-    a.Wf = d->fused, a.bias = d->master;
-    a.in_lo = d->scal, a.in_inv = d->scal + NIN;
-    a.out_lo = d->scal + 2 * NIN, a.out_rng = d->scal + 2 * NIN + NOUT;
-    a.orho = out->rho, a.oh = out->h, a.ocp = out->cp, a.oc = out->c, a.omu = out->mu, a.olam = out->lambda;
-    a.status = status;
-    if (fb) {
-        a.fb_idx = d->fb_idx;
-        a.fb_count = d->fb_count;
-        hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(1), 0, s, d->fb_count, 0);
-    }
-    if ((rc = launch_fwd(false, a, s))) return rc;
-    if (fb) {
-        props_out po{};
-        po.rho = out->rho, po.h = out->h, po.cp = out->cp, po.c = out->c, po.mu = out->mu, po.lambda = out->lambda;
-        props_in pi{};
-        pi.P = in->P, pi.T = in->T, pi.Y = in->Y;
-        rc = launch_pr_indirect(fb, PROPS_PTY, PROPS_MIXED, &pi, &po, n, d->fb_idx, d->fb_count, status,
-                                PROPS_ST_OUT_OF_HULL | PROPS_ST_FALLBACK, s);
-        if (rc) return rc;
-    }
-    return PROPS_OK;
+    return dnn_eval(d, fb, in, out, n, status, d->fb_idx, d->fb_count, s);
 }
 
 static int fit_scalers_dev(props_dnn_s *d, const float *X, const float *Y, int64_t n, hipStream_t s)

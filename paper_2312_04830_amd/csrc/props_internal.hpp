@@ -98,4 +98,8 @@ int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
 int launch_pr_indirect(const props_mech_s *m, int mode, int prec, const props_in *in,
                        const props_out *out, int64_t n, const int *idx, const int *count,
                        uint8_t *status, uint8_t st_or, hipStream_t stream);
+// The surrogate with caller-provided fallback scratch (idx: n ints, count: 1 int), so
+// that concurrent evaluations on different streams never share scratch (mlp.hip).
+int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_out *out, int64_t n,
+             uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s);
 }  // namespace props
