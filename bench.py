@@ -63,6 +63,27 @@ def bytes_per_cell(ns, guess=True, status=True):
     return inputs + outputs
 
 
+def measured_traffic(kernel_sources, summary):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by a plain copy's reading), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(os.path.join(ROOT, summary)):
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for f in kernel_sources:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != kv.get("source_sha256_16"):
+            return None
+        return float(kv["hbm_bytes_per_dispatch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(res, target_s=15.0):
     """The CPU oracle, as it stands, on a strided sample of the same field (all host cores)."""
     import oracle
@@ -241,6 +262,8 @@ def main():
     ap.add_argument("--dnn-epochs", type=int, default=30)
     ap.add_argument("--dnn-train", type=int, default=8_388_608)
     ap.add_argument("--dnn-res", type=int, default=256)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
@@ -339,7 +362,10 @@ def main():
                    "cells": n, "species": ns, "mode": "RHOEY", "precision": "FP64",
                    "kij": "dense synthetic U[0,0.1]"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": measured_traffic(("paper_2312_04830_amd/csrc/pr_kernel.hip",
+                                                  "paper_2312_04830_amd/csrc/props_internal.hpp"),
+                                                 "profiles/pr_kernel_rhoey_fp64_128cube_counters.txt"),
                      "ops_per_cell": ops, "mean_newton_evals": mean_evals,
                      "hbm_GBs": hbm, "hbm_frac": hbm / HBM_PEAK_GBS, "bytes_per_cell": bpc,
                      "kernel": "pr_kernel<8, RHOEY, FP64, transport>"},
@@ -373,6 +399,15 @@ def main():
         ms_ng, _ = timed(props.FP64, max(10, args.steps // 2), 2)
         ins = save
         rec["fp64_no_guess"] = {"value": n / (ms_ng * 1e-3), "ms_per_step": ms_ng}
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        rec["copy_calibration_bytes"] = 2 * src.numel() * 8
+        del src, dst
 
     net = None
     if not args.no_extras and not args.no_dnn:

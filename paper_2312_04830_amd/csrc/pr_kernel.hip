@@ -415,6 +415,9 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
             }
             bool fin = false, conv = false;
             int it = 0;
+            // With single-precision departures the residual carries ~1e-7 relative noise,
+            // so the step criterion is held at 1e-6 there (the double path keeps rtol).
+            const double rtol = (PREC == PROPS_FP64) ? a.rtol : fmax(a.rtol, 1e-6);
             for (; it < a.maxit; it++) {
                 R ram, ram1, ram2;
                 mix_a<PM, NS>(tm, Xr, (R)T, (R)sqrt(T), ram, ram1, ram2);
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
                 const double dT = Tn - T;
                 T = Tn;
                 if (fin) { conv = true; break; }
-                if (fabs(dT) <= a.rtol * T) fin = true;
+                if (fabs(dT) <= rtol * T) fin = true;
             }
             if (a.iters) a.iters[k] = (uint8_t)min(it + (conv ? 1 : 0), 255);
             if (!conv) st |= PROPS_ST_NEWTON_MAXIT;

@@ -135,8 +135,11 @@ def test_mixed_precision_error_report(props, orc, sp8, kij8):
     ref = om.state_rhoe(st["rho"], st["e"], Y)
     gm = props.Mechanism(sp8, kij8)
     g = run_gpu(props, gm, props.RHOEY, props.MIXED, n,
-                {"rho": st["rho"], "e": st["e"], "Y": Y, "T_guess": synth.temperature_guess(T)})
+                {"rho": st["rho"], "e": st["e"], "Y": Y, "T_guess": synth.temperature_guess(T)},
+                fields=FIELDS + ("iters",))
     stats = rel_err_stats(g, ref)
+    assert np.all(g["status"] == 0), np.unique(g["status"])
+    assert g["iters"].max() <= 8, np.bincount(g["iters"].astype(np.int64))
     print("\n[mixed rhoey] max/rms rel err: " + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in stats.items()))
     for f in ("rho", "h", "cp"):
         assert stats[f][0] <= 1e-3, (f, stats[f])
