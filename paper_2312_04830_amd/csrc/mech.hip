@@ -51,6 +51,7 @@ static void fill_mix(MixTab<R, NS> &t, const props_species_desc *sp, int ns, con
         t.sqac[i] = (R)std::sqrt(ac);
         t.k1[i] = (R)(1.0 + kap);
         t.k2[i] = (R)(kap / std::sqrt(s.Tc));
+        t.tstar[i] = (R)((kap > 0.0) ? s.Tc * (1.0 + 1.0 / kap) * (1.0 + 1.0 / kap) : HUGE_VAL);
         // Chung's constants use Vc in cm^3/mol and M in g/mol
         double Vc = s.Vc * 1e6, M = s.W * 1e3;
         double mur = 131.3 * s.dipole / std::sqrt(Vc * s.Tc);
@@ -73,13 +74,18 @@ static void fill_mix(MixTab<R, NS> &t, const props_species_desc *sp, int ns, con
             double wij = 0.5 * (sp[i].omega + sp[j].omega);
             double Mi = sp[i].W * 1e3, Mj = sp[j].W * 1e3;
             double Mij = 2.0 * Mi * Mj / (Mi + Mj);
-            t.S3[i][j] = (R)(f * sij3);
-            t.ES3[i][j] = (R)(f * eij * sij3);
-            t.WS3[i][j] = (R)(f * wij * sij3);
+            (void)sij3;
+            (void)wij;
             t.ESM[i][j] = (R)(f * eij * sij * sij * std::sqrt(Mij));
-            t.MU4[i][j] = (R)(f * mud[i] * mud[i] * mud[j] * mud[j] / sij3);
-            t.KAP[i][j] = (R)(f * std::sqrt(sp[i].kappa * sp[j].kappa));
         }
+    }
+    for (int i = 0; i < ns; i++) {
+        const double p = std::pow(sig[i], 1.5);
+        t.cp_p[i] = (R)p;
+        t.cp_q[i] = (R)(std::sqrt(eps[i]) * p);
+        t.cp_wp[i] = (R)(sp[i].omega * p);
+        t.cp_m[i] = (R)(mud[i] * mud[i] / p);
+        t.cp_k[i] = (R)std::sqrt(sp[i].kappa);
     }
 }
 
@@ -93,11 +99,11 @@ static void fill_thermo(ThermoTab<NS> &t, const props_species_desc *sp, int ns)
         t.RW[i] = kR / s.W;
         t.b[i] = kOmegaB * kR * s.Tc / s.Pc;
         for (int k = 0; k < 5; k++) {
-            t.cp[0][k][i] = s.nasa_lo[k];
-            t.cp[1][k][i] = s.nasa_hi[k];
+            t.cp[0][k][i] = t.RW[i] * s.nasa_lo[k];
+            t.cp[1][k][i] = t.RW[i] * s.nasa_hi[k];
         }
-        t.a6[0][i] = s.nasa_lo[5];
-        t.a6[1][i] = s.nasa_hi[5];
+        t.a6[0][i] = t.RW[i] * s.nasa_lo[5];
+        t.a6[1][i] = t.RW[i] * s.nasa_hi[5];
     }
     t.Tmid = sp[0].Tmid;
 }

@@ -21,19 +21,22 @@
 #include <cmath>
 #include <type_traits>
 
+#include "fastmath.hpp"
 #include "props_internal.hpp"
 
 namespace props {
 
 // ------------------------------------------------------------------ precision policies
+// Double precision with the lean exp/expm1/log and refined reciprocals of fastmath.hpp
+// (a few ulp; the property outputs stay within 1e-15 relative of correctly rounded maths).
 struct P64 {
     using R = double;
     static __device__ __forceinline__ R sqrt_(R x) { return sqrt(x); }
-    static __device__ __forceinline__ R log_(R x) { return log(x); }
-    static __device__ __forceinline__ R exp_(R x) { return exp(x); }
-    static __device__ __forceinline__ R expm1_(R x) { return expm1(x); }
+    static __device__ __forceinline__ R log_(R x) { return fm::log(x); }
+    static __device__ __forceinline__ R exp_(R x) { return fm::exp(x); }
+    static __device__ __forceinline__ R expm1_(R x) { return fm::expm1(x); }
     static __device__ __forceinline__ R cbrt_(R x) { return cbrt(x); }
-    static __device__ __forceinline__ R div(R a, R b) { return a / b; }
+    static __device__ __forceinline__ R div(R a, R b) { return a * fm::rcp(b); }
 };
 
 // Single precision with the hardware transcendental unit (v_exp_f32, v_log_f32, v_rcp_f32).
@@ -61,43 +64,71 @@ struct PRArgs {
 };
 
 // ------------------------------------------------------------------ mixing sums
-// a_m, da_m/dT, d2a_m/dT2 at temperature T (sT = sqrt(T)).  With u_i = X_i g_i and
-// q_i = sign(f_i) X_i sqrt(a_c,i) kappa_i / sqrt(Tc_i), the derivative vector is
-// u'_i = -q_i / (2 sqrt T) and u''_i = -u'_i / (2T), so
-//   a_m = u.K.u,  a_m' = 2 u'.K.u,  a_m'' = -a_m'/(2T) + 2 u'.K.u'.
+// With s = sqrt(T), each g_i = sqrt(a_c,i) |k1_i - k2_i s| is linear in s between the
+// temperatures T*_i = (k1_i/k2_i)^2 where its sign flips.  For a fixed sign pattern
+// sigma, u_i = X_i g_i = alpha_i - beta_i s with alpha_i = X_i sqrt(a_c,i) sigma_i k1_i and
+// beta_i = X_i sqrt(a_c,i) sigma_i k2_i, so the van der Waals sum is exactly
+//   a_m = u.K.u = A0 + A1 s + A2 T,  A0 = alpha.K.alpha, A1 = -2 alpha.K.beta, A2 = beta.K.beta
+// and a_m' = A1/(2s) + A2, a_m'' = -A1/(4 s T).  The two mat-vecs are done once per sign
+// pattern; every Newton evaluation is then O(1).  MixQuad::lo/hi bound the T interval in
+// which the pattern holds.
 template <class PM, int NS>
-__device__ __forceinline__ void mix_a(const MixTab<typename PM::R, NS> *__restrict__ t,
-                                      const typename PM::R (&X)[NS], typename PM::R T,
-                                      typename PM::R sT, typename PM::R &am,
-                                      typename PM::R &am1, typename PM::R &am2)
-{
+struct MixQuad {
     using R = typename PM::R;
-    R u[NS], q[NS];
+    R A0, A1, A2;
+    double lo, hi;   // T interval of the sign pattern
+
+    __device__ __forceinline__ void build(const MixTab<R, NS> *__restrict__ t0, const R (&X)[NS], double T)
+    {
+        // Read the table here, through the scalar cache, each time a pattern is built: left
+        // to itself the compiler hoists the 1 - k_ij matrix out of the Newton loop for the
+        // rare rebuild, and ~130 live uniform values spill into VGPR lanes.
+        const MixTab<R, NS> *tg = t0;
+        asm volatile("" : "+s"(tg));
+        const __attribute__((address_space(4))) MixTab<R, NS> *t =
+            (const __attribute__((address_space(4))) MixTab<R, NS> *)tg;
+        R al[NS], be[NS];
+        lo = 0.0;
+        hi = __builtin_inf();
 #pragma unroll
-    for (int i = 0; i < NS; i++) {
-        R f = t->k1[i] - t->k2[i] * sT;
-        R xs = X[i] * t->sqac[i];
-        u[i] = xs * fabs(f);
-        q[i] = copysign(xs * t->k2[i], f);
-    }
-    R a = 0, aq = 0, qq = 0;
-#pragma unroll
-    for (int i = 0; i < NS; i++) {
-        R w = 0, wq = 0;
-#pragma unroll
-        for (int j = 0; j < NS; j++) {
-            w += t->K[i][j] * u[j];
-            wq += t->K[i][j] * q[j];
+        for (int i = 0; i < NS; i++) {
+            const double ts = (double)t->tstar[i];
+            const bool neg = T > ts;   // f_i = k1 - k2 sqrt(T) < 0 beyond T*_i
+            if (neg) lo = fmax(lo, ts);
+            else hi = fmin(hi, ts);
+            const R xs = X[i] * t->sqac[i];
+            const R sg = neg ? R(-1) : R(1);
+            al[i] = sg * xs * t->k1[i];
+            be[i] = sg * xs * t->k2[i];
         }
-        a += u[i] * w;
-        aq += q[i] * w;
-        qq += q[i] * wq;
+        R a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+        for (int i = 0; i < NS; i++) {
+            R wa = 0, wb = 0;
+#pragma unroll
+            for (int j = 0; j < NS; j++) {
+                wa += t->K[i][j] * al[j];
+                wb += t->K[i][j] * be[j];
+            }
+            a0 += al[i] * wa;
+            a1 += al[i] * wb;
+            a2 += be[i] * wb;
+        }
+        A0 = a0;
+        A1 = R(-2) * a1;
+        A2 = a2;
     }
-    R c1 = PM::div(R(-0.5), sT);
-    am = a;
-    am1 = R(2) * c1 * aq;
-    am2 = PM::div(-am1, R(2) * T) + R(2) * c1 * c1 * qq;
-}
+
+    __device__ __forceinline__ bool valid(double T) const { return T > lo && T <= hi; }
+
+    // a_m and its first two T-derivatives (s = sqrt T, rs = 1/s)
+    __device__ __forceinline__ void eval(R T, R s, R rs, R &am, R &am1, R &am2) const
+    {
+        am = A0 + A1 * s + A2 * T;
+        am1 = R(0.5) * A1 * rs + A2;
+        am2 = R(-0.25) * A1 * rs * rs * rs;
+    }
+};
 
 // ------------------------------------------------------------------ NASA-7 mixture
 struct Nasa {
@@ -159,12 +190,13 @@ __device__ __forceinline__ typename PM::R qform(const typename PM::R (&C)[NS][NS
 
 // mu [Pa s] and lambda [W/(m K)] at T, molar density rhom [mol/m^3], ideal-gas molar Cv.
 template <class PM, int NS>
-__device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restrict__ t,
+__device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restrict__ t0,
                                       const typename PM::R (&X)[NS], typename PM::R T,
                                       typename PM::R rhom, typename PM::R Cv, bool want_mu,
                                       bool want_lam, double *omu, double *olam)
 {
     using R = typename PM::R;
+    const MixTab<R, NS> *__restrict__ t = t0;
     // mole-fraction-averaged low-pressure viscosity; T*^-0.14874 shared by all species
     const R sT = PM::sqrt_(T);
     const R Tp = PM::exp_(R(-0.14874) * PM::log_(T));
@@ -177,20 +209,29 @@ __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restri
         eta0 += PM::div(X[i] * t->mu0A[i], om);
     }
     eta0 *= sT;
-    // pseudo-mixture parameters (Chung's mixing rules)
-    const R s3 = qform<PM, NS>(t->S3, X);
-    const R es3 = qform<PM, NS>(t->ES3, X);
-    const R ws3 = qform<PM, NS>(t->WS3, X);
+    // pseudo-mixture parameters (Chung's mixing rules; see MixTab for the factorisation)
+    R sp = 0, sq = 0, swp = 0, sm = 0, sk = 0;
+#pragma unroll
+    for (int i = 0; i < NS; i++) {
+        sp += X[i] * t->cp_p[i];
+        sq += X[i] * t->cp_q[i];
+        swp += X[i] * t->cp_wp[i];
+        sm += X[i] * t->cp_m[i];
+        sk += X[i] * t->cp_k[i];
+    }
+    const R s3 = sp * sp;
+    const R es3 = sq * sq;
+    const R ws3 = swp * sp;
     const R esm = qform<PM, NS>(t->ESM, X);
-    const R mu4 = qform<PM, NS>(t->MU4, X);
-    const R km = qform<PM, NS>(t->KAP, X);
+    const R mu4 = sm * sm;
+    const R km = sk * sk;
     const R is3 = PM::div(R(1), s3);
-    const R sm = PM::cbrt_(s3);
+    const R sgm = PM::cbrt_(s3);                  // sigma_m
     const R em = es3 * is3;                       // (eps/k)_m
-    const R mq = PM::div(esm, em * sm * sm);
+    const R mq = PM::div(esm, em * sgm * sgm);
     const R Mm = mq * mq;                         // g/mol
     const R wm = ws3 * is3;
-    const R vs = sm * R(1.0 / 0.809);
+    const R vs = sgm * R(1.0 / 0.809);
     const R Vc23 = vs * vs;                       // Vc_m^(2/3), cm^2/mol^(2/3)
     const R Vcm = Vc23 * vs;                      // cm^3/mol
     const R Tcm = R(1.2593) * em;
@@ -321,7 +362,7 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
     const double in0 = a.in0[k], in1 = a.in1[k];
     if (MODE == PROPS_PTY) bad |= !(in0 > 0.0) || !(in1 > 0.0);
     else bad |= !(in0 > 0.0) || !(in1 == in1);
-    const double W = 1.0 / syw;
+    const double W = fm::rcp(syw);
     double X[NS];
     R Xr[NS];
     double bm = 0.0;
@@ -345,12 +386,12 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
             for (int c = 0; c < 5; c++) {
                 double s = 0.0;
 #pragma unroll
-                for (int i = 0; i < NS; i++) s += y[i] * tt->RW[i] * tt->cp[r][c][i];
+                for (int i = 0; i < NS; i++) s += y[i] * tt->cp[r][c][i];
                 ig.c[r][c] = s;
             }
             double s6 = 0.0;
 #pragma unroll
-            for (int i = 0; i < NS; i++) s6 += y[i] * tt->RW[i] * tt->a6[r][i];
+            for (int i = 0; i < NS; i++) s6 += y[i] * tt->a6[r][i];
             ig.a6[r] = s6;
         }
         double rw = 0.0;
@@ -364,12 +405,16 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
         // ---- (P, T, Y): cubic in Z with Gibbs selection
         P = in0;
         T = in1;
+        MixQuad<PM, NS> mq;
+        mq.build(tm, Xr, T);
+        const double sT = sqrt(T);
         R ram, ram1, ram2;
-        mix_a<PM, NS>(tm, Xr, (R)T, (R)sqrt(T), ram, ram1, ram2);
+        mq.eval((R)T, (R)sT, (R)fm::rcp(sT), ram, ram1, ram2);
         am = ram, am1 = ram1, am2 = ram2;
         const double RT = kR * T;
-        const double A = am * P / (RT * RT);
-        const double B = bm * P / RT;
+        const double iRT = fm::rcp(RT);
+        const double A = am * P * iRT * iRT;
+        const double B = bm * P * iRT;
         double z[3];
         const int nr = cubic_roots(A, B, z);
         double zl = nan, zv = nan;
@@ -397,16 +442,16 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
                 Z = (gl < gv) ? zl : zv;
             }
         }
-        v = Z * RT / P;
+        v = Z * RT * fm::rcp(P);
     } else if (MODE == PROPS_RHOEY && !bad) {
         // ---- (rho, e, Y): bracketed Newton on e(T) at fixed v
-        v = W / in0;
+        v = W * fm::rcp(in0);
         if (!(v > bm)) {
             bad = true;
         } else {
             const double estar = in1;
-            const double L = log((v + (1.0 + kSqrt2) * bm) / (v + (1.0 - kSqrt2) * bm));
-            const R Lw = (R)(L / (2.0 * kSqrt2 * bm * W));  // departure (per mole) -> J/kg factor
+            const double L = fm::log((v + (1.0 + kSqrt2) * bm) * fm::rcp(v + (1.0 - kSqrt2) * bm));
+            const R Lw = (R)(L * fm::rcp(2.0 * kSqrt2 * bm) * syw);  // departure (per mole) -> J/kg factor
             double lo = kTlo, hi = kThi;
             T = kThi;
             if (a.Tg) {
@@ -418,9 +463,13 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
             // With single-precision departures the residual carries ~1e-7 relative noise,
             // so the step criterion is held at 1e-6 there (the double path keeps rtol).
             const double rtol = (PREC == PROPS_FP64) ? a.rtol : fmax(a.rtol, 1e-6);
+            MixQuad<PM, NS> mq;
+            mq.build(tm, Xr, T);
             for (; it < a.maxit; it++) {
+                if (!mq.valid(T)) mq.build(tm, Xr, T);
+                const double sT = sqrt(T);
                 R ram, ram1, ram2;
-                mix_a<PM, NS>(tm, Xr, (R)T, (R)sqrt(T), ram, ram1, ram2);
+                mq.eval((R)T, (R)sT, (R)fm::rcp(sT), ram, ram1, ram2);
                 double h_ig, cp_ig;
                 ig.eval(T, h_ig, cp_ig);
                 const double edep = (double)(((R)T * ram1 - ram) * Lw);
@@ -430,7 +479,7 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
                 if (r > 0.0) hi = T;
                 else if (r < 0.0) lo = T;
                 else { conv = true; break; }
-                double Tn = T - r / rp;
+                double Tn = T - r * fm::rcp(rp);
                 if (!(rp > 0.0) || !(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
                 const double dT = Tn - T;
                 T = Tn;
@@ -443,11 +492,13 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
                 st |= PROPS_ST_BRACKET;
                 bad = true;
             } else {
+                if (!mq.valid(T)) mq.build(tm, Xr, T);
+                const double sT = sqrt(T);
                 R ram, ram1, ram2;
-                mix_a<PM, NS>(tm, Xr, (R)T, (R)sqrt(T), ram, ram1, ram2);
+                mq.eval((R)T, (R)sT, (R)fm::rcp(sT), ram, ram1, ram2);
                 am = ram, am1 = ram1, am2 = ram2;
                 const double den = v * v + 2.0 * bm * v - bm * bm;
-                P = kR * T / (v - bm) - am / den;
+                P = kR * T * fm::rcp(v - bm) - am * fm::rcp(den);
             }
         }
     }
@@ -489,16 +540,16 @@ __global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict
         const R cpm = cvm - PM::div(rT * dPdT * dPdT, dPdv);
         const R c2 = -PM::div(rv * rv, (R)W) * PM::div(cpm, cvm) * dPdv;
         const double hdep = (double)edep + P * v - RT;
-        h = h_ig + hdep / W;
-        e = h_ig - ig.rw * T + (double)edep / W;
-        cp = (double)cpm / W;
+        h = h_ig + hdep * syw;
+        e = h_ig - ig.rw * T + (double)edep * syw;
+        cp = (double)cpm * syw;
         c = (c2 > R(0)) ? (double)PM::sqrt_(c2) : nan;
         if (!(cvm > R(0))) st |= PROPS_ST_CV_NONPOS;
     }
     if (a.oT) a.oT[k] = T;
     if (a.oP) a.oP[k] = P;
-    if (a.oZ) a.oZ[k] = P * v / RT;
-    if (a.orho) a.orho[k] = W / v;
+    if (a.oZ) a.oZ[k] = P * v * fm::rcp(RT);
+    if (a.orho) a.orho[k] = W * fm::rcp(v);
     if (a.oh) a.oh[k] = h;
     if (a.oe) a.oe[k] = e;
     if (a.ocp) a.ocp[k] = cp;

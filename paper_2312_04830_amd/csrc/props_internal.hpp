@@ -47,31 +47,36 @@ struct ThermoTab {
     double invW[NS];      // 1/W_i [mol/kg]
     double RW[NS];        // R/W_i [J/(kg K)]
     double b[NS];         // PR co-volume b_i [m^3/mol]
-    double cp[2][5][NS];  // NASA a1..a5 per range (0: T < Tmid, 1: T >= Tmid)
-    double a6[2][NS];     // NASA a6 per range
+    double cp[2][5][NS];  // (R/W_i) a1..a5 per range (0: T < Tmid, 1: T >= Tmid), J/(kg K)
+    double a6[2][NS];     // (R/W_i) a6 per range, J/kg
     double Tmid;
 };
 
 // Mixing and transport constants, in the working precision R of the algebra.
-// Symmetric pair matrices are stored upper-triangular with doubled off-diagonals, so a
-// quadratic form x^T C x is sum_i x_i sum_{j >= i} C'_ij x_j.
+// A symmetric pair matrix stored upper-triangular with doubled off-diagonals gives the
+// quadratic form x^T C x as sum_i x_i sum_{j >= i} C'_ij x_j.
 template <typename R, int NS>
 struct MixTab {
     R sqac[NS];      // sqrt(a_c,i), a_c = Omega_a R^2 Tc^2 / Pc
     R k1[NS];        // 1 + kappa_i   (alpha_i = (k1 - k2 sqrt(T))^2)
     R k2[NS];        // kappa_i / sqrt(Tc_i)
     R K[NS][NS];     // 1 - k_ij (full, symmetric)
+    R tstar[NS];     // T*_i = Tc_i (1 + 1/kappa_i)^2 where 1 + kappa_i (1 - sqrt(T/Tc_i)) = 0 (inf if kappa_i = 0)
     // Chung (1988) per species
     R mu0A[NS];      // 40.785e-7 Fc_i sqrt(M_i) / Vc_i^(2/3): dilute mu_i = mu0A_i sqrt(T) / Omega_v
     R tsc[NS];       // 1.2593 / Tc_i  (T*_i = tsc_i T)
     R tsp[NS];       // 1.16145 tsc_i^-0.14874
-    // Chung pseudo-mixture pair matrices (upper-triangular, doubled off-diagonal)
-    R S3[NS][NS];    // sigma_ij^3
-    R ES3[NS][NS];   // eps_ij sigma_ij^3
-    R WS3[NS][NS];   // omega_ij sigma_ij^3
-    R ESM[NS][NS];   // eps_ij sigma_ij^2 sqrt(M_ij)
-    R MU4[NS][NS];   // mu_i^2 mu_j^2 / sigma_ij^3
-    R KAP[NS][NS];   // sqrt(kappa_i kappa_j)
+    // Chung pseudo-mixture.  With sigma_ij = sqrt(sigma_i sigma_j), eps_ij = sqrt(eps_i eps_j),
+    // kappa_ij = sqrt(kappa_i kappa_j) and omega_ij = (omega_i + omega_j)/2, five of the six
+    // double sums factor into single sums:
+    //   sum X_i X_j sigma_ij^3          = (sum X_i p_i)^2,          p_i = sigma_i^1.5
+    //   sum X_i X_j eps_ij sigma_ij^3   = (sum X_i q_i)^2,          q_i = sqrt(eps_i) p_i
+    //   sum X_i X_j omega_ij sigma_ij^3 = (sum X_i omega_i p_i)(sum X_j p_j)
+    //   sum X_i X_j mu_i^2 mu_j^2 / sigma_ij^3 = (sum X_i mu_i^2 / p_i)^2
+    //   sum X_i X_j kappa_ij            = (sum X_i sqrt(kappa_i))^2
+    // and only the molar-mass rule (harmonic mean M_ij) stays a quadratic form.
+    R cp_p[NS], cp_q[NS], cp_wp[NS], cp_m[NS], cp_k[NS];
+    R ESM[NS][NS];   // eps_ij sigma_ij^2 sqrt(M_ij), upper-triangular, doubled off-diagonal
 };
 
 }  // namespace props

@@ -523,3 +523,18 @@ def test_energy_equation_of_state(orc):
     rhs = T * (Pp - Pm) / (2 * dT) - P0
     scale = np.abs(T * (Pp - Pm) / (2 * dT)) + np.abs(P0)
     assert np.max(np.abs(dedv - rhs) / scale) < 1e-5
+
+
+def test_chung_viscosity_has_a_pole_at_negative_pseudo_acentric_factor(orc):
+    """A property of the method: with H2 (omega = -0.216) the pseudo-mixture acentric factor
+    of H2/CH4 sweeps through -0.0674, where Chung's E1 E4 + E2 + E3 vanishes and the dense
+    viscosity has a pole (changes sign); flame-like H2 fractions stay far from it."""
+    sp = synth.load_species(["CH4", "H2"])
+    xh2 = np.linspace(0.02, 0.98, 400)
+    W = np.array([s["W"] for s in sp])
+    Y = np.stack([(1 - xh2) * W[0], xh2 * W[1]])
+    Y /= Y.sum(0, keepdims=True)
+    r = orc.Mech(sp).state_PT(np.full(400, 10e6), np.full(400, 600.0), Y)
+    assert np.any(r["mu"] < 0) and np.any(r["mu"] > 0)
+    lean = xh2 < 0.05
+    assert np.all(r["mu"][lean] > 0)
