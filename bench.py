@@ -22,9 +22,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# FP64 VALU cost of each special function in the gfx950 build of this library
-# (instructions of the device-library routine).
-SP_COST = {"div": 10, "sqrt": 20, "cbrt": 30, "exp": 40, "expm1": 51, "log": 96}
+# FP64 VALU instructions per call of each special function in this library's gfx950 build,
+# amortised over several calls in one kernel (measured from our own assembly): the device
+# library's exp and expm1, sqrt and cbrt; the library's own log and refined reciprocal.
+SP_COST = {"rcp": 6, "sqrt": 20, "exp": 23, "cbrt": 30, "expm1": 33, "log": 40}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops (FMA).
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
@@ -36,23 +37,29 @@ def log(msg):
 
 
 def ops_per_cell(ns, evals, transport=True):
-    """Algorithmic FP64 work of one (rho, e, Y) cell in VALU lane-operations: every add,
-    multiply or fused multiply-add of the method's formulas counts 1, each special
-    function its instruction cost (SP_COST).  `evals` = e(T) evaluations of the inversion."""
+    """Algorithmic FP64 work of one (rho, e, Y) cell in VALU lane-operations, as the method
+    is evaluated here: every add, multiply or fused multiply-add counts 1 and each special
+    function its instruction cost (SP_COST).  `evals` = e(T) evaluations of the inversion.
+    The mixing sum a_m is built once per cell as A0 + A1 sqrt(T) + A2 T (two mat-vecs) and
+    each evaluation is O(1); five of Chung's six pseudo-mixture sums are single sums."""
     sp = lambda **k: sum(SP_COST[n] * c for n, c in k.items())  # noqa: E731
-    ops = 5 * ns + sp(div=1)                       # composition, X, W, b_m
-    ops += 25 * ns                                 # NASA-7 mixture coefficients (2 ranges)
-    ops += 7 + sp(div=3, log=1)                    # v, departure log L at fixed v
-    per_eval = 2 * ns * ns + 8 * ns + 29 + sp(div=3, sqrt=1)
+    ops = 5 * ns + sp(rcp=1)                          # W, X_i, b_m
+    ops += 12 * ns + ns                               # NASA-7 mixture coefficients (2 ranges)
+    ops += 8 + sp(rcp=3, log=1)                       # v, departure log L at fixed v
+    ops += 8 * ns + 2 * ns * ns + 3 * ns + 3          # A0, A1, A2 of the mixing sum
+    per_eval = 8 + 14 + 10 + 3 + sp(sqrt=1, rcp=2)    # a_m and derivatives, h_ig, c_p, residual, step
     ops += evals * per_eval
-    ops += per_eval + 40 + sp(div=15, log=1, sqrt=1)   # final state, P, h, e, cp, c
+    ops += per_eval + 45 + sp(rcp=10, log=1)          # final state, P, h, e, c_p, c
     if transport:
-        ops += 1 + sp(sqrt=1, log=1, exp=1)
-        ops += ns * (7 + SP_COST["div"] + 2 * SP_COST["exp"])   # species low-pressure viscosity
-        ops += 6 * (ns * (ns + 1) // 2 + ns)       # six pseudo-mixture quadratic forms
-        ops += 22 + sp(div=5, cbrt=1)              # pseudo-critical constants
-        ops += 50 + sp(div=4, exp=2, expm1=1, sqrt=1)    # viscosity
-        ops += 57 + sp(div=7, sqrt=2, exp=1, expm1=1)    # conductivity
+        ops += 2 + sp(sqrt=1, log=1, exp=1)
+        ops += ns * (6 + 2 * SP_COST["exp"] + SP_COST["rcp"])     # species low-pressure viscosity
+        ops += 5 * ns + (ns * (ns + 1) // 2 + ns)    # four single sums + the molar-mass quadratic form
+        ops += 20 + sp(rcp=4, cbrt=1)                 # pseudo-critical constants
+        ops += 30 + 21                                # Chung E and B coefficients
+        ops += 6 + sp(rcp=2)                          # y, 1/y, G1
+        ops += 2 * (8 + sp(expm1=1, exp=1, rcp=1))    # G2 for viscosity and conductivity
+        ops += 14 + sp(exp=1, rcp=3, sqrt=1)          # viscosity
+        ops += 30 + sp(rcp=5, sqrt=2)                 # conductivity
     return ops
 
 

@@ -3,7 +3,8 @@ import ctypes
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-library_path = os.path.join(_HERE, "libprops.so")
+# PROPS_LIBRARY may name another build of the same library (e.g. a tuning variant)
+library_path = os.environ.get("PROPS_LIBRARY", os.path.join(_HERE, "libprops.so"))
 
 PTY, RHOEY = 0, 1
 FP64, MIXED = 0, 1

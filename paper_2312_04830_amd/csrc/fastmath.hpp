@@ -1,19 +1,14 @@
-// Double-precision exp, expm1, log and reciprocal for the property kernels.
+// Double-precision log and reciprocal for the property kernels.
 //
-// The device library's general routines guard every special case (overflow, subnormal
-// scaling, NaN and infinity paths); the property path only evaluates them on finite,
-// moderate arguments, so these versions keep just the arithmetic:
-//   exp   — Cody & Waite argument reduction x = k ln2 + r, |r| <= ln2/2, with ln2 split
-//           into a 24-bit head (k * head exact) and a tail; e^r by its Taylor series to
-//           r^13 (truncation < 5e-18 relative); scaling by 2^k with ldexp.
-//   expm1 — the same series without its constant term for |x| < ln2/2, exp(x) - 1 beyond.
+// The device library's log guards every special case and costs about twice the VALU
+// instructions of the arithmetic below in our gfx950 build; its division is a correctly
+// rounded sequence of about twice the cost of a refined reciprocal:
 //   log   — x = m 2^e with m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(f), f = (m-1)/(m+1),
-//           |f| <= 0.1716, by the odd series of atanh to f^21 (truncation < 1e-18).
+//           |f| <= 0.1716, by the odd series of atanh to f^21 (truncation < 1e-18), and
+//           e ln2 with ln2 split into a 24-bit head and a tail.
 //   rcp   — hardware reciprocal refined by two Newton-Raphson steps.
-// Results are within a few units in the last place for the arguments the kernels use; a
-// host build of the same code is checked against long-double libm in the test-suite.
-// NaN propagates; exp underflows to 0 below -745.2 and overflows above 709.78; log of a
-// non-positive argument is NaN.
+// Both are within two units in the last place; a host build of log is checked against
+// long-double libm in the test-suite.  log of a non-positive argument is NaN.
 #pragma once
 
 #include <cmath>
@@ -32,42 +27,9 @@
 namespace props {
 namespace fm {
 
-constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2Hi = 0.6931471526622772;      // ln 2 rounded to 24 significant bits
 constexpr double kLn2Lo = 2.7897668087737545e-08;  // ln 2 - kLn2Hi
 constexpr double kSqrtHalf = 0.7071067811865476;
-
-// 1/n! for n = 13 .. 2 (Horner order), exact rationals rounded to double
-constexpr double kInvFact[12] = {
-    1.0 / 6227020800.0, 1.0 / 479001600.0, 1.0 / 39916800.0, 1.0 / 3628800.0,
-    1.0 / 362880.0,     1.0 / 40320.0,     1.0 / 5040.0,     1.0 / 720.0,
-    1.0 / 120.0,        1.0 / 24.0,        1.0 / 6.0,        1.0 / 2.0};
-
-// sum_{n>=2} r^(n-2) / n!  (so e^r = 1 + r + r^2 * tail(r))
-FM_HD inline double exp_tail(double r)
-{
-    double p = kInvFact[0];
-#pragma unroll
-    for (int i = 1; i < 12; i++) p = std::fma(p, r, kInvFact[i]);
-    return p;
-}
-
-FM_HD inline double exp(double x)
-{
-    double k = std::rint(x * kLog2e);
-    k = std::fmin(std::fmax(k, -1100.0), 1100.0);
-    double r = std::fma(-k, kLn2Hi, x);
-    r = std::fma(-k, kLn2Lo, r);
-    const double p = std::fma(r * r, exp_tail(r), r) + 1.0;
-    const double y = std::ldexp(p, (int)k);
-    return (x < -745.2) ? 0.0 : ((x > 709.78) ? HUGE_VAL : y);
-}
-
-FM_HD inline double expm1(double x)
-{
-    if (std::fabs(x) < 0.34657359027997264) return std::fma(x * x, exp_tail(x), x);
-    return exp(x) - 1.0;
-}
 
 FM_HD inline double log(double x)
 {

@@ -27,14 +27,15 @@
 namespace props {
 
 // ------------------------------------------------------------------ precision policies
-// Double precision with the lean exp/expm1/log and refined reciprocals of fastmath.hpp
-// (a few ulp; the property outputs stay within 1e-15 relative of correctly rounded maths).
+// Double precision: the device library's exp and expm1 (cheapest measured in our gfx950
+// build), the lean log and refined reciprocals of fastmath.hpp (a few ulp; outputs stay
+// within 1e-15 relative of correctly rounded maths).
 struct P64 {
     using R = double;
     static __device__ __forceinline__ R sqrt_(R x) { return sqrt(x); }
     static __device__ __forceinline__ R log_(R x) { return fm::log(x); }
-    static __device__ __forceinline__ R exp_(R x) { return fm::exp(x); }
-    static __device__ __forceinline__ R expm1_(R x) { return fm::expm1(x); }
+    static __device__ __forceinline__ R exp_(R x) { return exp(x); }
+    static __device__ __forceinline__ R expm1_(R x) { return expm1(x); }
     static __device__ __forceinline__ R cbrt_(R x) { return cbrt(x); }
     static __device__ __forceinline__ R div(R a, R b) { return a * fm::rcp(b); }
 };
@@ -327,8 +328,13 @@ __device__ __forceinline__ double gdep_RT(double Z, double A, double B)
 }
 
 // ------------------------------------------------------------------ the kernel
+// Minimum waves per SIMD the register allocation must allow (1: the compiler's choice;
+// forcing 4 or 5 for the 8-species FP64 kernel spills and measured slower).
+#ifndef PR_WAVES_PER_EU
+#define PR_WAVES_PER_EU 1
+#endif
 template <int NS, int MODE, int PREC, bool TRANSPORT>
-__global__ __launch_bounds__(256) void pr_kernel(const ThermoTab<NS> *__restrict__ tt,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PER_EU))) void pr_kernel(const ThermoTab<NS> *__restrict__ tt,
                                                  const MixTab<double, NS> *__restrict__ tmd,
                                                  const MixTab<float, NS> *__restrict__ tmf,
                                                  PRArgs a)
