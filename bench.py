@@ -114,9 +114,88 @@ def cpu_baseline(res, target_s=15.0):
     t0 = time.perf_counter()
     om.state_rhoe(st["rho"], st["e"], Ys)
     dt = time.perf_counter() - t0
+    # one thread on a smaller strided sample (about 3 s)
+    m1 = int(min(T.size, max(1000, 3.0 / max(dt / idx.size * threads, 1e-9))))
+    i1 = np.arange(0, T.size, max(1, T.size // m1))
+    Y1 = np.ascontiguousarray(Y[:, i1])
+    s1 = om.state_PT(P[i1], T[i1], Y1, transport=False)
+    t0 = time.perf_counter()
+    om.eval(oracle.RHOE, s1["rho"], s1["e"], Y1, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": idx.size / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
             "sample": f"every {stride}th cell of the {res}^3 field ({idx.size} cells), FP64 (rho,e,Y) "
-                      f"by bisection + Chung transport, {dt:.1f} s"}
+                      f"by bisection + Chung transport, {dt:.1f} s",
+            "single_thread_value": i1.size / dt1, "single_thread_sample_cells": int(i1.size),
+            "cpu_model": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Measured device-to-device copy rate (read + write bytes per second), the practical HBM
+    ceiling beside the 8 TB/s specification."""
+    import torch
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    t = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        t.append(e0.elapsed_time(e1) * 1e-3)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / float(np.median(t)) / 1e9
+
+
+def small_case_section(props, synth, reps=200):
+    """4096 independent CH4/O2 cells, (P,T,Y) FP64 -> Z, rho, h, cp, c: a launch-latency case
+    (the data fit in the last-level cache); device time and host round trip per call."""
+    import torch
+    dev = torch.device("cuda:0")
+    sp2 = synth.load_species(["CH4", "O2"])
+    mech2 = props.Mechanism(sp2, synth.synthetic_kij(2))
+    P, T, Y = synth.cells_uniform(4096, seed=0)
+    n = T.size
+    ins = {"P": torch.from_numpy(P).to(dev), "T": torch.from_numpy(T).to(dev),
+           "Y": torch.from_numpy(np.ascontiguousarray(Y)).to(dev)}
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("Z", "rho", "h", "cp", "c")}
+    st = torch.empty(n, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    call = lambda: props.pr(mech2, props.PTY, props.FP64, ins, out, n, status=st, stream=stream)  # noqa: E731
+    for _ in range(10):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dev_us = e0.elapsed_time(e1) * 1e3 / reps
+    rt = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        rt.append(time.perf_counter() - t0)
+    rt = np.array(rt) * 1e6
+    return {"workload": "4096 CH4/O2 cells, P~U[5,15] MPa, T~U[100,1000] K, (P,T,Y) FP64 -> Z,rho,h,cp,c",
+            "device_us_per_call": dev_us, "cells_per_s": n / (dev_us * 1e-6),
+            "round_trip_us_p50": float(np.median(rt)), "round_trip_us_p99": float(np.percentile(rt, 99)),
+            "flagged_cells": int((st != 0).sum())}
 
 
 def _rel_stats(pred, ref, key):
@@ -197,7 +276,7 @@ def dnn_section(props, synth, mech, sp, epochs, n_train, res, reps=5):
     }
 
 
-def serving_section(props, synth, mech, net, n_sub=64, reqs_per_sub=6, load=0.8):
+def serving_section(props, synth, mech, net, n_sub=64, reqs_per_sub=50, loads=(0.5, 0.8)):
     """Concurrent subdomains with log-uniform sizes submit requests with exponential think
     times (closed loop per subdomain); half of them route to the surrogate."""
     import threading
@@ -222,37 +301,44 @@ def serving_section(props, synth, mech, net, n_sub=64, reqs_per_sub=6, load=0.8)
     tk = [server.submit(props.PTY, route[k], int(sizes[k]), ins[k], outs[k]) for k in range(n_sub)]
     for t in tk:
         server.wait(t)
-    cap = float(sizes.sum()) / (time.perf_counter() - t0)
-    mean_gap = n_sub * float(sizes.mean()) / (load * cap)
+    cap_wall = time.perf_counter() - t0
+    cap = float(sizes.sum()) / cap_wall
+    st0 = server.stats()
     server.close()
-    server = props.Server(mech, net, mem_budget=1 << 30, chunk_cells=262144, streams=4)
-    lat = []
-    lock = threading.Lock()
+    res = {"subdomains": n_sub, "requests_per_subdomain": reqs_per_sub,
+           "mean_cells": float(sizes.mean()), "capacity_cells_per_s": cap,
+           "single_round": {"requests": n_sub, "wall_s": cap_wall, "p50_ms": st0["p50_s"] * 1e3,
+                            "p99_ms": st0["p99_s"] * 1e3},
+           "routes": "even subdomains PR mixed, odd DNN with PR fallback",
+           "io": "host (pinned) -> device -> host per request; latency includes PCIe copies",
+           "arrivals": "per subdomain: exponential think time, then submit and wait (closed loop)"}
+    for load in loads:
+        mean_gap = n_sub * float(sizes.mean()) / (load * cap)
+        server = props.Server(mech, net, mem_budget=1 << 30, chunk_cells=262144, streams=4)
 
-    def client(k):
-        rng = np.random.default_rng(1000 + k)
-        for _ in range(reqs_per_sub):
-            time.sleep(rng.exponential(mean_gap))
-            t = server.submit(props.PTY, route[k], int(sizes[k]), ins[k], outs[k])
-            r = server.wait(t)
-            with lock:
-                lat.append(r["latency_s"])
+        def client(k):
+            rng = np.random.default_rng(1000 + k)
+            for _ in range(reqs_per_sub):
+                time.sleep(rng.exponential(mean_gap))
+                server.wait(server.submit(props.PTY, route[k], int(sizes[k]), ins[k], outs[k]))
 
-    th = [threading.Thread(target=client, args=(k,)) for k in range(n_sub)]
-    t0 = time.perf_counter()
-    for x in th:
-        x.start()
-    for x in th:
-        x.join()
-    wall = time.perf_counter() - t0
-    st = server.stats()
-    server.close()
-    return {"subdomains": n_sub, "requests": n_sub * reqs_per_sub, "mean_cells": float(sizes.mean()),
-            "capacity_cells_per_s": cap, "offered_load": load, "mean_think_s": mean_gap,
+        th = [threading.Thread(target=client, args=(k,)) for k in range(n_sub)]
+        t0 = time.perf_counter()
+        for x in th:
+            x.start()
+        for x in th:
+            x.join()
+        wall = time.perf_counter() - t0
+        st = server.stats()
+        server.close()
+        res[f"load_{load}"] = {
+            "offered_load": load, "mean_think_s": mean_gap, "requests": n_sub * reqs_per_sub,
             "cells_per_s": st["cells_per_s"], "p50_ms": st["p50_s"] * 1e3, "p99_ms": st["p99_s"] * 1e3,
             "mean_ms": st["mean_s"] * 1e3, "max_ms": st["max_s"] * 1e3, "wall_s": wall,
-            "slots": st["slots"], "routes": "even subdomains PR mixed, odd DNN with PR fallback",
-            "io": "host (pinned) -> device -> host per request; latency includes PCIe copies"}
+            "slots": st["slots"]}
+        log(f"serving load {load}: p50 {st['p50_s'] * 1e3:.2f} ms, p99 {st['p99_s'] * 1e3:.2f} ms, "
+            f"{wall:.1f} s")
+    return res
 
 
 
@@ -406,6 +492,11 @@ def main():
         ms_ng, _ = timed(props.FP64, max(10, args.steps // 2), 2)
         ins = save
         rec["fp64_no_guess"] = {"value": n / (ms_ng * 1e-3), "ms_per_step": ms_ng}
+        cbw = copy_bandwidth()
+        rec["roofline"]["copy_GBs"] = cbw
+        rec["roofline"]["hbm_frac_of_copy"] = hbm / cbw
+        log(f"device copy {cbw:.0f} GB/s; 4096-cell latency case")
+        rec["small_case"] = small_case_section(props, synth)
 
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB

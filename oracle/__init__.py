@@ -22,7 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _LIB_LOAD = os.environ.get("ORACLE_LIB_OVERRIDE", _LIB)
 MAXNS = 16
 
-PT, RHOE, VT = 0, 1, 2
+PT, RHOE, VT, HP = 0, 1, 2, 3
 NONPHYS, NEWTON_MAXIT, BRACKET, THREE_ROOT, GIBBS_TIE, CV_NONPOS = 1, 2, 4, 8, 16, 32
 
 
@@ -50,8 +50,8 @@ class _Mech(ctypes.Structure):
 CELL_DTYPE = np.dtype([(n, "f8") for n in (
     "T", "P", "Z", "rho", "v", "W", "h", "e", "cp", "cv", "c", "mu", "lambda",
     "am", "dam", "d2am", "bm", "A", "B", "h_ig", "e_ig", "cp_ig", "cv_ig",
-    "h_scale", "e_scale", "kappa_Z", "kappa_cp", "kappa_T")] +
-    [("roots", "f8", (3,)), ("nroots", "i4"), ("nphys", "i4"), ("status", "i4"), ("iters", "i4")])
+    "h_scale", "e_scale", "kappa_Z", "kappa_cp", "kappa_T", "psi", "alpha")] +
+    [("hRT", "f8", (MAXNS,)), ("roots", "f8", (3,)), ("nroots", "i4"), ("nphys", "i4"), ("status", "i4"), ("iters", "i4")])
 
 _lib = None
 
@@ -139,6 +139,9 @@ class Mech:
 
     def state_vT(self, v, T, Y, **kw):
         return self.eval(VT, v, T, Y, **kw)
+
+    def state_hP(self, h, P, Y, **kw):
+        return self.eval(HP, h, P, Y, **kw)
 
     def mix(self, X, T):
         X = np.ascontiguousarray(X, dtype=np.float64)

@@ -21,6 +21,12 @@
  *   - Root selection by minimum Gibbs energy among the physical roots (Z > B).
  *   - Temperature inversion (rho, e, Y) -> T: the root of e(T; v, Y) = e*, here found by
  *     plain bisection to full double resolution (the definition, not an iteration scheme).
+ *   - Temperature inversion (h, P, Y) -> T, the pressure-based solver's state (Section 3:
+ *     properties are refreshed from h and p in every pressure-correction loop): the root of
+ *     h(T; P, Y) = h* with h(T; P, Y) the (P, T, Y) state's enthalpy, by plain bisection.
+ *   - The extra solver outputs of Section 4.1: psi = (d rho / d p) at constant enthalpy
+ *     (and composition), thermal diffusivity lambda / (rho c_p), and each species'
+ *     nondimensional standard-state enthalpy h_i/(R T) from its NASA polynomial.
  *   - Chung et al. (1988) dense-fluid viscosity and thermal conductivity ("modified Chung
  *     with mole-fraction-averaged viscosity", Section 2): Chung's high-pressure model on the
  *     one-fluid pseudo-mixture, with the low-pressure viscosity it builds on taken as the
@@ -77,6 +83,8 @@ typedef struct {
     double h_ig, e_ig, cp_ig, cv_ig;
     double h_scale, e_scale;          /* sums of magnitudes, for relative comparisons */
     double kappa_Z, kappa_cp, kappa_T; /* condition numbers, for tolerance scaling */
+    double psi, alpha;                /* (d rho/d P)_h [s^2/m^2]; lambda/(rho c_p) [m^2/s] */
+    double hRT[ORC_MAXNS];            /* h_i/(R T) of each species (ideal-gas standard state) */
     double roots[3];
     int32_t nroots, nphys;
     int32_t status, iters;
@@ -466,6 +474,8 @@ static void orc_fill_nan(orc_cell *c)
     double nan = NAN;
     c->T = c->P = c->Z = c->rho = c->v = nan;
     c->h = c->e = c->cp = c->cv = c->c = c->mu = c->lambda = nan;
+    c->psi = c->alpha = nan;
+    for (int i = 0; i < ORC_MAXNS; i++) c->hRT[i] = nan;
 }
 
 /* Properties at molar volume v [m^3/mol] and temperature T for mass fractions Y.
@@ -520,10 +530,21 @@ static void orc_props_vT(const orc_mech *m, const double *Y, const double *X, do
     c->kappa_cp = kdv * (1.0 + fabs(T * dPdT * dPdT / dPdv) / fabs(cp_molar));
     c->kappa_T = fabs(c->e_scale) / (T * fabs(c->cv));
     if (cv_molar <= 0.0) c->status |= ORC_CV_NONPOS;
+    /* psi = (d rho/d P) along an isenthalp at fixed composition.  With rho = W/v:
+     *   (dv/dP)_h = (dv/dP)_T + (dv/dT)_P (dT/dP)_h,
+     *   (dv/dP)_T = 1/(dP/dv)_T,  (dv/dT)_P = -(dP/dT)_v/(dP/dv)_T,
+     *   (dT/dP)_h = -(dH/dP)_T / C_p = -(v - T (dv/dT)_P) / C_p   (molar H, C_p). */
+    double dvdP_T = 1.0 / dPdv;
+    double dvdT_P = -dPdT / dPdv;
+    double dTdP_h = -(v - T * dvdT_P) / cp_molar;
+    double dvdP_h = dvdP_T + dvdT_P * dTdP_h;
+    c->psi = -(W / (v * v)) * dvdP_h;
+    for (int i = 0; i < ORC_MAXNS; i++) c->hRT[i] = (i < m->ns) ? orc_nasa_h_RT(&m->sp[i], T) : 0.0;
     if (want_transport) {
         orc_transport(m, X, T, 1.0 / v, W * cvig, &c->mu, &c->lambda);
+        c->alpha = c->lambda / (c->rho * c->cp);
     } else {
-        c->mu = c->lambda = NAN;
+        c->mu = c->lambda = c->alpha = NAN;
     }
 }
 
@@ -662,26 +683,72 @@ void orc_state_rhoe(const orc_mech *m, double rho, double e, const double *Y,
     c->iters = it;
 }
 
+/* Mass-specific enthalpy of the (P, T, Y) state (Gibbs-selected root). */
+static double orc_enthalpy_PT(const orc_mech *m, double P, double T, const double *Y)
+{
+    orc_cell c;
+    orc_state_PT(m, P, T, Y, 0, &c);
+    return c.h;
+}
+
+/* (h, P, Y) mode: T solves h(T; P, Y) = h* with h the (P, T, Y) state's enthalpy, found by
+ * bisection on [60 K, 5000 K] until the midpoint is an endpoint; then the (P, T, Y) state.
+ * Where the selected root switches (liquid- to vapour-like), h(T) jumps and the bisection
+ * ends at the switch temperature; the side with the smaller |h - h*| is reported. */
+void orc_state_hP(const orc_mech *m, double h, double P, const double *Y,
+                  int want_transport, orc_cell *c)
+{
+    memset(c, 0, sizeof(*c));
+    if (!(P > 0.0) || !(h == h) || orc_check_Y(m, Y)) {
+        c->status |= ORC_NONPHYS;
+        orc_fill_nan(c);
+        return;
+    }
+    double lo = ORC_TLO, hi = ORC_THI;
+    double rlo = orc_enthalpy_PT(m, P, lo, Y) - h;
+    double rhi = orc_enthalpy_PT(m, P, hi, Y) - h;
+    if (rlo > 0.0 || rhi < 0.0) {
+        c->status |= ORC_BRACKET;
+        orc_fill_nan(c);
+        return;
+    }
+    int it = 0;
+    for (; it < 4000; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        double r = orc_enthalpy_PT(m, P, mid, Y) - h;
+        if (r == 0.0) { lo = hi = mid; break; }
+        if (r < 0.0) lo = mid; else hi = mid;
+    }
+    double rl = fabs(orc_enthalpy_PT(m, P, lo, Y) - h);
+    double rh = fabs(orc_enthalpy_PT(m, P, hi, Y) - h);
+    double T = (rl <= rh) ? lo : hi;
+    orc_state_PT(m, P, T, Y, want_transport, c);
+    c->iters = it;
+}
+
 /* ----------------------------------------------------------------------------------- */
 /* Batched entry points (cells independent; OpenMP over cells only)                    */
 /* ----------------------------------------------------------------------------------- */
 
 /* mode 0: (P, T, Y) with in0 = P, in1 = T.  mode 1: (rho, e, Y) with in0 = rho, in1 = e.
- * mode 2: (v, T, Y) with in0 = molar volume, in1 = T.  Y is species-major [ns][n]. */
+ * mode 2: (v, T, Y) with in0 = molar volume, in1 = T.  mode 3: (h, P, Y) with in0 = h,
+ * in1 = P.  Y is species-major [ns][n].  nthreads > 0 caps the threads of this call. */
 int orc_eval(const orc_mech *m, int mode, int64_t n, const double *in0, const double *in1,
              const double *Y, int want_transport, orc_cell *out, int nthreads)
 {
-    if (m->ns < 1 || m->ns > ORC_MAXNS || mode < 0 || mode > 2) return -1;
+    if (m->ns < 1 || m->ns > ORC_MAXNS || mode < 0 || mode > 3) return -1;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#pragma omp parallel for schedule(dynamic, 256)
+    const int nt = (nthreads > 0) ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nt)
 #endif
     for (int64_t k = 0; k < n; k++) {
         double y[ORC_MAXNS];
         for (int i = 0; i < m->ns; i++) y[i] = Y[(int64_t)i * n + k];
         if (mode == 0) orc_state_PT(m, in0[k], in1[k], y, want_transport, &out[k]);
         else if (mode == 1) orc_state_rhoe(m, in0[k], in1[k], y, want_transport, &out[k]);
-        else orc_state_vT(m, in0[k], in1[k], y, want_transport, &out[k]);
+        else if (mode == 2) orc_state_vT(m, in0[k], in1[k], y, want_transport, &out[k]);
+        else orc_state_hP(m, in0[k], in1[k], y, want_transport, &out[k]);
     }
     return 0;
 }
