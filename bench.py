@@ -160,6 +160,54 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / float(np.median(t)) / 1e9
 
 
+def hpy_section(props, mech, n, h0, Pd, Yd, Tg, o_rhoe, stream, steps, ncopy=3):
+    """(h, P, Y) mode, the pressure-based solver's state, on the same field: T by Newton
+    with the cubic in every evaluation, all outputs plus psi, alpha and h_i/RT."""
+    import torch
+    dev = Pd.device
+    ins = [{"h": h0.clone(), "P": Pd.clone(), "Y": Yd.clone(), "T_guess": Tg.clone()} for _ in range(ncopy)]
+    keys = ("T", "P", "Z", "rho", "h", "e", "cp", "c", "mu", "lambda", "psi", "alpha")
+    outs = [{k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys} for _ in range(ncopy)]
+    for o in outs:
+        o["hRT"] = torch.empty((Yd.shape[0], n), dtype=torch.float64, device=dev)
+    st = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(ncopy)]
+
+    def timed(prec):
+        for i in range(3):
+            props.pr(mech, props.HPY, prec, ins[i % ncopy], outs[i % ncopy], n, status=st[i % ncopy], stream=stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for i in range(steps):
+            props.pr(mech, props.HPY, prec, ins[i % ncopy], outs[i % ncopy], n, status=st[i % ncopy], stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ms64 = timed(props.FP64)
+    it = torch.empty(n, dtype=torch.uint8, device=dev)
+    o = dict(outs[0], iters=it)
+    props.pr(mech, props.HPY, props.FP64, ins[0], o, n, status=st[0], stream=stream)
+    torch.cuda.synchronize()
+    evals = float(it.double().mean())
+    flagged = int((st[0] != 0).sum())
+    o = {k: v.clone() for k, v in o.items()}     # the timed mixed runs below reuse outs
+    # agreement with the (rho, e, Y) path on the same field (both FP64)
+    t_err = float(((o["T"] / o_rhoe["T"]) - 1).abs().max())
+    ms32 = timed(props.MIXED)
+    o32 = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T", "rho", "cp", "psi")}
+    props.pr(mech, props.HPY, props.MIXED, ins[0], o32, n, stream=stream)
+    torch.cuda.synchronize()
+    err = {k: float(((o32[k] - o[k]).abs() / o[k].abs()).max()) for k in o32}
+    bytes_cell = (3 + Yd.shape[0]) * 8 + (12 + Yd.shape[0]) * 8 + 1
+    return {"workload": "same field, (h,P,Y)->T Newton with the cubic per evaluation, FP64, T_guess; "
+                        "outputs T P Z rho h e cp c mu lambda psi alpha + h_i/RT",
+            "fp64": {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "mean_evals": evals,
+                     "flagged_cells": flagged, "max_rel_T_diff_vs_rhoey": t_err,
+                     "bytes_per_cell": bytes_cell, "hbm_GBs": bytes_cell * n / (ms64 * 1e-3) / 1e9},
+            "mixed": {"value": n / (ms32 * 1e-3), "ms_per_step": ms32, "max_rel_err_vs_fp64": err}}
+
+
 def small_case_section(props, synth, reps=200):
     """4096 independent CH4/O2 cells, (P,T,Y) FP64 -> Z, rho, h, cp, c: a launch-latency case
     (the data fit in the last-level cache); device time and host round trip per call."""
@@ -386,9 +434,10 @@ def main():
     Pd, Td, Yd = dt(P), dt(T), dt(Y)
     rho0 = torch.empty(n, dtype=torch.float64, device=dev)
     e0 = torch.empty_like(rho0)
-    props.pr(mech, props.PTY, props.FP64, {"P": Pd, "T": Td, "Y": Yd}, {"rho": rho0, "e": e0}, n)
+    h0 = torch.empty_like(rho0)
+    props.pr(mech, props.PTY, props.FP64, {"P": Pd, "T": Td, "Y": Yd}, {"rho": rho0, "e": e0, "h": h0}, n)
     torch.cuda.synchronize()
-    del Pd, Td
+    del Td
 
     NCOPY = 3
     ins, outs, stats = [], [], []
@@ -492,6 +541,9 @@ def main():
         ms_ng, _ = timed(props.FP64, max(10, args.steps // 2), 2)
         ins = save
         rec["fp64_no_guess"] = {"value": n / (ms_ng * 1e-3), "ms_per_step": ms_ng}
+        rec["hpy"] = hpy_section(props, mech, n, h0, Pd, Yd, dt(Tg), o_ref, stream, max(10, args.steps // 2))
+        log(f"(h,P,Y): FP64 {rec['hpy']['fp64']['ms_per_step']:.4f} ms, "
+            f"mixed {rec['hpy']['mixed']['ms_per_step']:.4f} ms")
         cbw = copy_bandwidth()
         rec["roofline"]["copy_GBs"] = cbw
         rec["roofline"]["hbm_frac_of_copy"] = hbm / cbw

@@ -80,31 +80,37 @@ int props_mech_create(const props_species_desc *sp, int ns, const double *kij,
 void props_mech_destroy(props_mech_t m);
 int props_mech_num_species(props_mech_t m);
 
-/* Newton options of the (rho, e, Y) inversion: max_iter >= 1 (default 100) and the
- * relative step size below which one last Newton step is taken (default 1e-10). */
+/* Newton options of the (rho, e, Y) and (h, P, Y) inversions: max_iter >= 1 (default 100)
+ * and the relative step size below which one last Newton step is taken (default 1e-10). */
 int props_mech_set_newton(props_mech_t m, int max_iter, double rtol);
 
 /* ------------------------------------------------------------------ property evaluation */
-enum { PROPS_PTY = 0, PROPS_RHOEY = 1 };
+enum { PROPS_PTY = 0, PROPS_RHOEY = 1, PROPS_HPY = 2 };
 enum { PROPS_FP64 = 0, PROPS_MIXED = 1 };
 
 /* Device input arrays, n cells each (Y: ns*n). Unused members may be NULL. */
 typedef struct {
-    const double *P;       /* Pa       (PROPS_PTY) */
+    const double *P;       /* Pa       (PROPS_PTY, PROPS_HPY) */
     const double *T;       /* K        (PROPS_PTY) */
     const double *rho;     /* kg/m^3   (PROPS_RHOEY) */
     const double *e;       /* J/kg     (PROPS_RHOEY) */
-    const double *Y;       /* [ns][n]  (both) */
-    const double *T_guess; /* K, optional start of the T inversion (PROPS_RHOEY) */
+    const double *Y;       /* [ns][n]  (every mode) */
+    const double *T_guess; /* K, optional start of the T inversion (PROPS_RHOEY, PROPS_HPY) */
+    const double *h;       /* J/kg     (PROPS_HPY) */
 } props_in;
 
 /* Device output arrays, n cells each.  A NULL member is not computed or written; with
- * mu and lambda both NULL the transport model is skipped entirely.  iters (optional,
- * PROPS_RHOEY only) receives the number of e(T) evaluations the inversion took, saturated
- * at 255. */
+ * mu, lambda and alpha all NULL the transport model is skipped entirely.  iters (optional,
+ * PROPS_RHOEY and PROPS_HPY) receives the number of residual evaluations the inversion
+ * took, saturated at 255.  The solver outputs of Section 4.1:
+ *   psi   = (d rho / d P) at constant h and Y, s^2/m^2;
+ *   alpha = lambda / (rho cp), the thermal diffusivity, m^2/s;
+ *   hRT   = h_i/(R T) of each species' ideal-gas standard state (NASA polynomial),
+ *           [ns][n] species-major like Y. */
 typedef struct {
     double *T, *P, *Z, *rho, *h, *e, *cp, *c, *mu, *lambda;
     uint8_t *iters;
+    double *psi, *alpha, *hRT;
 } props_out;
 
 /* Evaluate the Peng-Robinson property path on n independent cells.
@@ -112,6 +118,12 @@ typedef struct {
  *                roots (Z > B) by minimum Gibbs energy, then rho, h, e, cp, c (+ mu, lambda).
  *   PROPS_RHOEY: given rho, e, Y: find T with e(T; v = W/rho, Y) = e* by bracketed Newton
  *                iteration on [60, 5000] K, then P from Eq. (1) and every property.
+ *   PROPS_HPY:   given h, P, Y (the state of the pressure-based solver, Section 3): find T
+ *                with h(T; P, Y) = h* by bracketed Newton iteration on [60, 5000] K, the
+ *                cubic and root choice of PROPS_PTY inside every evaluation, the slope
+ *                being the real-fluid cp; then every property at (P, T).  Where the chosen
+ *                root switches (a subcritical two-phase gap) h(T) jumps; an h* inside the
+ *                jump has no root and the iteration ends at the switch temperature.
  *   PROPS_FP64:  every step in double precision.
  *   PROPS_MIXED: mixing sums, departure functions and transport in single precision;
  *                the cubic (discriminant and root polish), the ideal-gas energy and the
@@ -228,7 +240,7 @@ typedef struct {
 } props_serve_cfg;
 
 typedef struct {
-    int mode;                 /* PROPS_PTY or PROPS_RHOEY (PROPS_ROUTE_DNN: PTY only) */
+    int mode;                 /* PROPS_PTY, PROPS_RHOEY or PROPS_HPY (PROPS_ROUTE_DNN: PTY only) */
     int route;                /* PROPS_ROUTE_* */
     int64_t n;
     props_in in;              /* HOST arrays (Y: [ns][n]) */

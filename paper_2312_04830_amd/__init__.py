@@ -6,6 +6,6 @@ and streams; tensors are passed to the C ABI as raw device pointers.  The bindin
 loudly when the library is missing.
 """
 from ._lib import (  # noqa: F401
-    EXEC_GPU, EXEC_MOCK, FP64, MIXED, PTY, RHOEY, ROUTE_DNN, ROUTE_PR_FP64, ROUTE_PR_MIXED, Network,
+    EXEC_GPU, EXEC_MOCK, FP64, HPY, MIXED, PTY, RHOEY, ROUTE_DNN, ROUTE_PR_FP64, ROUTE_PR_MIXED, Network,
     PropsError, Mechanism, Server, lib, library_path, pr, status_bits,
 )

@@ -6,7 +6,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 # PROPS_LIBRARY may name another build of the same library (e.g. a tuning variant)
 library_path = os.environ.get("PROPS_LIBRARY", os.path.join(_HERE, "libprops.so"))
 
-PTY, RHOEY = 0, 1
+PTY, RHOEY, HPY = 0, 1, 2
 FP64, MIXED = 0, 1
 MAX_SPECIES = 8
 
@@ -34,15 +34,19 @@ class SpeciesDesc(ctypes.Structure):
 _P = ctypes.c_void_p
 
 
+IN_FIELDS = ("P", "T", "rho", "e", "Y", "T_guess", "h")
+
+
 class PropsIn(ctypes.Structure):
-    _fields_ = [(n, _P) for n in ("P", "T", "rho", "e", "Y", "T_guess")]
+    _fields_ = [(n, _P) for n in IN_FIELDS]
 
 
 OUT_FIELDS = ("T", "P", "Z", "rho", "h", "e", "cp", "c", "mu", "lambda")
+EXTRA_OUT_FIELDS = ("psi", "alpha", "hRT")   # solver outputs; hRT is [ns][n]
 
 
 class PropsOut(ctypes.Structure):
-    _fields_ = [(n, _P) for n in OUT_FIELDS] + [("iters", _P)]
+    _fields_ = [(n, _P) for n in OUT_FIELDS] + [("iters", _P)] + [(n, _P) for n in EXTRA_OUT_FIELDS]
 
 
 class TrainCfg(ctypes.Structure):
@@ -191,8 +195,8 @@ class Mechanism:
 def pr(mech, mode, prec, inputs, outputs, n, status=None, stream=None):
     """props_pr: ``inputs``/``outputs`` map C field names to contiguous float64 device
     tensors (missing or None = NULL)."""
-    pin = PropsIn(**{k: _ptr(inputs.get(k)) for k in ("P", "T", "rho", "e", "Y", "T_guess")})
-    pout = PropsOut(**{k: _ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)})
+    pin = PropsIn(**{k: _ptr(inputs.get(k)) for k in IN_FIELDS})
+    pout = PropsOut(**{k: _ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",) + EXTRA_OUT_FIELDS})
     check(lib().props_pr(mech.handle, int(mode), int(prec), ctypes.byref(pin), ctypes.byref(pout),
                          int(n), _ptr(status), _stream(stream)))
 
@@ -243,7 +247,7 @@ class Network:
 
     def __call__(self, inputs, outputs, n, fallback=None, status=None, stream=None):
         """props_dnn: inputs P, T, Y; outputs rho, h, cp, c, mu, lambda (device tensors)."""
-        pin = PropsIn(**{k: _ptr(inputs.get(k)) for k in ("P", "T", "rho", "e", "Y", "T_guess")})
+        pin = PropsIn(**{k: _ptr(inputs.get(k)) for k in IN_FIELDS})
         pout = PropsOut(**{k: _ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)})
         check(lib().props_dnn(self.handle, fallback.handle if fallback is not None else None,
                               ctypes.byref(pin), ctypes.byref(pout), int(n), _ptr(status), _stream(stream)))
@@ -314,7 +318,7 @@ class Server:
     def submit(self, mode, route, n, inputs, outputs, status=None):
         """Non-blocking; host arrays must stay alive until wait() returns."""
         req = Request(mode=int(mode), route=int(route), n=int(n),
-                      inp=PropsIn(**{k: _host_ptr(inputs.get(k)) for k in ("P", "T", "rho", "e", "Y", "T_guess")}),
+                      inp=PropsIn(**{k: _host_ptr(inputs.get(k)) for k in IN_FIELDS}),
                       out=PropsOut(**{k: _host_ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)}),
                       status=_host_ptr(status))
         t = ctypes.c_uint64()

@@ -97,6 +97,7 @@ static void fill_thermo(ThermoTab<NS> &t, const props_species_desc *sp, int ns)
         const props_species_desc &s = sp[i];
         t.invW[i] = 1.0 / s.W;
         t.RW[i] = kR / s.W;
+        t.WR[i] = s.W / kR;
         t.b[i] = kOmegaB * kR * s.Tc / s.Pc;
         for (int k = 0; k < 5; k++) {
             t.cp[0][k][i] = t.RW[i] * s.nasa_lo[k];
@@ -219,13 +220,15 @@ int props_pr(props_mech_t m, int mode, int prec, const props_in *in, const props
              int64_t n, uint8_t *status, void *hip_stream)
 {
     if (!m || !in || !out) return fail(PROPS_EINVAL, "props_pr: null mechanism, input or output");
-    if (mode != PROPS_PTY && mode != PROPS_RHOEY) return fail(PROPS_EINVAL, "props_pr: unknown mode %d", mode);
+    if (mode != PROPS_PTY && mode != PROPS_RHOEY && mode != PROPS_HPY)
+        return fail(PROPS_EINVAL, "props_pr: unknown mode %d", mode);
     if (prec != PROPS_FP64 && prec != PROPS_MIXED) return fail(PROPS_EINVAL, "props_pr: unknown precision %d", prec);
     if (n < 0) return fail(PROPS_EINVAL, "props_pr: n = %lld < 0", (long long)n);
     if (n == 0) return PROPS_OK;
     if (!in->Y) return fail(PROPS_EINVAL, "props_pr: Y is NULL");
     if (mode == PROPS_PTY && (!in->P || !in->T)) return fail(PROPS_EINVAL, "props_pr: PTY mode needs P and T");
     if (mode == PROPS_RHOEY && (!in->rho || !in->e)) return fail(PROPS_EINVAL, "props_pr: RHOEY mode needs rho and e");
+    if (mode == PROPS_HPY && (!in->h || !in->P)) return fail(PROPS_EINVAL, "props_pr: HPY mode needs h and P");
     int dev = -1;
     PROPS_HIP_TRY(hipGetDevice(&dev));
     if (dev != m->device)

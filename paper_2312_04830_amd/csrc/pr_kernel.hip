@@ -10,7 +10,11 @@
 //                    minimum residual Gibbs energy between the liquid- and vapour-like root
 //   (rho,e,Y)        bracketed Newton on e(T; v, Y) = e* (v fixed, so the departure log is
 //                    computed once), bisection whenever a step leaves the bracket
-//   departures       e, h, cv, cp, (dP/dT)_v, (dP/dv)_T, sound speed
+//   (h,P,Y)          the pressure-based solver's state (Section 3): bracketed Newton on
+//                    h(T; P, Y) = h* with the cubic and root choice inside every evaluation
+//                    and the real-fluid cp as the slope
+//   departures       e, h, cv, cp, (dP/dT)_v, (dP/dv)_T, sound speed, and the solver
+//                    outputs of Section 4.1: psi = (d rho/d P)_h, lambda/(rho cp), h_i/(R T)
 //   transport        Chung's high-pressure viscosity and conductivity on the pseudo-mixture,
 //                    with the mole-fraction-averaged low-pressure viscosity (Section 2)
 //
@@ -55,6 +59,7 @@ struct P32 {
 struct PRArgs {
     const double *in0, *in1, *Y, *Tg;
     double *oT, *oP, *oZ, *orho, *oh, *oe, *ocp, *oc, *omu, *olam;
+    double *opsi, *oalpha, *ohRT;
     uint8_t *status, *iters;
     const int *idx;    // optional cell list: lane k evaluates cell idx[k] for k < *count
     const int *count;
@@ -327,13 +332,44 @@ __device__ __forceinline__ double gdep_RT(double Z, double A, double B)
            A / (2.0 * kSqrt2 * B) * log((Z + (1.0 + kSqrt2) * B) / (Z + (1.0 - kSqrt2) * B));
 }
 
+// Z of the stable phase at (A, B): the physical roots are those above B; of the smallest
+// and the largest, the one of lower residual Gibbs energy (a tie within 1e-12 takes the
+// vapour-like root).  NaN if there is no physical root.  Sets THREE_ROOT / GIBBS_TIE in st.
+__device__ __forceinline__ double stable_root(double A, double B, uint8_t &st)
+{
+    double z[3];
+    const int nr = cubic_roots(A, B, z);
+    double zl = __builtin_nan(""), zv = __builtin_nan("");
+    int np = 0;
+    for (int r = 0; r < nr; r++) {
+        if (z[r] > B) {
+            if (np == 0) zl = z[r];
+            zv = z[r];
+            np++;
+        }
+    }
+    if (np <= 1) return zv;
+    if (np == 3) st |= PROPS_ST_THREE_ROOT;
+    const double gl = gdep_RT(zl, A, B), gv = gdep_RT(zv, A, B);
+    const double tie = 1e-12 * fmax(1.0, fmax(fabs(gl), fabs(gv)));
+    if (fabs(gl - gv) <= tie) {
+        st |= PROPS_ST_GIBBS_TIE;
+        return zv;
+    }
+    return (gl < gv) ? zl : zv;
+}
+
 // ------------------------------------------------------------------ the kernel
 // Minimum waves per SIMD the register allocation must allow (1: the compiler's choice;
 // forcing 4 or 5 for the 8-species FP64 kernel spills and measured slower).
 #ifndef PR_WAVES_PER_EU
 #define PR_WAVES_PER_EU 1
 #endif
-template <int NS, int MODE, int PREC, bool TRANSPORT>
+// OUTS selects optional output groups at compile time, so that a launch carries only the
+// code (and the register pressure) of what it writes: bit 0 the transport model (mu,
+// lambda, alpha), bit 1 the solver outputs (psi, alpha, h_i/RT).
+constexpr int kOutTransport = 1, kOutSolver = 2;
+template <int NS, int MODE, int PREC, int OUTS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PER_EU))) void pr_kernel(const ThermoTab<NS> *__restrict__ tt,
                                                  const MixTab<double, NS> *__restrict__ tmd,
                                                  const MixTab<float, NS> *__restrict__ tmf,
@@ -341,6 +377,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
 {
     using PM = typename std::conditional<PREC == PROPS_FP64, P64, P32>::type;
     using R = typename PM::R;
+    constexpr bool TRANSPORT = (OUTS & kOutTransport) != 0;
+    constexpr bool SOLVER = (OUTS & kOutSolver) != 0;
     const MixTab<R, NS> *__restrict__ tm;
     if constexpr (PREC == PROPS_FP64) tm = tmd; else tm = tmf;
 
@@ -367,7 +405,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     bad |= !(fabs(sy - 1.0) <= 1e-6);
     const double in0 = a.in0[k], in1 = a.in1[k];
     if (MODE == PROPS_PTY) bad |= !(in0 > 0.0) || !(in1 > 0.0);
-    else bad |= !(in0 > 0.0) || !(in1 == in1);
+    else if (MODE == PROPS_RHOEY) bad |= !(in0 > 0.0) || !(in1 == in1);
+    else bad |= !(in0 == in0) || !(in1 > 0.0);
     const double W = fm::rcp(syw);
     double X[NS];
     R Xr[NS];
@@ -407,10 +446,82 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
         ig.Tmid = tt->Tmid;
     }
 
-    if (MODE == PROPS_PTY && !bad) {
+    if (MODE == PROPS_HPY && !bad) {
+        // ---- (h, P, Y): bracketed Newton on h(T) at fixed P, the cubic in every evaluation
+        P = in1;
+        const double hstar = in0;
+        const double iP = fm::rcp(P);
+        double lo = kTlo, hi = kThi;
+        T = kThi;
+        if (a.Tg) {
+            const double g = a.Tg[k];
+            if (g > kTlo && g < kThi) T = g;
+        }
+        bool fin = false, conv = false;
+        double dT1 = __builtin_inf(), dT2 = __builtin_inf();   // sizes of the last two steps
+        int it = 0;
+        const double rtol = (PREC == PROPS_FP64) ? a.rtol : fmax(a.rtol, 1e-6);
+        MixQuad<PM, NS> mq;
+        mq.build(tm, Xr, T);
+        for (; it < a.maxit; it++) {
+            if (!mq.valid(T)) mq.build(tm, Xr, T);
+            const double sT = sqrt(T);
+            R ram, ram1, ram2;
+            mq.eval((R)T, (R)sT, (R)fm::rcp(sT), ram, ram1, ram2);
+            const double RT = kR * T;
+            const double iRT = fm::rcp(RT);
+            const double A = (double)ram * P * iRT * iRT;
+            const double B = bm * P * iRT;
+            uint8_t st_dummy = 0;
+            const double Z = stable_root(A, B, st_dummy);
+            const double vv = Z * RT * iP;
+            double h_ig, cp_ig;
+            ig.eval(T, h_ig, cp_ig);
+            // departures at (v, T): molar h_dep and the real-fluid c_p (the slope dh/dT at P)
+            const R rv = (R)vv, rb = (R)bm, rT = (R)T;
+            const R rden = rv * rv + R(2) * rb * rv - rb * rb, rvb = rv - rb;
+            const R L = PM::log_(PM::div(rv + R(1.0 + kSqrt2) * rb, rv + R(1.0 - kSqrt2) * rb));
+            const R Lb = PM::div(L, R(2.0 * kSqrt2) * rb);
+            const R edep = (rT * ram1 - ram) * Lb;
+            const R cvdep = rT * ram2 * Lb;
+            const R dPdT = PM::div(R(kR), rvb) - PM::div(ram1, rden);
+            const R dPdv = -PM::div((R)RT, rvb * rvb) + PM::div(R(2) * ram * (rv + rb), rden * rden);
+            const R cvm = (R)(W * (cp_ig - ig.rw)) + cvdep;
+            const R cpm = cvm - PM::div(rT * dPdT * dPdT, dPdv);
+            const double hdep = (double)edep + P * vv - RT;
+            const double r = h_ig + hdep * syw - hstar;
+            const double rp = (double)cpm * syw;
+            if (r > 0.0) hi = T;
+            else if (r < 0.0) lo = T;
+            else { conv = true; break; }
+            // Newton step when it stays in the closed bracket and at least halves the step
+            // taken two iterations before (else Newton can cycle where the slope varies
+            // strongly, as near pseudo-boiling); otherwise bisection.  The last (polishing)
+            // step never bisects: a converged T whose step rounds to nothing sits on a
+            // bracket end, and bisecting there would throw it away.
+            double Tn = T - r * fm::rcp(rp);
+            if (!(rp > 0.0) || !(Tn >= lo && Tn <= hi) || !(fabs(Tn - T) <= 0.5 * dT2))
+                Tn = fin ? T : 0.5 * (lo + hi);
+            const double dT = Tn - T;
+            dT2 = dT1;
+            dT1 = fabs(dT);
+            T = Tn;
+            if (fin) { conv = true; break; }
+            if (fabs(dT) <= rtol * T) fin = true;
+        }
+        if (a.iters) a.iters[k] = (uint8_t)min(it + (conv ? 1 : 0), 255);
+        if (!conv) st |= PROPS_ST_NEWTON_MAXIT;
+        if (T <= kTlo * (1.0 + 1e-9) || T >= kThi * (1.0 - 1e-9)) {
+            st |= PROPS_ST_BRACKET;
+            bad = true;
+        }
+    }
+    if ((MODE == PROPS_PTY || MODE == PROPS_HPY) && !bad) {
         // ---- (P, T, Y): cubic in Z with Gibbs selection
-        P = in0;
-        T = in1;
+        if (MODE == PROPS_PTY) {
+            P = in0;
+            T = in1;
+        }
         MixQuad<PM, NS> mq;
         mq.build(tm, Xr, T);
         const double sT = sqrt(T);
@@ -421,33 +532,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
         const double iRT = fm::rcp(RT);
         const double A = am * P * iRT * iRT;
         const double B = bm * P * iRT;
-        double z[3];
-        const int nr = cubic_roots(A, B, z);
-        double zl = nan, zv = nan;
-        int np = 0;
-        for (int r = 0; r < nr; r++) {
-            if (z[r] > B) {
-                if (np == 0) zl = z[r];
-                zv = z[r];
-                np++;
-            }
-        }
-        double Z = nan;
-        if (np == 0) {
-            bad = true;
-        } else if (np == 1) {
-            Z = zv;
-        } else {
-            if (np == 3) st |= PROPS_ST_THREE_ROOT;
-            const double gl = gdep_RT(zl, A, B), gv = gdep_RT(zv, A, B);
-            const double tie = 1e-12 * fmax(1.0, fmax(fabs(gl), fabs(gv)));
-            if (fabs(gl - gv) <= tie) {
-                Z = zv;
-                st |= PROPS_ST_GIBBS_TIE;
-            } else {
-                Z = (gl < gv) ? zl : zv;
-            }
-        }
+        const double Z = stable_root(A, B, st);
+        if (!(Z == Z)) bad = true;
         v = Z * RT * fm::rcp(P);
     } else if (MODE == PROPS_RHOEY && !bad) {
         // ---- (rho, e, Y): bracketed Newton on e(T) at fixed v
@@ -465,6 +551,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
                 if (g > kTlo && g < kThi) T = g;
             }
             bool fin = false, conv = false;
+            double dT1 = __builtin_inf(), dT2 = __builtin_inf();   // sizes of the last two steps
             int it = 0;
             // With single-precision departures the residual carries ~1e-7 relative noise,
             // so the step criterion is held at 1e-6 there (the double path keeps rtol).
@@ -485,9 +572,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
                 if (r > 0.0) hi = T;
                 else if (r < 0.0) lo = T;
                 else { conv = true; break; }
+                // Newton step when it stays in the closed bracket and at least halves the step
+                // taken two iterations before (else Newton can cycle where the slope varies
+                // strongly, as near pseudo-boiling); otherwise bisection.  The last (polishing)
+                // step never bisects: a converged T whose step rounds to nothing sits on a
+                // bracket end, and bisecting there would throw it away.
                 double Tn = T - r * fm::rcp(rp);
-                if (!(rp > 0.0) || !(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);
+                if (!(rp > 0.0) || !(Tn >= lo && Tn <= hi) || !(fabs(Tn - T) <= 0.5 * dT2))
+                    Tn = fin ? T : 0.5 * (lo + hi);
                 const double dT = Tn - T;
+                dT2 = dT1;
+                dT1 = fabs(dT);
                 T = Tn;
                 if (fin) { conv = true; break; }
                 if (fabs(dT) <= rtol * T) fin = true;
@@ -522,6 +617,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
         if (a.oc) a.oc[k] = nan;
         if (a.omu) a.omu[k] = nan;
         if (a.olam) a.olam[k] = nan;
+        if constexpr (SOLVER) {
+            if (a.opsi) a.opsi[k] = nan;
+            if (a.oalpha) a.oalpha[k] = nan;
+            if (a.ohRT) {
+#pragma unroll
+                for (int i = 0; i < NS; i++)
+                    if (i < a.ns) a.ohRT[(int64_t)i * n + k] = nan;
+            }
+        }
         if (a.status) a.status[k] = st;
         return;
     }
@@ -532,7 +636,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     const double RT = kR * T;
     const double den = v * v + 2.0 * bm * v - bm * bm;
     const double vb = v - bm;
-    double h, e, cp, c;
+    double h, e, cp, c, psi = nan;
     {
         const R rv = (R)v, rb = (R)bm, rT = (R)T, rden = (R)den, rvb = (R)vb;
         const R ram = (R)am, ram1 = (R)am1, ram2 = (R)am2;
@@ -551,6 +655,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
         cp = (double)cpm * syw;
         c = (c2 > R(0)) ? (double)PM::sqrt_(c2) : nan;
         if (!(cvm > R(0))) st |= PROPS_ST_CV_NONPOS;
+        // psi = (d rho/d P)_h = -(W/v^2) (dv/dP)_h with, q = (dP/dT)_v/(dP/dv)_T,
+        // (dv/dP)_h = 1/(dP/dv)_T + q (v + T q)/C_p  (molar C_p)
+        if (SOLVER && a.opsi) {
+            const R idPdv = PM::div(R(1), dPdv);
+            const R q = dPdT * idPdv;
+            const R dvdPh = idPdv + PM::div(q * (rv + rT * q), cpm);
+            psi = -(double)dvdPh * W * fm::rcp(v * v);
+        }
     }
     if (a.oT) a.oT[k] = T;
     if (a.oP) a.oP[k] = P;
@@ -560,18 +672,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     if (a.oe) a.oe[k] = e;
     if (a.ocp) a.ocp[k] = cp;
     if (a.oc) a.oc[k] = c;
+    if (SOLVER && a.opsi) a.opsi[k] = psi;
+    if (SOLVER && a.ohRT) {
+        // h_i/(R T) = (h_i [J/kg]) (W_i/R) / T, from the pre-scaled NASA coefficients
+        const int r = (T >= ig.Tmid) ? 1 : 0;
+        const double iT = fm::rcp(T);
+#pragma unroll
+        for (int i = 0; i < NS; i++) {
+            if (i < a.ns) {
+                const double hi_ = T * (tt->cp[r][0][i] + T * (tt->cp[r][1][i] * 0.5 + T * (tt->cp[r][2][i] * (1.0 / 3.0) +
+                                   T * (tt->cp[r][3][i] * 0.25 + T * (tt->cp[r][4][i] * 0.2))))) + tt->a6[r][i];
+                a.ohRT[(int64_t)i * n + k] = hi_ * tt->WR[i] * iT;
+            }
+        }
+    }
     if constexpr (TRANSPORT) {
         double mu = 0, lam = 0;
         chung<PM, NS>(tm, Xr, (R)T, (R)(1.0 / v), (R)(W * (cp_ig - ig.rw)), a.omu != nullptr,
-                      a.olam != nullptr, &mu, &lam);
+                      a.olam != nullptr || (SOLVER && a.oalpha != nullptr), &mu, &lam);
         if (a.omu) a.omu[k] = mu;
         if (a.olam) a.olam[k] = lam;
+        if (SOLVER && a.oalpha) a.oalpha[k] = lam * v * fm::rcp(W * cp);
     }
     if (a.status) a.status[k] = st;
 }
 
 // ------------------------------------------------------------------ host launch
-template <int NS, int MODE, int PREC, bool TR>
+template <int NS, int MODE, int PREC, int OUTS>
 static int launch_one(const props_mech_s *m, const PRArgs &a, hipStream_t s)
 {
     const auto *base = static_cast<const unsigned char *>(m->d_tab);
@@ -580,24 +707,35 @@ static int launch_one(const props_mech_s *m, const PRArgs &a, hipStream_t s)
     const auto *tmf = reinterpret_cast<const MixTab<float, NS> *>(base + m->off_mixf);
     const int64_t blocks = (a.n + 255) / 256;
     if (blocks > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_pr: n = %lld too large", (long long)a.n);
-    hipLaunchKernelGGL((pr_kernel<NS, MODE, PREC, TR>), dim3((unsigned)blocks), dim3(256), 0, s, tt, tmd, tmf, a);
+    hipLaunchKernelGGL((pr_kernel<NS, MODE, PREC, OUTS>), dim3((unsigned)blocks), dim3(256), 0, s, tt, tmd, tmf, a);
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
 }
 
-template <int NS>
-static int dispatch_ns(const props_mech_s *m, int mode, int prec, bool tr, const PRArgs &a, hipStream_t s)
+template <int NS, int MODE, int PREC>
+static int launch_outs(const props_mech_s *m, int outs, const PRArgs &a, hipStream_t s)
 {
-    if (mode == PROPS_PTY) {
-        if (prec == PROPS_FP64) return tr ? launch_one<NS, PROPS_PTY, PROPS_FP64, true>(m, a, s)
-                                          : launch_one<NS, PROPS_PTY, PROPS_FP64, false>(m, a, s);
-        return tr ? launch_one<NS, PROPS_PTY, PROPS_MIXED, true>(m, a, s)
-                  : launch_one<NS, PROPS_PTY, PROPS_MIXED, false>(m, a, s);
+    switch (outs) {
+        case 0: return launch_one<NS, MODE, PREC, 0>(m, a, s);
+        case kOutTransport: return launch_one<NS, MODE, PREC, kOutTransport>(m, a, s);
+        case kOutSolver: return launch_one<NS, MODE, PREC, kOutSolver>(m, a, s);
+        default: return launch_one<NS, MODE, PREC, kOutTransport | kOutSolver>(m, a, s);
     }
-    if (prec == PROPS_FP64) return tr ? launch_one<NS, PROPS_RHOEY, PROPS_FP64, true>(m, a, s)
-                                      : launch_one<NS, PROPS_RHOEY, PROPS_FP64, false>(m, a, s);
-    return tr ? launch_one<NS, PROPS_RHOEY, PROPS_MIXED, true>(m, a, s)
-              : launch_one<NS, PROPS_RHOEY, PROPS_MIXED, false>(m, a, s);
+}
+
+template <int NS, int MODE>
+static int launch_prec(const props_mech_s *m, int prec, int outs, const PRArgs &a, hipStream_t s)
+{
+    return (prec == PROPS_FP64) ? launch_outs<NS, MODE, PROPS_FP64>(m, outs, a, s)
+                                : launch_outs<NS, MODE, PROPS_MIXED>(m, outs, a, s);
+}
+
+template <int NS>
+static int dispatch_ns(const props_mech_s *m, int mode, int prec, int outs, const PRArgs &a, hipStream_t s)
+{
+    if (mode == PROPS_PTY) return launch_prec<NS, PROPS_PTY>(m, prec, outs, a, s);
+    if (mode == PROPS_RHOEY) return launch_prec<NS, PROPS_RHOEY>(m, prec, outs, a, s);
+    return launch_prec<NS, PROPS_HPY>(m, prec, outs, a, s);
 }
 
 static int launch_pr_args(const props_mech_s *m, int mode, int prec, const props_in *in,
@@ -608,24 +746,26 @@ static int launch_pr_args(const props_mech_s *m, int mode, int prec, const props
     a.idx = idx;
     a.count = count;
     a.st_or = st_or;
-    a.in0 = (mode == PROPS_PTY) ? in->P : in->rho;
-    a.in1 = (mode == PROPS_PTY) ? in->T : in->e;
+    a.in0 = (mode == PROPS_PTY) ? in->P : (mode == PROPS_RHOEY) ? in->rho : in->h;
+    a.in1 = (mode == PROPS_PTY) ? in->T : (mode == PROPS_RHOEY) ? in->e : in->P;
     a.Y = in->Y;
-    a.Tg = (mode == PROPS_RHOEY) ? in->T_guess : nullptr;
+    a.Tg = (mode != PROPS_PTY) ? in->T_guess : nullptr;
     a.oT = out->T, a.oP = out->P, a.oZ = out->Z, a.orho = out->rho, a.oh = out->h;
     a.oe = out->e, a.ocp = out->cp, a.oc = out->c, a.omu = out->mu, a.olam = out->lambda;
+    a.opsi = out->psi, a.oalpha = out->alpha, a.ohRT = out->hRT;
     a.status = status;
-    a.iters = (mode == PROPS_RHOEY) ? out->iters : nullptr;
+    a.iters = (mode != PROPS_PTY) ? out->iters : nullptr;
     a.n = n;
     a.ns = m->ns;
     a.maxit = m->maxit;
     a.rtol = m->rtol;
-    const bool tr = out->mu || out->lambda;
+    const int outs = ((out->mu || out->lambda || out->alpha) ? kOutTransport : 0) |
+                     ((out->psi || out->alpha || out->hRT) ? kOutSolver : 0);
     switch (m->nsp) {
-        case 1: return dispatch_ns<1>(m, mode, prec, tr, a, stream);
-        case 2: return dispatch_ns<2>(m, mode, prec, tr, a, stream);
-        case 4: return dispatch_ns<4>(m, mode, prec, tr, a, stream);
-        default: return dispatch_ns<8>(m, mode, prec, tr, a, stream);
+        case 1: return dispatch_ns<1>(m, mode, prec, outs, a, stream);
+        case 2: return dispatch_ns<2>(m, mode, prec, outs, a, stream);
+        case 4: return dispatch_ns<4>(m, mode, prec, outs, a, stream);
+        default: return dispatch_ns<8>(m, mode, prec, outs, a, stream);
     }
 }
 

@@ -49,6 +49,7 @@ struct ThermoTab {
     double b[NS];         // PR co-volume b_i [m^3/mol]
     double cp[2][5][NS];  // (R/W_i) a1..a5 per range (0: T < Tmid, 1: T >= Tmid), J/(kg K)
     double a6[2][NS];     // (R/W_i) a6 per range, J/kg
+    double WR[NS];        // W_i/R [kg K/J], turns a species' h [J/kg] at T into h/(R T) * T
     double Tmid;
 };
 

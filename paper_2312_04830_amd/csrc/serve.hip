@@ -97,6 +97,14 @@ struct props_server_s {
 
 namespace {
 
+// The two per-cell scalar inputs of a request's mode (Y aside): (P, T), (rho, e) or (h, P).
+void mode_inputs(const props_request &q, const double **a, const double **b)
+{
+    if (q.mode == PROPS_PTY) *a = q.in.P, *b = q.in.T;
+    else if (q.mode == PROPS_RHOEY) *a = q.in.rho, *b = q.in.e;
+    else *a = q.in.h, *b = q.in.P;
+}
+
 int dispatch_gpu(props_server_s *S, Chunk *ch, const Request &R)
 {
     const Slot &sl = S->slots[ch->slot];
@@ -105,7 +113,8 @@ int dispatch_gpu(props_server_s *S, Chunk *ch, const Request &R)
     const int64_t m = ch->m, off = ch->off, n = q.n;
     const size_t b = (size_t)m * sizeof(double);
     const bool pty = q.mode == PROPS_PTY;
-    const double *h0 = pty ? q.in.P : q.in.rho, *h1 = pty ? q.in.T : q.in.e;
+    const double *h0, *h1;
+    mode_inputs(q, &h0, &h1);
     PROPS_HIP_TRY(hipMemcpyAsync(sl.in0, h0 + off, b, hipMemcpyHostToDevice, st));
     PROPS_HIP_TRY(hipMemcpyAsync(sl.in1, h1 + off, b, hipMemcpyHostToDevice, st));
     for (int i = 0; i < S->ns; i++)
@@ -114,7 +123,8 @@ int dispatch_gpu(props_server_s *S, Chunk *ch, const Request &R)
     if (tg) PROPS_HIP_TRY(hipMemcpyAsync(sl.Tg, q.in.T_guess + off, b, hipMemcpyHostToDevice, st));
     props_in in{};
     if (pty) in.P = sl.in0, in.T = sl.in1;
-    else in.rho = sl.in0, in.e = sl.in1;
+    else if (q.mode == PROPS_RHOEY) in.rho = sl.in0, in.e = sl.in1;
+    else in.h = sl.in0, in.P = sl.in1;
     in.Y = sl.Y;
     in.T_guess = tg ? sl.Tg : nullptr;
     props_out out{};
@@ -142,8 +152,8 @@ int dispatch_gpu(props_server_s *S, Chunk *ch, const Request &R)
 void mock_eval(props_server_s *S, Chunk *ch, const Request &R)
 {
     const props_request &q = R.r;
-    const bool pty = q.mode == PROPS_PTY;
-    const double *a = pty ? q.in.P : q.in.rho, *b = pty ? q.in.T : q.in.e;
+    const double *a, *b;
+    mode_inputs(q, &a, &b);
     if (ch->m > 0 && std::isnan(a[ch->off])) {
         ch->rc = fail(PROPS_EINVAL, "mock executor: chunk rejected (NaN first input)");
         return;
@@ -366,14 +376,15 @@ int serve_submit(props_server_t S, const props_request *req, uint64_t *ticket)
     if (!S || !req || !ticket) return fail(PROPS_EINVAL, "serve_submit: null argument");
     const props_request &q = *req;
     if (q.n <= 0) return fail(PROPS_EINVAL, "serve_submit: n = %lld", (long long)q.n);
-    if (q.mode != PROPS_PTY && q.mode != PROPS_RHOEY) return fail(PROPS_EINVAL, "serve_submit: unknown mode %d", q.mode);
+    if (q.mode != PROPS_PTY && q.mode != PROPS_RHOEY && q.mode != PROPS_HPY)
+        return fail(PROPS_EINVAL, "serve_submit: unknown mode %d", q.mode);
     if (q.route < PROPS_ROUTE_PR_FP64 || q.route > PROPS_ROUTE_DNN)
         return fail(PROPS_EINVAL, "serve_submit: unknown route %d", q.route);
     if (q.route == PROPS_ROUTE_DNN && (!S->dnn || q.mode != PROPS_PTY))
         return fail(PROPS_EINVAL, "serve_submit: the DNN route needs a network and (P, T, Y) inputs");
-    const bool pty = q.mode == PROPS_PTY;
-    if (!q.in.Y || (pty && (!q.in.P || !q.in.T)) || (!pty && (!q.in.rho || !q.in.e)))
-        return fail(PROPS_EINVAL, "serve_submit: missing input arrays");
+    const double *a, *b;
+    mode_inputs(q, &a, &b);
+    if (!q.in.Y || !a || !b) return fail(PROPS_EINVAL, "serve_submit: missing input arrays");
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->stop) return fail(PROPS_ENOTREADY, "serve_submit: server is shutting down");
     const uint64_t t = S->next_ticket++;

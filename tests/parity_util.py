@@ -6,14 +6,21 @@ R = 8.31446261815324
 FIELDS = ("T", "P", "Z", "rho", "h", "e", "cp", "c", "mu", "lambda")
 
 
-def run_gpu(props, mech, mode, prec, n, inputs, fields=FIELDS, stream=None, want_status=True):
-    """Copy numpy inputs to the device, call props_pr, return numpy outputs + status."""
+def run_gpu(props, mech, mode, prec, n, inputs, fields=FIELDS, stream=None, want_status=True, ns=None):
+    """Copy numpy inputs to the device, call props_pr, return numpy outputs + status
+    (hRT, [ns][n], needs ns)."""
     import torch
     dev = torch.device("cuda:0")
     tin = {k: torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).to(dev)
            for k, v in inputs.items() if v is not None}
-    tout = {k: (torch.zeros(n, dtype=torch.uint8, device=dev) if k == "iters" else
-                torch.full((n,), -12345.0, dtype=torch.float64, device=dev)) for k in fields}
+
+    def alloc(k):
+        if k == "iters":
+            return torch.zeros(n, dtype=torch.uint8, device=dev)
+        shape = (ns, n) if k == "hRT" else (n,)
+        return torch.full(shape, -12345.0, dtype=torch.float64, device=dev)
+
+    tout = {k: alloc(k) for k in fields}
     st = torch.full((n,), 255, dtype=torch.uint8, device=dev) if want_status else None
     props.pr(mech, mode, prec, tin, tout, n, status=st, stream=stream)
     torch.cuda.synchronize()

@@ -19,14 +19,19 @@ def make_request(n, seed, mode=P.PTY):
     a = rng.uniform(1e6, 2e7, n)
     b = rng.uniform(100, 3000, n)
     Y = rng.dirichlet(np.ones(NS), n).T.copy()
-    ins = {"P": a, "T": b, "Y": Y} if mode == P.PTY else {"rho": a, "e": b, "Y": Y}
+    if mode == P.PTY:
+        ins = {"P": a, "T": b, "Y": Y}
+    elif mode == P.RHOEY:
+        ins = {"rho": a, "e": b, "Y": Y}
+    else:
+        ins = {"h": a, "P": b, "Y": Y}
     outs = {k: np.full(n, np.nan) for k in OUTS}
     return ins, outs, np.full(n, 255, dtype=np.uint8)
 
 
 def expected(ins, mode, route):
-    a = ins["P"] if mode == P.PTY else ins["rho"]
-    b = ins["T"] if mode == P.PTY else ins["e"]
+    a, b = {P.PTY: ("P", "T"), P.RHOEY: ("rho", "e"), P.HPY: ("h", "P")}[mode]
+    a, b = ins[a], ins[b]
     ys = sum((i + 1) * ins["Y"][i] for i in range(NS))
     n = a.size
     return {"T": b, "P": a, "Z": ys, "rho": a + 2 * b, "h": a * b, "e": a - b, "cp": ys * 3,
@@ -44,7 +49,7 @@ def test_every_cell_returns_to_its_place():
     s = server(streams=3)
     reqs = []
     for i, (n, mode, route) in enumerate([(1, P.PTY, 0), (999, P.PTY, 1), (1000, P.RHOEY, 0),
-                                          (1001, P.PTY, 1), (5432, P.RHOEY, 1), (37, P.PTY, 0)]):
+                                          (1001, P.HPY, 1), (5432, P.RHOEY, 1), (37, P.HPY, 0)]):
         ins, outs, st = make_request(n, i, mode)
         reqs.append((s.submit(mode, route, n, ins, outs, st), ins, outs, st, mode, route))
     for t, ins, outs, st, mode, route in reqs:

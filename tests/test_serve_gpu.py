@@ -130,3 +130,29 @@ def test_small_budget_still_completes(env):
     o, st = run_alone(P, s, P.PTY, P.ROUTE_PR_MIXED, ins, KEYS6)
     assert np.all(np.isfinite(o["rho"])) and np.all(st == 0)
     s.close()
+
+
+def test_server_hpy_equals_direct_calls(env):
+    """(h, P, Y) requests through the server equal a direct props_pr call bit for bit."""
+    import torch
+    P, mech, net = env
+    s = P.Server(mech, net, mem_budget=256 << 20, chunk_cells=1024, streams=2)
+    ins = req(3000, 11, res=16)
+    n = 3000
+    d = {k: torch.from_numpy(v).to("cuda:0") for k, v in ins.items()}
+    h = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    P.pr(mech, P.PTY, P.FP64, d, {"h": h}, n)
+    torch.cuda.synchronize()
+    hin = {"h": h.cpu().numpy(), "P": ins["P"], "Y": ins["Y"], "T_guess": ins["T"] * 0.995}
+    dh = {k: torch.from_numpy(v).to("cuda:0") for k, v in hin.items()}
+    for route, prec in ((P.ROUTE_PR_FP64, P.FP64), (P.ROUTE_PR_MIXED, P.MIXED)):
+        o, st = run_alone(P, s, P.HPY, route, hin, KEYS10)
+        od = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in KEYS10}
+        sd = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        P.pr(mech, P.HPY, prec, dh, od, n, status=sd)
+        torch.cuda.synchronize()
+        for k in KEYS10:
+            assert np.array_equal(o[k], od[k].cpu().numpy(), equal_nan=True), (route, k)
+        assert np.array_equal(st, sd.cpu().numpy())
+        assert np.all(st == 0)
+    s.close()
