@@ -282,54 +282,73 @@ __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restri
 }
 
 // ------------------------------------------------------------------ cubic (double)
-// Real roots of Z^3 + c2 Z^2 + c1 Z + c0 for Eq. (1) in Z, ascending; returns the count.
+// Eq. (1) as a cubic in Z: Z^3 + c2 Z^2 + c1 Z + c0 = 0.  Only the extreme roots matter for
+// the phase choice, so the largest root is taken directly (Cardano's real root when the
+// discriminant is positive, else the largest trigonometric root 2 r cos(phi/3)), polished by
+// Newton on the cubic, and the cubic is deflated by it to a quadratic whose two roots, when
+// real, are the smaller pair (each polished on the full cubic).  One transcendental chain
+// per cell instead of three cosines and three polishes.
+struct Cubic {
+    double c2, c1, c0;
+    __device__ __forceinline__ double f(double x) const { return ((x + c2) * x + c1) * x + c0; }
+    __device__ __forceinline__ double fp(double x) const { return (3.0 * x + 2.0 * c2) * x + c1; }
+    // one guarded Newton step (skipped if it would move the root by more than 0.1 %)
+    __device__ __forceinline__ double polish(double x) const
+    {
+        const double d = fp(x);
+        if (d != 0.0) {
+            const double dx = f(x) * fm::rcp(d);
+            if (fabs(dx) < 1e-3 * fabs(x) + 1e-12) return x - dx;
+        }
+        return x;
+    }
+};
+
+// Roots of Eq. (1) in ascending order: z[2] is the largest; z[0] <= z[1] are the deflated
+// pair when the cubic has three real roots (then 3 is returned), else 1.
 __device__ __forceinline__ int cubic_roots(double A, double B, double z[3])
 {
-    const double c2 = B - 1.0;
-    const double c1 = A - 3.0 * B * B - 2.0 * B;
-    const double c0 = -(A * B - B * B - B * B * B);
-    const double sh = c2 * (1.0 / 3.0);
-    const double p = c1 - c2 * sh;
-    const double q = (2.0 * c2 * c2 * c2 - 9.0 * c2 * c1) * (1.0 / 27.0) + c0;
+    Cubic cb;
+    cb.c2 = B - 1.0;
+    cb.c1 = A - 3.0 * B * B - 2.0 * B;
+    cb.c0 = -(A * B - B * B - B * B * B);
+    const double sh = cb.c2 * (1.0 / 3.0);
+    const double p = cb.c1 - cb.c2 * sh;
+    const double q = (2.0 * cb.c2 * cb.c2 * cb.c2 - 9.0 * cb.c2 * cb.c1) * (1.0 / 27.0) + cb.c0;
     const double D = 0.25 * q * q + p * p * p * (1.0 / 27.0);
+    double zx;
     int nr;
     if (D > 0.0) {
         const double C = -0.5 * q - copysign(sqrt(D), q);
         const double t = cbrt(C);
-        const double t1 = (t != 0.0) ? t - p / (3.0 * t) : 0.0;
-        z[0] = t1 - sh;
+        zx = ((t != 0.0) ? t - p * fm::rcp(3.0 * t) : 0.0) - sh;
         nr = 1;
     } else {
         const double r = sqrt(-p * (1.0 / 3.0));
-        double arg = (r > 0.0) ? -0.5 * q / (r * r * r) : 0.0;
+        double arg = (r > 0.0) ? -0.5 * q * fm::rcp(r * r * r) : 0.0;
         arg = fmin(1.0, fmax(-1.0, arg));
-        const double ph = acos(arg) * (1.0 / 3.0);
-        const double tpi3 = 2.0943951023931957;  // 2 pi / 3
-        z[0] = 2.0 * r * cos(ph + tpi3) - sh;
-        z[1] = 2.0 * r * cos(ph - tpi3) - sh;
-        z[2] = 2.0 * r * cos(ph) - sh;
+        zx = 2.0 * r * cos(acos(arg) * (1.0 / 3.0)) - sh;
         nr = 3;
     }
-    // Newton polish on the cubic itself
-    for (int k = 0; k < nr; k++) {
-#pragma unroll
-        for (int it = 0; it < 2; it++) {
-            const double x = z[k];
-            const double f = ((x + c2) * x + c1) * x + c0;
-            const double fp = (3.0 * x + 2.0 * c2) * x + c1;
-            if (fp != 0.0) {
-                const double dx = f / fp;
-                if (fabs(dx) < 1e-3 * fabs(x) + 1e-12) z[k] = x - dx;
-            }
-        }
+    zx = cb.polish(cb.polish(zx));
+    z[2] = zx;
+    if (nr == 3) {
+        // Z^3 + c2 Z^2 + c1 Z + c0 = (Z - zx)(Z^2 + b1 Z + b0)
+        const double b1 = cb.c2 + zx;
+        const double b0 = cb.c1 + zx * b1;
+        const double sd = sqrt(fmax(b1 * b1 - 4.0 * b0, 0.0));
+        const double qq = -0.5 * (b1 + copysign(sd, b1));
+        const double za = qq, zb = (qq != 0.0) ? b0 * fm::rcp(qq) : 0.0;
+        z[0] = cb.polish(cb.polish(fmin(za, zb)));
+        z[1] = cb.polish(cb.polish(fmax(za, zb)));
     }
     return nr;
 }
 
 __device__ __forceinline__ double gdep_RT(double Z, double A, double B)
 {
-    return Z - 1.0 - log(Z - B) -
-           A / (2.0 * kSqrt2 * B) * log((Z + (1.0 + kSqrt2) * B) / (Z + (1.0 - kSqrt2) * B));
+    return Z - 1.0 - fm::log(Z - B) -
+           A * fm::rcp(2.0 * kSqrt2 * B) * fm::log((Z + (1.0 + kSqrt2) * B) * fm::rcp(Z + (1.0 - kSqrt2) * B));
 }
 
 // Z of the stable phase at (A, B): the physical roots are those above B; of the smallest
@@ -339,16 +358,12 @@ __device__ __forceinline__ double stable_root(double A, double B, uint8_t &st)
 {
     double z[3];
     const int nr = cubic_roots(A, B, z);
-    double zl = __builtin_nan(""), zv = __builtin_nan("");
-    int np = 0;
-    for (int r = 0; r < nr; r++) {
-        if (z[r] > B) {
-            if (np == 0) zl = z[r];
-            zv = z[r];
-            np++;
-        }
-    }
-    if (np <= 1) return zv;
+    const double zv = z[2];
+    if (!(zv > B)) return __builtin_nan("");
+    if (nr == 1) return zv;
+    const int np = 1 + (z[1] > B ? 1 : 0) + (z[0] > B ? 1 : 0);
+    if (np == 1) return zv;
+    const double zl = (z[0] > B) ? z[0] : z[1];
     if (np == 3) st |= PROPS_ST_THREE_ROOT;
     const double gl = gdep_RT(zl, A, B), gv = gdep_RT(zv, A, B);
     const double tie = 1e-12 * fmax(1.0, fmax(fabs(gl), fabs(gv)));
