@@ -3,16 +3,16 @@
 // Network: 10 -> 256 -> 256 -> 256 -> 256 -> 6, GELU after each hidden layer, L1 loss.
 //
 // Inference / training forward: one fused kernel.  Cells are the N dimension of
-// v_mfma_f32_16x16x32_bf16 (16 cells per MFMA column block) and features the M and K
-// dimensions, so the 16x16 FP32 accumulator of an output block holds, in each lane, four
-// consecutive output features of one cell.  Two such blocks (32 features) are exactly the
-// eight bf16 values one lane contributes to the B operand of the next layer, so
-// activations never leave registers: the next layer's weights are stored with the
-// matching permutation of their input index.  Each wave carries 32 cells (two column
-// blocks) through all five layers; the 8 waves of a workgroup share each layer's weights,
-// staged once per 256-cell tile in LDS (rows padded by 16 bytes so the 16 lanes reading
-// 16 rows hit distinct banks).  GELU (tanh form, hardware exp2 and reciprocal) and the
-// bias are applied in FP32 on the accumulators, then packed to bf16 with
+// v_mfma_f32_32x32x16_bf16 (32 cells per wave) and features the M and K dimensions: the
+// 32x32 FP32 accumulator of a 32-feature output block holds, in each lane, 16 features of
+// one cell, which are exactly the 2 x 8 bf16 values that lane contributes to two K blocks
+// of the next layer's B operand.  Activations therefore never leave registers; the next
+// layer's weights are stored with the matching permutation of their input index.  The 8
+// waves of a workgroup share each layer's weights, staged once per 256-cell tile in LDS
+// (rows padded by 16 bytes so that the lanes reading consecutive rows hit distinct banks);
+// a 32-row A fragment feeds 32 cells, twice the reuse of the 16x16 shape, which halves the
+// LDS traffic per matrix-core operation.  GELU (tanh form, hardware exp2 and reciprocal)
+// and the bias are applied in FP32 on the accumulators, then packed to bf16 with
 // v_cvt_pk_bf16_f32 (round to nearest even).
 //
 // Backward: tiled bf16 GEMMs (64x64x32 tiles, 4 waves of 2x2 MFMA blocks) for
@@ -34,13 +34,16 @@ namespace props {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short bf16_t;  // storage type of a bfloat16
 
 constexpr int NIN = PROPS_DNN_IN, NOUT = PROPS_DNN_OUT, HID = PROPS_DNN_HIDDEN, NL = PROPS_DNN_LAYERS;
-constexpr int IN_PAD = 32;     // input features padded to one K block of the MFMA
-constexpr int OUT_PAD = 16;    // output rows padded to one 16-row block
+constexpr int IN_PAD = 32;     // input columns of the layer-0 weights and of saved inputs
+constexpr int OUT_PAD = 16;    // output rows of the last layer's weights and saved outputs
 constexpr int HROW = HID + 8;  // bf16 per weight row in the fused layout (528 B)
-constexpr int IROW = IN_PAD + 8;
+constexpr int FK0 = 16;        // layer-0 K in the fused layout: one 16-deep K block
+constexpr int IROW = FK0 + 8;  // bf16 per layer-0 fused row (48 B)
+constexpr int FOUT_ROWS = 32;  // last layer padded to one 32-row output block
 constexpr int FWD_WAVES = 8;
 constexpr int FWD_THREADS = FWD_WAVES * 64;
 constexpr int CELLS_PER_WAVE = 32;
@@ -60,7 +63,9 @@ __host__ __device__ constexpr int tin(int l) { return l == 0 ? NIN : HID; }
 // the natural bf16 layout
 __host__ __device__ constexpr size_t w_off(int l) { return l == 0 ? 0 : w_off(l - 1) + (size_t)lout(l - 1) * lin(l - 1) + lout(l - 1); }
 __host__ __device__ constexpr size_t b_off(int l) { return w_off(l) + (size_t)lout(l) * lin(l); }
-__host__ __device__ constexpr size_t f_off(int l) { return l == 0 ? 0 : f_off(l - 1) + (size_t)lout(l - 1) * lrow(l - 1); }
+// rows of each layer in the fused layout (the last layer padded to a 32-row block)
+__host__ __device__ constexpr int frows(int l) { return l == NL - 1 ? FOUT_ROWS : lout(l); }
+__host__ __device__ constexpr size_t f_off(int l) { return l == 0 ? 0 : f_off(l - 1) + (size_t)frows(l - 1) * lrow(l - 1); }
 __host__ __device__ constexpr size_t n_off(int l) { return l == 0 ? 0 : n_off(l - 1) + (size_t)lout(l - 1) * lin(l - 1); }
 struct Layout {
     static constexpr size_t total = w_off(NL);
@@ -90,6 +95,15 @@ __device__ __forceinline__ bf16_t to_bf16(float a) { return (bf16_t)(pack_bf16x2
 
 __device__ __forceinline__ float bf16_to_f(bf16_t h) { return __builtin_bit_cast(float, (unsigned)h << 16); }
 
+// k-slot of input feature i (i >= 0) in the fused layout of a layer after a hidden one: the
+// 32x32 accumulator gives lane half h the features 8q + 4h + (0..3) of a block, q = 0..3,
+// and its values 8c..8c+7 form K block 2 ob + c, so within each 16-feature block r = i % 16
+// sits at slot 8 ((r >> 2) & 1) + 4 (r >> 3) + (r & 3): bits 2 and 3 of r swap.
+__host__ __device__ constexpr int kslot(int i)
+{
+    return (i & ~15) | (((i >> 2) & 1) << 3) | (((i >> 3) & 1) << 2) | (i & 3);
+}
+
 // GELU, tanh form of Hendrycks & Gimpel: x * sigmoid(2 sqrt(2/pi) (x + 0.044715 x^3)),
 // with exp2 and reciprocal on the transcendental unit.
 constexpr float kG0 = -2.0f * 0.7978845608028654f * 1.4426950408889634f;  // -2 sqrt(2/pi) log2(e)
@@ -115,6 +129,11 @@ __device__ __forceinline__ float gelu_grad_f(float x)
 __device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
 }
 
 // sample index of training row i in epoch permutation (a odd/coprime, c offset)
@@ -148,12 +167,21 @@ struct FwdArgs {
     float *y;            // [n][16] output layer
 };
 
-// Stage one fused layer (rows x row-stride bf16, a multiple of 16 bytes) into LDS.
+// Stage one fused layer (rows x row-stride bf16, a multiple of 16 bytes) into LDS with
+// global_load_lds_dwordx4: each lane's 16 bytes go straight to LDS base + 16 lane, without
+// passing through registers; one 1 KB chunk per wave and instruction.
 __device__ __forceinline__ void stage(unsigned char *lds, const bf16_t *src, int bytes)
 {
     const uint4 *s = reinterpret_cast<const uint4 *>(src);
-    uint4 *d = reinterpret_cast<uint4 *>(lds);
-    for (int i = threadIdx.x; i < bytes / 16; i += FWD_THREADS) d[i] = s[i];
+    const int n16 = bytes / 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = wave; c * 64 < n16; c += FWD_WAVES) {
+        const int i = c * 64 + lane;
+        if (i < n16)
+            __builtin_amdgcn_global_load_lds((const void *)(s + i),
+                                             (__attribute__((address_space(3))) void *)(lds + c * 1024), 16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed (the caller's barrier does the rest)
 }
 
 __device__ __forceinline__ bf16x8 lds_frag(const unsigned char *lds, int row, int rowlen, int slot)
@@ -161,59 +189,83 @@ __device__ __forceinline__ bf16x8 lds_frag(const unsigned char *lds, int row, in
     return *reinterpret_cast<const bf16x8 *>(lds + ((size_t)row * rowlen + slot) * 2);
 }
 
+// Bias-initialised accumulator of output block ob: lane half h holds rows 8q + 4h + (0..3);
+// only the first nq row groups exist (the last layer has 16 bias entries, nq = 2).
+__device__ __forceinline__ f32x16 bias_block(const float *bias, int ob, int h, int nq = 4)
+{
+    f32x16 c;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const f32x4 b = (q < nq) ? *reinterpret_cast<const f32x4 *>(bias + 32 * ob + 8 * q + 4 * h) : f32x4{};
+        c[4 * q + 0] = b[0];
+        c[4 * q + 1] = b[1];
+        c[4 * q + 2] = b[2];
+        c[4 * q + 3] = b[3];
+    }
+    return c;
+}
+
+// Training saves of one 32-feature block of layer l: pre-activations z (FP32) and the
+// packed bf16 activations p (8 pairs), in natural feature order [cell][256].
+__device__ __forceinline__ void save_block(const FwdArgs &a, int l, int64_t cell, int ob, int h,
+                                           const f32x16 &z, const unsigned *p)
+{
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int64_t off = cell * HID + 32 * ob + 8 * q + 4 * h;
+        *reinterpret_cast<f32x4 *>(a.z[l] + off) = f32x4{z[4 * q], z[4 * q + 1], z[4 * q + 2], z[4 * q + 3]};
+        *reinterpret_cast<uint2 *>(a.h[l] + off) = make_uint2(p[2 * q], p[2 * q + 1]);
+    }
+}
 template <bool TRAIN>
 __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
-    const int g = lane >> 4;         // 0..3: k-slot group (B operand) / row group (C)
-    const int col = lane & 15;       // cell within a 16-cell column block
+    const int h = lane >> 5;         // lane half: K slots 8h..8h+7 (A, B); rows 8q + 4h.. (C)
+    const int col = lane & 31;       // cell within the wave's 32-cell block (B, C); A row
     const int64_t ntiles = (a.n + TILE_CELLS - 1) / TILE_CELLS;
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        bf16x8 act[8][2];            // [k-block][column block]
+        bf16x8 act[16];              // B operand: one bf16x8 per 16-deep K block
 #pragma unroll
-        for (int kb = 0; kb < 8; kb++) act[kb][0] = act[kb][1] = bf16x8{};
-        int64_t cell[2];
-        bool live[2];
-        uint8_t flag[2] = {0, 0};
-        // ---- inputs -> scaled bf16 B operand of layer 0 (slot 8g + j = feature 8g + j)
-#pragma unroll
-        for (int c = 0; c < 2; c++) {
-            cell[c] = tile * TILE_CELLS + wave * CELLS_PER_WAVE + c * 16 + col;
-            live[c] = cell[c] < a.n;
+        for (int kb = 0; kb < 16; kb++) act[kb] = bf16x8{};
+        const int64_t cell = tile * TILE_CELLS + wave * CELLS_PER_WAVE + col;
+        const bool live = cell < a.n;
+        uint8_t flag = 0;
+        // ---- inputs -> scaled bf16 B operand of layer 0 (half 0: features 0..7, half 1: 8, 9)
+        {
             float xs[8];
 #pragma unroll
             for (int j = 0; j < 8; j++) xs[j] = 0.0f;
-            if (live[c] && g < 2) {
+            if (live) {
                 double raw[NIN];
                 if (TRAIN) {
-                    const int64_t sidx = perm_index(a.row0 + cell[c], a.pa, a.pc, a.nx);
+                    const int64_t sidx = perm_index(a.row0 + cell, a.pa, a.pc, a.nx);
 #pragma unroll
                     for (int f = 0; f < NIN; f++) raw[f] = (double)a.X[(int64_t)f * a.nx + sidx];
                 } else {
-                    raw[0] = a.P[cell[c]];
-                    raw[1] = a.T[cell[c]];
+                    raw[0] = a.P[cell];
+                    raw[1] = a.T[cell];
 #pragma unroll
-                    for (int f = 0; f < NIN - 2; f++) raw[2 + f] = a.Y[(int64_t)f * a.n + cell[c]];
+                    for (int f = 0; f < NIN - 2; f++) raw[2 + f] = a.Y[(int64_t)f * a.n + cell];
                 }
-                // lane group g = 0 carries features 0..7, g = 1 features 8, 9 (then zeros)
-                if (g == 0) {
+                if (h == 0) {
 #pragma unroll
                     for (int j = 0; j < 8; j++) xs[j] = (float)((raw[j] - a.in_lo[j]) * a.in_inv[j]);
                 } else {
 #pragma unroll
                     for (int j = 0; j < NIN - 8; j++) xs[j] = (float)((raw[8 + j] - a.in_lo[8 + j]) * a.in_inv[8 + j]);
                 }
-                if (!TRAIN && g == 0) {
+                if (!TRAIN && h == 0) {
                     // training box (the hull) and physical sanity of the whole cell
                     bool out = false, bad = !(raw[0] > 0.0) || !(raw[1] > 0.0);
                     double sy = 0.0;
 #pragma unroll
                     for (int f = 0; f < NIN; f++) {
-                        const double s = (raw[f] - a.in_lo[f]) * a.in_inv[f];
-                        out |= !(s >= -1e-9 && s <= 1.0 + 1e-9);
+                        const double sc = (raw[f] - a.in_lo[f]) * a.in_inv[f];
+                        out |= !(sc >= -1e-9 && sc <= 1.0 + 1e-9);
                     }
 #pragma unroll
                     for (int f = 2; f < NIN; f++) {
@@ -221,119 +273,138 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
                         sy += raw[f];
                     }
                     bad |= !(fabs(sy - 1.0) <= 1e-6);
-                    flag[c] = (out || bad) ? 1 : 0;
+                    flag = (out || bad) ? 1 : 0;
                 }
             }
             unsigned p[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) p[j] = pack_bf16x2(xs[2 * j], xs[2 * j + 1]);
-            act[0][c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<uint4 *>(p));
-            if (TRAIN && live[c]) *reinterpret_cast<uint4 *>(a.h0 + cell[c] * IN_PAD + 8 * g) = *reinterpret_cast<uint4 *>(p);
+            act[0] = __builtin_bit_cast(bf16x8, *reinterpret_cast<uint4 *>(p));
+            if (TRAIN && live) {
+                // saved inputs keep IN_PAD columns; 16..31 stay zero from allocation
+                *reinterpret_cast<uint4 *>(a.h0 + cell * IN_PAD + 8 * h) = *reinterpret_cast<uint4 *>(p);
+            }
         }
 
-        // ---- layers 0..3 (GELU) and 4 (linear output)
+        // ---- hidden layers 0..3 (GELU)
 #pragma unroll 1
-        for (int l = 0; l < NL; l++) {
+        for (int l = 0; l < NL - 1; l++) {
             __syncthreads();   // previous layer done with the LDS buffer
-            const int rows = lout(l), rowlen = lrow(l);
-            stage(lds, a.Wf + kLay::f(l), rows * rowlen * 2);
+            const int rowlen = lrow(l);
+            stage(lds, a.Wf + kLay::f(l), frows(l) * rowlen * 2);
             __syncthreads();
             const float *bias = a.bias + kLay::b(l);
-            const int nkb = (l == 0) ? 1 : 8;
-            if (l < NL - 1) {
-                bf16x8 nxt[8][2];
+            bf16x8 nxt[16];
+            if (l == 0) {
+                // one 16-deep K block: eight single MFMAs, then GELU
 #pragma unroll
-                for (int obp = 0; obp < 8; obp++) {
-                    f32x4 acc[2][2];
+                for (int ob = 0; ob < 8; ob++) {
+                    const bf16x8 a0 = lds_frag(lds, ob * 32 + col, rowlen, 8 * h);
+                    const f32x16 z = mfma32(a0, act[0], bias_block(bias, ob, h));
+                    unsigned p[8];
 #pragma unroll
-                    for (int h = 0; h < 2; h++) {
-                        const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + (2 * obp + h) * 16 + 4 * g);
-                        acc[h][0] = bv;
-                        acc[h][1] = bv;
-                    }
-#pragma unroll
-                    for (int kb = 0; kb < 8; kb++) {
-                        if (kb < nkb) {
-                            const bf16x8 a0 = lds_frag(lds, (2 * obp) * 16 + col, rowlen, kb * 32 + 8 * g);
-                            const bf16x8 a1 = lds_frag(lds, (2 * obp + 1) * 16 + col, rowlen, kb * 32 + 8 * g);
-#pragma unroll
-                            for (int c = 0; c < 2; c++) {
-                                acc[0][c] = mfma16(a0, act[kb][c], acc[0][c]);
-                                acc[1][c] = mfma16(a1, act[kb][c], acc[1][c]);
-                            }
-                        }
-                    }
-#pragma unroll
-                    for (int c = 0; c < 2; c++) {
-                        unsigned p[4];
-#pragma unroll
-                        for (int h = 0; h < 2; h++) {
-                            const f32x4 z = acc[h][c];
-                            const float g0 = gelu_f(z[0]), g1 = gelu_f(z[1]), g2 = gelu_f(z[2]), g3 = gelu_f(z[3]);
-                            p[2 * h] = pack_bf16x2(g0, g1);
-                            p[2 * h + 1] = pack_bf16x2(g2, g3);
-                            if (TRAIN && live[c]) {
-                                const int64_t off = cell[c] * HID + (2 * obp + h) * 16 + 4 * g;
-                                *reinterpret_cast<f32x4 *>(a.z[l] + off) = z;
-                                *reinterpret_cast<uint2 *>(a.h[l] + off) = make_uint2(p[2 * h], p[2 * h + 1]);
-                            }
-                        }
-                        nxt[obp][c] = __builtin_bit_cast(bf16x8, *reinterpret_cast<uint4 *>(p));
-                    }
-                }
-#pragma unroll
-                for (int kb = 0; kb < 8; kb++) {
-                    act[kb][0] = nxt[kb][0];
-                    act[kb][1] = nxt[kb][1];
+                    for (int q = 0; q < 8; q++) p[q] = pack_bf16x2(gelu_f(z[2 * q]), gelu_f(z[2 * q + 1]));
+                    nxt[2 * ob] = __builtin_bit_cast(bf16x8, make_uint4(p[0], p[1], p[2], p[3]));
+                    nxt[2 * ob + 1] = __builtin_bit_cast(bf16x8, make_uint4(p[4], p[5], p[6], p[7]));
+                    if (TRAIN && live) save_block(a, 0, cell, ob, h, z, p);
                 }
             } else {
-                f32x4 acc[2];
-                const f32x4 bv = *reinterpret_cast<const f32x4 *>(bias + 4 * g);
-                acc[0] = bv;
-                acc[1] = bv;
+                // One 32-row output block per step; the GELU of block ob - 1 is interleaved
+                // with the matrix-core work of block ob (one value per K block), so that the
+                // vector and matrix units of a SIMD work at the same time.
+                f32x16 pz = {};
 #pragma unroll
-                for (int kb = 0; kb < 8; kb++) {
-                    const bf16x8 a0 = lds_frag(lds, col, rowlen, kb * 32 + 8 * g);
-                    acc[0] = mfma16(a0, act[kb][0], acc[0]);
-                    acc[1] = mfma16(a0, act[kb][1], acc[1]);
+                for (int ob = 0; ob <= 8; ob++) {
+                    f32x16 acc = {};
+                    bf16x8 a0 = {};
+                    unsigned pg[8];
+                    float gv[16];
+                    if (ob < 8) {
+                        acc = bias_block(bias, ob, h);
+                        a0 = lds_frag(lds, ob * 32 + col, rowlen, 8 * h);
+                    }
+#pragma unroll
+                    for (int kb = 0; kb < 16; kb++) {
+                        if (ob < 8) {
+                            const bf16x8 n0 = (kb + 1 < 16) ? lds_frag(lds, ob * 32 + col, rowlen, (kb + 1) * 16 + 8 * h) : a0;
+                            acc = mfma32(a0, act[kb], acc);
+                            a0 = n0;
+                        }
+                        if (ob > 0) {
+                            gv[kb] = gelu_f(pz[kb]);
+                            if (kb & 1) pg[kb >> 1] = pack_bf16x2(gv[kb - 1], gv[kb]);
+                        }
+                        if (ob > 0 && ob < 8) {
+                            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
+                            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
+                            __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);   // VALU
+                        } else {
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    }
+                    if (ob > 0) {
+                        const int pb = ob - 1;
+                        nxt[2 * pb] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
+                        nxt[2 * pb + 1] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
+                        if (TRAIN && live) save_block(a, l, cell, pb, h, pz, pg);
+                    }
+                    if (ob < 8) pz = acc;
                 }
+            }
 #pragma unroll
-                for (int c = 0; c < 2; c++) {
-                    if (!live[c]) continue;
+            for (int kb = 0; kb < 16; kb++) act[kb] = nxt[kb];
+        }
+        // ---- output layer (linear), outside the loop so that its double-precision
+        // epilogue does not share the register budget of the hidden layers
+        {
+            constexpr int l = NL - 1;
+            __syncthreads();
+            const int rowlen = lrow(l);
+            stage(lds, a.Wf + kLay::f(l), frows(l) * rowlen * 2);
+            __syncthreads();
+            const float *bias = a.bias + kLay::b(l);
+            {
+                f32x16 acc = bias_block(bias, 0, h, OUT_PAD / 8);   // rows 16..31: padding
+#pragma unroll
+                for (int kb = 0; kb < 16; kb++) {
+                    const bf16x8 a0 = lds_frag(lds, col, rowlen, kb * 16 + 8 * h);
+                    acc = mfma32(a0, act[kb], acc);
+                }
+                if (live) {
                     if (TRAIN) {
-                        *reinterpret_cast<f32x4 *>(a.y + cell[c] * OUT_PAD + 4 * g) = acc[c];
-                    } else if (g == 0) {
-                        // outputs 4g + j: lanes g = 0 hold rho, h, cp, c; g = 1 hold mu, lambda
-                        const f32x4 y = acc[c];
-                        if (a.orho) a.orho[cell[c]] = exp(a.out_lo[0] + (double)y[0] * a.out_rng[0]);
-                        if (a.oh) a.oh[cell[c]] = a.out_lo[1] + (double)y[1] * a.out_rng[1];
-                        if (a.ocp) a.ocp[cell[c]] = exp(a.out_lo[2] + (double)y[2] * a.out_rng[2]);
-                        if (a.oc) a.oc[cell[c]] = a.out_lo[3] + (double)y[3] * a.out_rng[3];
-                    } else if (g == 1) {
-                        const f32x4 y = acc[c];
-                        if (a.omu) a.omu[cell[c]] = exp(a.out_lo[4] + (double)y[0] * a.out_rng[4]);
-                        if (a.olam) a.olam[cell[c]] = exp(a.out_lo[5] + (double)y[1] * a.out_rng[5]);
+                        // rows 8q + 4h + (0..3) for q = 0, 1 are the 16 saved outputs
+#pragma unroll
+                        for (int q = 0; q < 2; q++)
+                            *reinterpret_cast<f32x4 *>(a.y + cell * OUT_PAD + 8 * q + 4 * h) =
+                                f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+                    } else if (h == 0) {
+                        // rows 0..3: rho, h, cp, c
+                        if (a.orho) a.orho[cell] = exp(a.out_lo[0] + (double)acc[0] * a.out_rng[0]);
+                        if (a.oh) a.oh[cell] = a.out_lo[1] + (double)acc[1] * a.out_rng[1];
+                        if (a.ocp) a.ocp[cell] = exp(a.out_lo[2] + (double)acc[2] * a.out_rng[2]);
+                        if (a.oc) a.oc[cell] = a.out_lo[3] + (double)acc[3] * a.out_rng[3];
+                    } else {
+                        // rows 4, 5: mu, lambda
+                        if (a.omu) a.omu[cell] = exp(a.out_lo[4] + (double)acc[0] * a.out_rng[4]);
+                        if (a.olam) a.olam[cell] = exp(a.out_lo[5] + (double)acc[1] * a.out_rng[5]);
                     }
                 }
             }
         }
         if (!TRAIN) {
-            // status and fallback list (lanes g == 0 own their cell)
-#pragma unroll
-            for (int c = 0; c < 2; c++) {
-                const bool mine = live[c] && g == 0;
-                const bool f = mine && flag[c];
-                if (mine && a.status) a.status[cell[c]] = f ? PROPS_ST_OUT_OF_HULL : 0;
-                if (a.fb_idx) {
-                    const unsigned long long bal = __ballot(f);
-                    const int cnt = __popcll(bal);
-                    int base = 0;
-                    if (cnt) {
-                        const int first = __builtin_ctzll(bal);
-                        if (lane == first) base = atomicAdd(a.fb_count, cnt);
-                        base = __shfl(base, first);
-                        if (f) a.fb_idx[base + __popcll(bal & ((1ull << lane) - 1))] = (int)cell[c];
-                    }
+            // status and fallback list (lanes of half 0 own their cell)
+            const bool mine = live && h == 0;
+            const bool f = mine && flag;
+            if (mine && a.status) a.status[cell] = f ? PROPS_ST_OUT_OF_HULL : 0;
+            if (a.fb_idx) {
+                const unsigned long long bal = __ballot(f);
+                const int cnt = __popcll(bal);
+                int base = 0;
+                if (cnt) {
+                    const int first = __builtin_ctzll(bal);
+                    if (lane == first) base = atomicAdd(a.fb_count, cnt);
+                    base = __shfl(base, first);
+                    if (f) a.fb_idx[base + __popcll(bal & ((1ull << lane) - 1))] = (int)cell;
                 }
             }
         }
@@ -527,15 +598,10 @@ __global__ void convert_weights_kernel(const float *master, bf16_t *nat, bf16_t 
         const float wv = master[kLay::w(l) + e];
         const bf16_t b = to_bf16(wv);
         nat[kLay::nat(l) + e] = b;
-        int slot;
-        if (l == 0) {
-            slot = i;
-        } else {
-            // input i = 32 kb + r sits in k-slot 8 g + j of block kb, where the lane's
-            // accumulator rows 4g..4g+3 (r < 16) fill j = 0..3 and rows 16 + 4g.. fill j = 4..7
-            const int kb = i >> 5, r = i & 31;
-            slot = (r < 16) ? kb * 32 + 8 * (r >> 2) + (r & 3) : kb * 32 + 8 * ((r - 16) >> 2) + 4 + (r & 3);
-        }
+        // layer 0 keeps the natural input order in its one 16-deep K block (inputs >= 16
+        // are padding); later layers take the permutation of the accumulator layout
+        if (l == 0 && i >= FK0) continue;
+        const int slot = (l == 0) ? i : kslot(i);
         fused[kLay::f(l) + (int64_t)o * rowlen + slot] = b;
     }
 }
@@ -678,6 +744,8 @@ static int ensure_train_scratch(props_dnn_s *d)
         (rc = dalloc(&d->part, (size_t)SPLITK * HID * HID)) || (rc = dalloc(&d->lpart, (size_t)B / 256 + 64)) ||
         (rc = dalloc(&d->cpart, (size_t)256 * HID)))
         return rc;
+    // the forward writes input columns 0..15 of the saved inputs; 16..31 stay zero
+    PROPS_HIP_TRY(hipMemset(d->h0, 0, sizeof(bf16_t) * B * IN_PAD));
     for (int l = 0; l < 4; l++)
         if ((rc = dalloc(&d->hs[l], B * HID)) || (rc = dalloc(&d->zs[l], B * HID))) return rc;
     return PROPS_OK;
@@ -687,8 +755,8 @@ static int fwd_grid(int64_t n)
 {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) {
-        hipDeviceProp_t p;
-        if (hipGetDeviceProperties(&p, dev) == hipSuccess) cus = p.multiProcessorCount;
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
     }
     const int64_t tiles = (n + TILE_CELLS - 1) / TILE_CELLS;
     return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
