@@ -49,7 +49,7 @@ constexpr int FWD_THREADS = FWD_WAVES * 64;
 constexpr int CELLS_PER_WAVE = 32;
 constexpr int TILE_CELLS = FWD_WAVES * CELLS_PER_WAVE;   // 256
 constexpr int MAX_BATCH = 65536;
-constexpr int SPLITK = 32;
+constexpr int SPLITW = 64;     // batch splits of the weight-gradient GEMMs
 
 // padded (out, in) of each weight layer and its offsets in the FP32 master vector
 __host__ __device__ constexpr int lout(int l) { return l == 0 ? HID : (l == NL - 1 ? OUT_PAD : HID); }
@@ -550,27 +550,68 @@ __global__ void reduce_partials_kernel(const float *part, int S, int64_t stride,
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     float s = 0.f;
-    for (int k = 0; k < S; k++) s += part[k * stride + i];
+    int k = 0;
+    for (; k + 8 <= S; k += 8) {   // eight partials in flight, summed in order
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) v[j] = part[(k + j) * stride + i];
+#pragma unroll
+        for (int j = 0; j < 8; j++) s += v[j];
+    }
+    for (; k < S; k++) s += part[k * stride + i];
     dst[i] = s;
 }
 
-// column sums of a bf16 [n][ncol] matrix: block p sums rows [p*rows, ...) into part[p][col]
-__global__ void colsum_partial_kernel(const bf16_t *dz, int n, int ncol, int rows, float *part)
+// Column sums of a bf16 [n][ncol] matrix (ncol a multiple of 8, at most 256): block p sums
+// rows [p*rows, ...) into part[p][col].  Thread (g, c8) adds the 8 columns 8 c8.. of rows
+// r0 + g, r0 + g + G, ... with 16-byte loads; the G row groups are then combined in a fixed
+// order, so the result is deterministic.
+__global__ __launch_bounds__(256) void colsum_partial_kernel(const bf16_t *dz, int n, int ncol, int rows, float *part)
 {
-    const int c = threadIdx.x;
-    if (c >= ncol) return;
+    __shared__ float red[256 * 8];
+    const int cg = ncol / 8;                  // 16-byte column groups per row
+    const int G = 256 / cg;                   // row groups per block
+    const int g = threadIdx.x / cg, c8 = threadIdx.x % cg;
     const int r0 = blockIdx.x * rows, r1 = min(n, r0 + rows);
-    float s = 0.f;
-    for (int r = r0; r < r1; r++) s += bf16_to_f(dz[(int64_t)r * ncol + c]);
-    part[blockIdx.x * ncol + c] = s;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (g < G) {
+        for (int r = r0 + g; r < r1; r += G) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(dz + (int64_t)r * ncol + 8 * c8);
+            const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                acc[2 * j] += __builtin_bit_cast(float, w[j] << 16);
+                acc[2 * j + 1] += __builtin_bit_cast(float, w[j] & 0xffff0000u);
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; j++) red[threadIdx.x * 8 + j] = acc[j];
+    __syncthreads();
+    if (threadIdx.x < ncol) {
+        const int c = threadIdx.x;
+        float s = 0.f;
+        for (int q = 0; q < G; q++) s += red[(q * cg + c / 8) * 8 + (c % 8)];
+        part[blockIdx.x * ncol + c] = s;
+    }
 }
 
-__global__ void sum_rows_kernel(const float *part, int P, int ncol, float *dst)
+// dst[c] = sum_p part[p][c] in the order p = 0, 1, ... (one thread per column, eight
+// partial rows loaded at a time)
+__global__ __launch_bounds__(256) void sum_rows_kernel(const float *part, int P, int ncol, float *dst)
 {
     const int c = threadIdx.x;
     if (c >= ncol) return;
     float s = 0.f;
-    for (int p = 0; p < P; p++) s += part[p * ncol + c];
+    int p = 0;
+    for (; p + 8 <= P; p += 8) {
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) v[j] = part[(p + j) * ncol + c];
+#pragma unroll
+        for (int j = 0; j < 8; j++) s += v[j];
+    }
+    for (; p < P; p++) s += part[p * ncol + c];
     dst[c] = s;
 }
 
@@ -587,7 +628,8 @@ __global__ void adam_kernel(float *w, const float *gr, float *m, float *v, int64
     w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// FP32 master -> bf16 natural [out][in] and fused (row-padded, k-permuted) layouts.
+// FP32 master -> bf16 transposed [in][out] (the B operand of dz W, contiguous along its K
+// = out) and fused (row-padded, k-permuted) layouts.
 __global__ void convert_weights_kernel(const float *master, bf16_t *nat, bf16_t *fused)
 {
     const int l = blockIdx.y;
@@ -597,7 +639,7 @@ __global__ void convert_weights_kernel(const float *master, bf16_t *nat, bf16_t 
         const int o = (int)(e / cols), i = (int)(e % cols);
         const float wv = master[kLay::w(l) + e];
         const bf16_t b = to_bf16(wv);
-        nat[kLay::nat(l) + e] = b;
+        nat[kLay::nat(l) + (int64_t)i * rows + o] = b;   // transposed: [in][out]
         // layer 0 keeps the natural input order in its one 16-deep K block (inputs >= 16
         // are padding); later layers take the permutation of the accumulator layout
         if (l == 0 && i >= FK0) continue;
@@ -741,7 +783,7 @@ static int ensure_train_scratch(props_dnn_s *d)
     const size_t B = MAX_BATCH;
     if ((rc = dalloc(&d->h0, B * IN_PAD)) || (rc = dalloc(&d->dz, B * HID)) || (rc = dalloc(&d->dz2, B * HID)) ||
         (rc = dalloc(&d->dzo, B * OUT_PAD)) || (rc = dalloc(&d->y, B * OUT_PAD)) ||
-        (rc = dalloc(&d->part, (size_t)SPLITK * HID * HID)) || (rc = dalloc(&d->lpart, (size_t)B / 256 + 64)) ||
+        (rc = dalloc(&d->part, (size_t)SPLITW * HID * HID)) || (rc = dalloc(&d->lpart, (size_t)B / 256 + 64)) ||
         (rc = dalloc(&d->cpart, (size_t)256 * HID)))
         return rc;
     // the forward writes input columns 0..15 of the saved inputs; 16..31 stay zero
@@ -775,6 +817,174 @@ static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
     const int grid = fwd_grid(a.n);
     if (train) hipLaunchKernelGGL(mlp_fwd_kernel<true>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
     else hipLaunchKernelGGL(mlp_fwd_kernel<false>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
+}
+
+// Weight gradient C_z[m][n] = sum_{k in split z} A[k][m] B[k][n], with both operands stored
+// k-major ([batch][feature] activations and output gradients), on v_mfma_f32_32x32x16_bf16,
+// K in steps of 32.  The matrix cores want each lane's eight bf16 consecutive along K, so tiles
+// are staged in LDS as bf16 pairs (k even, k odd) per column: a thread reads two k rows of
+// eight columns (two 16-byte loads), interleaves them and stores eight pair-dwords; a
+// fragment is then four 4-byte LDS reads.  Rows of 136 dwords put the two lane halves of a
+// fragment read 32 banks apart.  Double-buffered: the next step's global loads are in
+// flight during the current step's MFMAs, one barrier per step.
+// A tile of TM x TN outputs per workgroup of 4 waves arranged WAVES_M x (4 / WAVES_M), each
+// wave BM x BN blocks of 32 x 32.  Columns at or beyond M (N) read as zero and are not
+// written, so the 16-row output layer runs on a 32-row tile.
+constexpr int KW_PAD = 8;          // extra pair-dwords per LDS row
+__device__ __forceinline__ void kw_interleave(uint4 x, uint4 y, uint4 &lo, uint4 &hi)
+{
+    // x: row 2kp, y: row 2kp + 1, eight bf16 columns each -> eight (x_j, y_j) pairs
+    const unsigned xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
+    unsigned d[8];
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        d[2 * w] = (xs[w] & 0xffffu) | (ys[w] << 16);
+        d[2 * w + 1] = (xs[w] >> 16) | (ys[w] & 0xffff0000u);
+    }
+    lo = make_uint4(d[0], d[1], d[2], d[3]);
+    hi = make_uint4(d[4], d[5], d[6], d[7]);
+}
+
+template <int TM, int TN, int WAVES_M>
+__global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int lda, int M, const bf16_t *B, int ldb,
+                                                          int N, int K, int kchunk, float *C, int ldc, int64_t strideC)
+{
+    constexpr int WAVES_N = 4 / WAVES_M;
+    constexpr int BM = TM / WAVES_M / 32, BN = TN / WAVES_N / 32;
+    constexpr int CA = TM / 8, CB = TN / 8;   // 16-byte column chunks per k row
+    __shared__ __attribute__((aligned(16))) unsigned As[2][16][TM + KW_PAD];
+    __shared__ __attribute__((aligned(16))) unsigned Bs[2][16][TN + KW_PAD];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w / WAVES_N, wn = w % WAVES_N;
+    const int h = lane >> 5, r = lane & 31;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int kbeg = blockIdx.z * kchunk;
+    const int kend = min(K, kbeg + kchunk);
+    // loader work items: (pair row kp, 16-byte column chunk) for A then B
+    constexpr int NA = 16 * CA, NB = 16 * CB;
+    constexpr int PER = (NA + NB + 255) / 256;
+    auto item = [&](int q, bool &isA, int &kp, int &c8) {
+        isA = q < NA;
+        const int qq = isA ? q : q - NA;
+        const int cc = isA ? CA : CB;
+        kp = qq / cc;
+        c8 = qq % cc;
+    };
+    auto load = [&](int k0, uint4 (&rx)[PER][2]) {
+#pragma unroll
+        for (int p = 0; p < PER; p++) {
+            const int q = t + 256 * p;
+            rx[p][0] = rx[p][1] = make_uint4(0, 0, 0, 0);
+            if (q < NA + NB) {
+                bool isA;
+                int kp, c8;
+                item(q, isA, kp, c8);
+                const int col = (isA ? m0 : n0) + 8 * c8;
+                const int lim = isA ? M : N;
+                const bf16_t *src = isA ? A : B;
+                const int ld = isA ? lda : ldb;
+#pragma unroll
+                for (int e = 0; e < 2; e++) {
+                    const int k = k0 + 2 * kp + e;
+                    if (k < kend && col < lim) rx[p][e] = *reinterpret_cast<const uint4 *>(src + (int64_t)k * ld + col);
+                }
+            }
+        }
+    };
+    auto store = [&](int buf, const uint4 (&rx)[PER][2]) {
+#pragma unroll
+        for (int p = 0; p < PER; p++) {
+            const int q = t + 256 * p;
+            if (q < NA + NB) {
+                bool isA;
+                int kp, c8;
+                item(q, isA, kp, c8);
+                uint4 lo, hi;
+                kw_interleave(rx[p][0], rx[p][1], lo, hi);
+                unsigned *dst = isA ? &As[buf][kp][8 * c8] : &Bs[buf][kp][8 * c8];
+                *reinterpret_cast<uint4 *>(dst) = lo;
+                *reinterpret_cast<uint4 *>(dst + 4) = hi;
+            }
+        }
+    };
+    f32x16 acc[BM][BN];
+#pragma unroll
+    for (int i = 0; i < BM; i++)
+#pragma unroll
+        for (int j = 0; j < BN; j++) acc[i][j] = f32x16{};
+    uint4 rx[PER][2];
+    int buf = 0;
+    if (kbeg < kend) {
+        load(kbeg, rx);
+        store(0, rx);
+    }
+    __syncthreads();
+    for (int k0 = kbeg; k0 < kend; k0 += 32) {
+        const bool more = k0 + 32 < kend;
+        if (more) load(k0 + 32, rx);
+#pragma unroll
+        for (int kb = 0; kb < 2; kb++) {
+            bf16x8 af[BM], bfr[BN];
+#pragma unroll
+            for (int i = 0; i < BM; i++) {
+                const int col = (wm * BM + i) * 32 + r;
+                unsigned p[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) p[j] = As[buf][8 * kb + 4 * h + j][col];
+                af[i] = __builtin_bit_cast(bf16x8, make_uint4(p[0], p[1], p[2], p[3]));
+            }
+#pragma unroll
+            for (int i = 0; i < BN; i++) {
+                const int col = (wn * BN + i) * 32 + r;
+                unsigned p[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) p[j] = Bs[buf][8 * kb + 4 * h + j][col];
+                bfr[i] = __builtin_bit_cast(bf16x8, make_uint4(p[0], p[1], p[2], p[3]));
+            }
+#pragma unroll
+            for (int i = 0; i < BM; i++)
+#pragma unroll
+                for (int j = 0; j < BN; j++) acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
+        }
+        if (more) store(buf ^ 1, rx);
+        __syncthreads();
+        buf ^= 1;
+    }
+    // C layout of the 32 x 32 blocks: column = lane % 32 (n), rows 8q + 4h + (0..3) (m)
+    float *Cz = C + blockIdx.z * strideC;
+#pragma unroll
+    for (int i = 0; i < BM; i++)
+#pragma unroll
+        for (int j = 0; j < BN; j++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int m = m0 + (wm * BM + i) * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+                const int n = n0 + (wn * BN + j) * 32 + r;
+                if (m < M && n < N) Cz[(int64_t)m * ldc + n] = acc[i][j][v];
+            }
+}
+
+// dW = dz^T h for the layer shapes of the network: (256, 256) on 128 x 128 tiles, (256, 32)
+// (input layer) on 128 x 32 tiles, (16, 256) (output layer) on 32 x 128 tiles.
+static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float *part, int &splits, hipStream_t s)
+{
+    const int kchunk = ((n + SPLITW - 1) / SPLITW + 31) / 32 * 32;
+    splits = (n + kchunk - 1) / kchunk;
+    const int64_t stride = (int64_t)O * I;
+    if (O % 128 == 0 && I % 128 == 0) {
+        hipLaunchKernelGGL((gemm_wgrad_kernel<128, 128, 2>), dim3(I / 128, O / 128, splits), dim3(256), 0, s,
+                           dz, O, O, hp, I, I, n, kchunk, part, I, stride);
+    } else if (O % 128 == 0 && I == 32) {
+        hipLaunchKernelGGL((gemm_wgrad_kernel<128, 32, 4>), dim3(1, O / 128, splits), dim3(256), 0, s,
+                           dz, O, O, hp, I, I, n, kchunk, part, I, stride);
+    } else if (O <= 32 && O % 8 == 0 && I % 128 == 0) {
+        hipLaunchKernelGGL((gemm_wgrad_kernel<32, 128, 1>), dim3(I / 128, 1, splits), dim3(256), 0, s,
+                           dz, O, O, hp, I, I, n, kchunk, part, I, stride);
+    } else {
+        return fail(PROPS_EINVAL, "wgrad: unsupported layer shape %d x %d", O, I);
+    }
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
 }
@@ -822,13 +1032,8 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
         const int O = lout(l), I = lin(l);
         const bf16_t *hprev = (l == 0) ? d->h0 : d->hs[l - 1];
         // dW = dz^T h  (M = O, N = I, K = n), split over the batch
-        const int kchunk = ((n + SPLITK - 1) / SPLITK + 31) / 32 * 32;
-        const int splits = (n + kchunk - 1) / kchunk;
-        GemmArgs gw{};
-        gw.M = O, gw.N = I, gw.K = n, gw.kchunk = kchunk;
-        gw.A = dzl, gw.lda = O, gw.B = hprev, gw.ldb = I;
-        gw.C = d->part, gw.ldc = I, gw.strideC = (int64_t)O * I;
-        if ((rc = gemm<true, false, EPI_F32>(gw, splits, s))) return rc;
+        int splits = 0;
+        if ((rc = wgrad(dzl, O, hprev, I, n, d->part, splits, s))) return rc;
         const int64_t cnt = (int64_t)O * I;
         hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                            d->part, splits, (int64_t)O * I, cnt, d->grad + kLay::w(l));
@@ -842,9 +1047,9 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
             bf16_t *out = (dzl == d->dz) ? d->dz2 : d->dz;
             GemmArgs gh{};
             gh.M = n, gh.N = I, gh.K = O, gh.kchunk = O;
-            gh.A = dzl, gh.lda = O, gh.B = d->nat + kLay::nat(l), gh.ldb = I;
+            gh.A = dzl, gh.lda = O, gh.B = d->nat + kLay::nat(l), gh.ldb = O;
             gh.Cb = out, gh.ldc = I, gh.Z = d->zs[l - 1], gh.ldz = HID;
-            if ((rc = gemm<false, false, EPI_GELU_BWD>(gh, 1, s))) return rc;
+            if ((rc = gemm<false, true, EPI_GELU_BWD>(gh, 1, s))) return rc;
             dzl = out;
         }
     }
