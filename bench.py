@@ -324,6 +324,91 @@ def dnn_section(props, synth, mech, sp, epochs, n_train, res, reps=5):
     }
 
 
+def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps=5):
+    """The paper's own surrogate inputs (Section 4.1): (h, P, Box-Cox Bilger Z) -> T, rho, mu,
+    psi, thermal diffusivity and h_CH4/RT, one network with six outputs, trained on PR labels
+    and compared with the (h, P, Y) Newton path on a res^3 field."""
+    import torch
+    dev = torch.device("cuda:0")
+    ns = len(sp)
+    keys = ("rho", "T", "mu", "hRT0", "psi", "alpha")   # outputs 0, 2, 4, 5 trained on log
+    # training set: jittered flame states, labels from the FP64 (P, T, Y) path
+    P, T, Y = synth.training_states(n_train, seed=13)
+    Pd, Td, Yd = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (P, T, Y))
+    del P, T, Y
+    lab = {k: torch.empty(n_train, dtype=torch.float64, device=dev) for k in ("rho", "mu", "psi", "alpha", "h")}
+    hrt = torch.empty((ns, n_train), dtype=torch.float64, device=dev)
+    st = torch.empty(n_train, dtype=torch.uint8, device=dev)
+    props.pr(mech, props.PTY, props.FP64, {"P": Pd, "T": Td, "Y": Yd}, dict(lab, hRT=hrt), n_train, status=st)
+    X = torch.empty((10, n_train), dtype=torch.float64, device=dev)
+    props.features_hpz(sp, 0, 1, lam, lab["h"], Pd, Yd, n_train, X)
+    L = torch.stack([lab["rho"], Td, lab["mu"], hrt[0], lab["psi"], lab["alpha"]]).float().contiguous()
+    Xf = X.float().contiguous()
+    bad_labels = int((st != 0).sum())
+    del X, lab, hrt, Pd, Td, Yd
+    net = props.Network(seed=2025)
+    log(f"(h,P,Z) surrogate: training {epochs} epochs on {n_train} samples")
+    rep, losses = net.train(Xf, L, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=7)
+    del Xf, L
+    # inference field and the (h, P, Y) reference
+    Pf, Tf, Yf = synth.flame_field(res, seed=4)
+    n = Tf.size
+    Pd = torch.from_numpy(Pf).to(dev)
+    Yd = torch.from_numpy(np.ascontiguousarray(Yf)).to(dev)
+    Tg = torch.from_numpy(synth.temperature_guess(Tf)).to(dev)
+    del Pf, Yf
+    h = torch.empty(n, dtype=torch.float64, device=dev)
+    props.pr(mech, props.PTY, props.FP64, {"P": Pd, "T": torch.from_numpy(Tf).to(dev), "Y": Yd}, {"h": h}, n)
+    ref = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("T", "rho", "mu", "psi", "alpha")}
+    ref["hRT"] = torch.empty((ns, n), dtype=torch.float64, device=dev)
+    hin = {"h": h, "P": Pd, "Y": Yd, "T_guess": Tg}
+    X = torch.empty((10, n), dtype=torch.float64, device=dev)
+    Yo = torch.empty((6, n), dtype=torch.float64, device=dev)
+
+    def timeit(fn, k=reps):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(k):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k
+
+    def surrogate():
+        props.features_hpz(sp, 0, 1, lam, h, Pd, Yd, n, X)
+        net.features(X, Yo, n)
+
+    ms_dnn = timeit(surrogate)
+    ms_hpy64 = timeit(lambda: props.pr(mech, props.HPY, props.FP64, hin, ref, n))
+    out32 = {k: torch.empty_like(v) for k, v in ref.items()}
+    ms_hpy32 = timeit(lambda: props.pr(mech, props.HPY, props.MIXED, hin, out32, n))
+    props.pr(mech, props.HPY, props.FP64, hin, ref, n)
+    surrogate()
+    torch.cuda.synchronize()
+    refs = {"rho": ref["rho"], "T": ref["T"], "mu": ref["mu"], "hRT0": ref["hRT"][0], "psi": ref["psi"],
+            "alpha": ref["alpha"]}
+    err = {}
+    for j, k in enumerate(keys):
+        if k in ("T", "hRT0"):
+            scale = refs[k].abs() + (1.0 if k == "hRT0" else 0.0)
+            d = (Yo[j] - refs[k]).abs() / scale
+            r2 = 1.0 - float(((Yo[j] - refs[k]) ** 2).sum() / ((refs[k] - refs[k].mean()) ** 2).sum())
+            err[k] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt()), "r2": r2}
+        else:
+            err[k] = _rel_stats(Yo[j], refs[k], k)
+    return {"workload": f"{res}^3 flame field ({n} cells): (h, P, Box-Cox(lambda={lam}) Bilger Z) -> "
+                        "T, rho, mu, psi, lambda/(rho cp), h_CH4/RT; one network, 6 of the paper's 17 outputs",
+            "value": n / (ms_dnn * 1e-3), "unit": "cells/s", "ms": ms_dnn,
+            "pr_hpy_fp64_cells_per_s": n / (ms_hpy64 * 1e-3), "pr_hpy_mixed_cells_per_s": n / (ms_hpy32 * 1e-3),
+            "speedup_vs_pr_hpy_fp64": ms_hpy64 / ms_dnn, "speedup_vs_pr_hpy_mixed": ms_hpy32 / ms_dnn,
+            "rel_err_vs_pr_hpy_fp64": err,
+            "train": {"samples": n_train, "epochs": epochs, "seconds": rep["seconds"],
+                      "samples_per_s": rep["samples_per_s"], "loss_first": float(losses[0]),
+                      "loss_last": float(losses[-1]), "label_flags": bad_labels}}
+
+
 def serving_section(props, synth, mech, net, n_sub=64, reqs_per_sub=50, loads=(0.5, 0.8)):
     """Concurrent subdomains with log-uniform sizes submit requests with exponential think
     times (closed loop per subdomain); half of them route to the surrogate."""
@@ -565,6 +650,10 @@ def main():
         torch.cuda.empty_cache()
         log("surrogate: labels, training, inference")
         net, rec["dnn"] = dnn_section(props, synth, mech, sp, args.dnn_epochs, args.dnn_train, args.dnn_res)
+        torch.cuda.empty_cache()
+        rec["dnn_hpz"] = dnn_hpz_section(props, synth, mech, sp, args.dnn_epochs, args.dnn_train, args.dnn_res)
+        log(f"(h,P,Z) surrogate: {rec['dnn_hpz']['value']:.3e} cells/s, "
+            f"{rec['dnn_hpz']['speedup_vs_pr_hpy_fp64']:.2f}x the FP64 (h,P,Y) path")
     if not args.no_extras and not args.no_serving:
         if net is None:
             net = props.Network(seed=77)

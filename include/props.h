@@ -180,6 +180,30 @@ int props_dnn_load(const char *path, props_dnn_t *out);
 int props_dnn(props_dnn_t net, props_mech_t fallback, const props_in *in, const props_out *out,
               int64_t n, uint8_t *status, void *hip_stream);
 
+/* Evaluate the surrogate on raw features: X is a device array [PROPS_DNN_IN][n] (feature-
+ * major, double), Y a device array [PROPS_DNN_OUT][n] that receives the six outputs in the
+ * network's target units (outputs 0, 2, 4 and 5 were trained on their logarithm and are
+ * returned through exp).  Inputs are min-max scaled by the network's input box; no hull
+ * test, status or fallback.  This is the entry for networks trained on other inputs than
+ * (P, T, Y), such as the (h, P, Z) features below.  Asynchronous on hip_stream. */
+int props_dnn_features(props_dnn_t net, const double *X, double *Y, int64_t n, void *hip_stream);
+
+/* The inputs of the paper's surrogate (Section 4.1): enthalpy, pressure and Bilger's
+ * mixture fraction of the previous iterate, the latter Box-Cox transformed (Section 4.2).
+ * Bilger's coupling function beta = 2 Y_C/W_C + Y_H/(2 W_H) - Y_O/W_O is, per species i with
+ * c_i, h_i, o_i carbon, hydrogen and oxygen atoms and molar mass W_i, beta = sum_i Y_i b_i with
+ * b_i = (2 c_i + h_i / 2 - o_i) / W_i; Z = (beta - b_ox) / (b_fuel - b_ox) for the pure
+ * species `fuel` and `oxidizer`, clamped below at 0; BC(Z) = (Z^lambda - 1) / lambda with
+ * 0 < lambda <= 1 (a power transform spreading the many small values; lambda = 0, the
+ * logarithm, is refused because Z = 0 occurs in pure oxidizer).
+ *   atoms: host [ns][3] (C, H, O per molecule); W: host [ns] kg/mol;
+ *   h, P: device [n]; Y: device [ns][n];
+ *   X: device [PROPS_DNN_IN][n] <- X[0] = h, X[1] = P, X[2] = BC(Z), X[3..] = 0.
+ * Asynchronous on hip_stream. */
+int props_features_hpz(const int *atoms, const double *W, int ns, int fuel, int oxidizer, double bc_lambda,
+                       const double *h, const double *P, const double *Y, int64_t n, double *X,
+                       void *hip_stream);
+
 /* ------------------------------------------------------------------ training */
 typedef struct {
     int epochs;          /* epochs to run in this call */

@@ -59,8 +59,11 @@ def bf16(x):
 
 # ------------------------------------------------------------------ scaling
 def scale_inputs(X, lo, hi):
-    """X: [n, 10] raw (P, T, Y_1..8); min-max to [0, 1] in float64."""
-    return (X - lo) / (hi - lo)
+    """X: [n, 10] raw (P, T, Y_1..8); min-max to [0, 1] in float64.  A feature with an
+    empty range (constant in the training data) carries no information and scales to 0."""
+    rng = np.asarray(hi, dtype=np.float64) - np.asarray(lo, dtype=np.float64)
+    safe = np.where(rng > 0, rng, 1.0)
+    return np.where(rng > 0, (X - lo) / safe, 0.0)
 
 
 def transform_outputs(Y, lo, hi):

@@ -120,6 +120,9 @@ def lib():
         L.props_dnn.argtypes = [_P, _P, ctypes.POINTER(PropsIn), ctypes.POINTER(PropsOut),
                                 ctypes.c_int64, _P, _P]
         L.props_dnn_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_float), _P]
+        L.props_dnn_features.argtypes = [_P, _P, _P, ctypes.c_int64, _P]
+        L.props_features_hpz.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                         _P, _P, _P, ctypes.c_int64, _P, _P]
         L.train_dnn.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(TrainCfg),
                                 ctypes.POINTER(TrainReport), _P]
         L.serve_create.argtypes = [ctypes.POINTER(ServeCfg), _P, _P, ctypes.POINTER(_P)]
@@ -201,6 +204,16 @@ def pr(mech, mode, prec, inputs, outputs, n, status=None, stream=None):
                          int(n), _ptr(status), _stream(stream)))
 
 
+def features_hpz(species, fuel, oxidizer, bc_lambda, h, P, Y, n, X, stream=None):
+    """props_features_hpz: species dicts give W and "atoms" {C, H, O}; h, P [n], Y [ns, n]
+    and X [10, n] are float64 device tensors."""
+    import numpy as np
+    atoms = np.ascontiguousarray([[s["atoms"][e] for e in ("C", "H", "O")] for s in species], dtype=np.int32)
+    W = np.ascontiguousarray([s["W"] for s in species], dtype=np.float64)
+    check(lib().props_features_hpz(atoms.ctypes.data, W.ctypes.data, len(species), int(fuel), int(oxidizer),
+                                   float(bc_lambda), _ptr(h), _ptr(P), _ptr(Y), int(n), _ptr(X), _stream(stream)))
+
+
 class Network:
     """props_dnn_* handle: the MLP surrogate (10 -> 4 x 256 GELU -> 6)."""
 
@@ -251,6 +264,10 @@ class Network:
         pout = PropsOut(**{k: _ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)})
         check(lib().props_dnn(self.handle, fallback.handle if fallback is not None else None,
                               ctypes.byref(pin), ctypes.byref(pout), int(n), _ptr(status), _stream(stream)))
+
+    def features(self, X, Y, n, stream=None):
+        """props_dnn_features: X [10, n] raw features, Y [6, n] outputs (float64 device tensors)."""
+        check(lib().props_dnn_features(self.handle, _ptr(X), _ptr(Y), int(n), _stream(stream)))
 
     def grad(self, X, Y, n, stream=None):
         """props_dnn_grad on device X [10, n], Y [6, n] (float32): (loss, flat gradient)."""

@@ -156,6 +156,9 @@ struct FwdArgs {
     const float *bias;   // FP32 master vector (biases read from their offsets)
     const double *in_lo, *in_inv;   // [10] input box
     const double *out_lo, *out_rng; // [6] target box
+    // ... or inference on raw feature-major inputs [10][n], outputs [6][n]
+    const double *Xd;
+    double *Yd;
     // inference outputs
     double *orho, *oh, *ocp, *oc, *omu, *olam;
     uint8_t *status;
@@ -245,6 +248,9 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
                     const int64_t sidx = perm_index(a.row0 + cell, a.pa, a.pc, a.nx);
 #pragma unroll
                     for (int f = 0; f < NIN; f++) raw[f] = (double)a.X[(int64_t)f * a.nx + sidx];
+                } else if (a.Xd) {
+#pragma unroll
+                    for (int f = 0; f < NIN; f++) raw[f] = a.Xd[(int64_t)f * a.n + cell];
                 } else {
                     raw[0] = a.P[cell];
                     raw[1] = a.T[cell];
@@ -258,7 +264,7 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
 #pragma unroll
                     for (int j = 0; j < NIN - 8; j++) xs[j] = (float)((raw[8 + j] - a.in_lo[8 + j]) * a.in_inv[8 + j]);
                 }
-                if (!TRAIN && h == 0) {
+                if (!TRAIN && !a.Xd && h == 0) {
                     // training box (the hull) and physical sanity of the whole cell
                     bool out = false, bad = !(raw[0] > 0.0) || !(raw[1] > 0.0);
                     double sy = 0.0;
@@ -377,6 +383,18 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
                         for (int q = 0; q < 2; q++)
                             *reinterpret_cast<f32x4 *>(a.y + cell * OUT_PAD + 8 * q + 4 * h) =
                                 f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
+                    } else if (a.Yd) {
+                        // feature-major outputs in target units: lanes of half 0 hold rows
+                        // 0..3, half 1 rows 4, 5; rows 0, 2, 4, 5 were trained on their log
+                        const int j0 = 4 * h;
+#pragma unroll
+                        for (int v = 0; v < 4; v++) {
+                            const int j = j0 + v;
+                            if (j < NOUT) {
+                                const double y = a.out_lo[j] + (double)acc[v] * a.out_rng[j];
+                                a.Yd[(int64_t)j * a.n + cell] = (j == 1 || j == 3) ? y : exp(y);
+                            }
+                        }
                     } else if (h == 0) {
                         // rows 0..3: rho, h, cp, c
                         if (a.orho) a.orho[cell] = exp(a.out_lo[0] + (double)acc[0] * a.out_rng[0]);
@@ -1074,6 +1092,30 @@ static void epoch_perm(uint64_t seed, int epoch, int64_t n, uint64_t &pa, uint64
     if (n == 1) pa = 1, pc = 0;
 }
 
+// (h, P, Bilger Z) features of the pressure-based solver's state (Section 4.1), Z Box-Cox
+// transformed (Section 4.2): X[0] = h, X[1] = P, X[2] = (Z^lambda - 1) / lambda, X[3..9] = 0.
+struct HpzArgs {
+    double beta[PROPS_MAX_SPECIES];
+    int ns;
+    double beta_ox, inv_range, lambda;
+    const double *h, *P, *Y;
+    double *X;
+    int64_t n;
+};
+
+__global__ __launch_bounds__(256) void hpz_features_kernel(HpzArgs a)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.n) return;
+    double b = 0.0;
+    for (int i = 0; i < a.ns; i++) b += a.Y[(int64_t)i * a.n + k] * a.beta[i];
+    const double Z = fmax((b - a.beta_ox) * a.inv_range, 0.0);
+    a.X[k] = a.h[k];
+    a.X[a.n + k] = a.P[k];
+    a.X[2 * a.n + k] = (pow(Z, a.lambda) - 1.0) / a.lambda;
+    for (int f = 3; f < NIN; f++) a.X[(int64_t)f * a.n + k] = 0.0;
+}
+
 int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_out *out, int64_t n,
              uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s)
 {
@@ -1230,6 +1272,53 @@ int props_dnn(props_dnn_t d, props_mech_t fb, const props_in *in, const props_ou
         d->fb_cap = n;
     }
     return dnn_eval(d, fb, in, out, n, status, d->fb_idx, d->fb_count, s);
+}
+
+int props_dnn_features(props_dnn_t d, const double *X, double *Y, int64_t n, void *hip_stream)
+{
+    if (!d || !X || !Y) return fail(PROPS_EINVAL, "props_dnn_features: null network, input or output");
+    if (n < 0) return fail(PROPS_EINVAL, "props_dnn_features: n < 0");
+    if (n == 0) return PROPS_OK;
+    if (n > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_dnn_features: n too large");
+    FwdArgs a{};
+    a.Xd = X, a.Yd = Y, a.n = n;
+    a.Wf = d->fused, a.bias = d->master;
+    a.in_lo = d->scal, a.in_inv = d->scal + NIN;
+    a.out_lo = d->scal + 2 * NIN, a.out_rng = d->scal + 2 * NIN + NOUT;
+    return launch_fwd(false, a, (hipStream_t)hip_stream);
+}
+
+int props_features_hpz(const int *atoms, const double *W, int ns, int fuel, int oxidizer, double bc_lambda,
+                       const double *h, const double *P, const double *Y, int64_t n, double *X, void *hip_stream)
+{
+    if (!atoms || !W || !h || !P || !Y || !X) return fail(PROPS_EINVAL, "props_features_hpz: null argument");
+    if (ns < 1 || ns > PROPS_MAX_SPECIES) return fail(PROPS_EINVAL, "props_features_hpz: ns = %d", ns);
+    if (fuel < 0 || fuel >= ns || oxidizer < 0 || oxidizer >= ns)
+        return fail(PROPS_EINVAL, "props_features_hpz: fuel %d / oxidizer %d out of range", fuel, oxidizer);
+    if (!(bc_lambda > 0.0 && bc_lambda <= 1.0))
+        return fail(PROPS_EINVAL, "props_features_hpz: need 0 < lambda <= 1 (got %g)", bc_lambda);
+    double beta[PROPS_MAX_SPECIES];
+    for (int i = 0; i < ns; i++) {
+        if (!(W[i] > 0.0)) return fail(PROPS_EINVAL, "props_features_hpz: W[%d] <= 0", i);
+        beta[i] = (2.0 * atoms[3 * i] + 0.5 * atoms[3 * i + 1] - atoms[3 * i + 2]) / W[i];
+    }
+    const double beta_fuel = beta[fuel], beta_ox = beta[oxidizer];
+    if (!(beta_fuel != beta_ox))
+        return fail(PROPS_EINVAL, "props_features_hpz: fuel and oxidizer have the same coupling function");
+    if (n < 0) return fail(PROPS_EINVAL, "props_features_hpz: n < 0");
+    if (n == 0) return PROPS_OK;
+    HpzArgs a{};
+    for (int i = 0; i < ns; i++) a.beta[i] = beta[i];
+    a.ns = ns;
+    a.beta_ox = beta_ox;
+    a.inv_range = 1.0 / (beta_fuel - beta_ox);
+    a.lambda = bc_lambda;
+    a.h = h, a.P = P, a.Y = Y, a.X = X, a.n = n;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_features_hpz: n too large");
+    hipLaunchKernelGGL(hpz_features_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, a);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
 }
 
 static int fit_scalers_dev(props_dnn_s *d, const float *X, const float *Y, int64_t n, hipStream_t s)

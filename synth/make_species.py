@@ -121,6 +121,11 @@ def fit_nasa7(linear, vib, elec, dhf):
     return lo7, hi7, err
 
 
+# atoms per molecule (C, H, O, N): the element balance behind Bilger's mixture fraction
+ATOMS = {"CH4": (1, 4, 0, 0), "O2": (0, 0, 2, 0), "CO2": (1, 0, 2, 0), "H2O": (0, 2, 1, 0),
+         "CO": (1, 0, 1, 0), "H2": (0, 2, 0, 0), "OH": (0, 1, 1, 0), "N2": (0, 0, 0, 2)}
+
+
 def main():
     out = {
         "description": "CH4/O2 supercritical flame mixture, 8 species; SI units. "
@@ -135,6 +140,7 @@ def main():
             "name": name, "W": W, "Tc": Tc, "Pc": Pc, "Vc": Vc, "omega": om,
             "dipole": 0.0, "dipole_physical": dip, "kappa": kap, "dhf298": dhf, "Tmid": T_MID,
             "nasa_lo": lo, "nasa_hi": hi, "fit_max_rel_err": err,
+            "atoms": dict(zip(("C", "H", "O", "N"), ATOMS[name])),
             "rrho": {"linear": linear, "vib_cm": vib, "elec": elec},
         })
         print(f"{name:4s} fit max rel err {err:.2e}  cp(298)/R={cp_rrho_over_R(np.array([T_REF]), linear, vib, elec)[0]:.4f}")
