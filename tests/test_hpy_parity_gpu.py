@@ -272,3 +272,31 @@ def test_hpy_mixed_error_report(props, orc, sp8, kij8):
     print("\n[mixed hpy] max/rms rel err: " + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in stats.items()))
     for f in ALL:
         assert stats[f][0] <= 1e-3, (f, stats[f])
+
+
+def test_hpy_newton_iteration_limit_and_empty_launch(props, orc, sp8, kij8):
+    import torch
+    P, T, Y = synth.flame_field(6, seed=3)
+    h = orc.Mech(sp8, kij8).state_PT(P, T, Y, transport=False)["h"]
+    m = props.Mechanism(sp8, kij8)
+    m.set_newton(max_iter=1)
+    g = run_gpu(props, m, props.HPY, props.FP64, T.size, {"h": h, "P": P, "Y": Y}, fields=("T",))
+    assert np.all(g["status"] & 2)
+    m.set_newton(100, 1e-10)
+    g = run_gpu(props, m, props.HPY, props.FP64, T.size, {"h": h, "P": P, "Y": Y}, fields=("T",))
+    assert np.all(g["status"] == 0)
+    z = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    props.pr(m, props.HPY, props.FP64, {"h": z, "P": z, "Y": z}, {"T": z}, 0)
+    with pytest.raises(props.PropsError):
+        props.pr(m, props.HPY, props.FP64, {"P": z, "Y": z}, {"T": z}, 1)    # h missing
+
+
+def test_hpy_deterministic_bitwise(props, orc, sp8, kij8):
+    P, T, Y = synth.flame_field(12, seed=5)
+    h = orc.Mech(sp8, kij8).state_PT(P, T, Y, transport=False)["h"]
+    m = props.Mechanism(sp8, kij8)
+    inp = {"h": h, "P": P, "Y": Y, "T_guess": synth.temperature_guess(T)}
+    a = run_gpu(props, m, props.HPY, props.FP64, T.size, inp, fields=ALL + ("hRT",), ns=8)
+    b = run_gpu(props, m, props.HPY, props.FP64, T.size, inp, fields=ALL + ("hRT",), ns=8)
+    for f in ALL + ("hRT",):
+        assert np.array_equal(a[f].view(np.int64), b[f].view(np.int64)), f
