@@ -15,10 +15,11 @@
 // and the bias are applied in FP32 on the accumulators, then packed to bf16 with
 // v_cvt_pk_bf16_f32 (round to nearest even).
 //
-// Backward: tiled bf16 GEMMs (64x64x32 tiles, 4 waves of 2x2 MFMA blocks) for
-// dH = dZ W (with the GELU derivative fused in the epilogue) and dW = dZ^T H (split over
-// the batch with a fixed-order reduction: training is deterministic and resumable bit for
-// bit), column sums for the biases, Adam on FP32 master weights.
+// Backward: dH = dZ W with the GELU derivative fused in the epilogue (64x64 tiles on the
+// 16x16x32 MFMA, W kept transposed so both operands are contiguous along K), dW = dZ^T H on
+// the 32x32x16 MFMA with both operands k-major (split over the batch with a fixed-order
+// reduction: training is deterministic and resumable bit for bit), column sums for the
+// biases, Adam on FP32 master weights.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -429,70 +430,46 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
     }
 }
 
-// ------------------------------------------------------------------ generic bf16 GEMM
-// C[m][n] = sum_k A(m, k) B(k, n); A(m,k) = A[m*lda + k] (TA = false) or A[k*lda + m];
-// B(k,n) = B[k*ldb + n] (TB = false) or B[n*ldb + k].  All of M, N, K, lda, ldb multiples
-// of 8.  blockIdx.z splits K into chunks of kchunk.
-enum { EPI_F32 = 0, EPI_GELU_BWD = 1 };
+// ------------------------------------------------------------------ input-gradient GEMM
+// D[m][n] = bf16( (sum_k A[m][k] B[n][k]) gelu'(Z[m][n]) ): dz_{l-1} = (dz_l W_l) * GELU'(z_{l-1})
+// with A = dz_l (rows = batch, K = the layer's outputs) and B = W_l transposed ([in][out]),
+// both contiguous along K.  64 x 64 tiles, K in steps of 32 staged in LDS with 16-byte
+// stores, 4 waves of 2 x 2 v_mfma_f32_16x16x32_bf16 blocks.  M, N, K, lda, ldb multiples of 8.
+// (An LDS-free variant with 16-byte fragment loads straight from global memory, cells on
+// either MFMA side, measured 1.5-2x slower.)
 struct GemmArgs {
-    int M, N, K, kchunk;
+    int M, N, K;
     const bf16_t *A;
     int lda;
     const bf16_t *B;
     int ldb;
-    float *C;            // EPI_F32: C + z * strideC
+    bf16_t *Cb;
     int ldc;
-    int64_t strideC;
-    bf16_t *Cb;          // EPI_GELU_BWD: bf16(acc * gelu'(Z))
     const float *Z;
     int ldz;
 };
 
-template <bool TA, bool TB, int EPI>
-__global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
+__global__ __launch_bounds__(256) void gemm_dh_kernel(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) bf16_t As[64][40];
     __shared__ __attribute__((aligned(16))) bf16_t Bs[64][40];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    const int kbeg = blockIdx.z * g.kchunk;
-    const int kend = min(g.K, kbeg + g.kchunk);
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = kbeg; k0 < kend; k0 += 32) {
-        // ---- A tile (64 m x 32 k) -> As[m][k]
-        if (!TA) {
-            const int m = t >> 2, k8 = (t & 3) * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (m0 + m < g.M && k0 + k8 < kend) v = *reinterpret_cast<const uint4 *>(g.A + (int64_t)(m0 + m) * g.lda + k0 + k8);
-            *reinterpret_cast<uint4 *>(&As[m][k8]) = v;
-        } else {
-            const int k = t >> 3, m8 = (t & 7) * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (m0 + m8 < g.M && k0 + k < kend) v = *reinterpret_cast<const uint4 *>(g.A + (int64_t)(k0 + k) * g.lda + m0 + m8);
-            const bf16_t *e = reinterpret_cast<const bf16_t *>(&v);
-#pragma unroll
-            for (int j = 0; j < 8; j++) As[m8 + j][k] = e[j];
-        }
-        // ---- B tile (32 k x 64 n) -> Bs[n][k]
-        if (!TB) {
-            const int k = t >> 3, n8 = (t & 7) * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (n0 + n8 < g.N && k0 + k < kend) v = *reinterpret_cast<const uint4 *>(g.B + (int64_t)(k0 + k) * g.ldb + n0 + n8);
-            const bf16_t *e = reinterpret_cast<const bf16_t *>(&v);
-#pragma unroll
-            for (int j = 0; j < 8; j++) Bs[n8 + j][k] = e[j];
-        } else {
-            const int n = t >> 2, k8 = (t & 3) * 8;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (n0 + n < g.N && k0 + k8 < kend) v = *reinterpret_cast<const uint4 *>(g.B + (int64_t)(n0 + n) * g.ldb + k0 + k8);
-            *reinterpret_cast<uint4 *>(&Bs[n][k8]) = v;
-        }
+    for (int k0 = 0; k0 < g.K; k0 += 32) {
+        // A tile (64 m x 32 k) -> As[m][k]; B tile (64 n x 32 k) -> Bs[n][k]
+        const int r = t >> 2, k8 = (t & 3) * 8;
+        uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+        if (m0 + r < g.M && k0 + k8 < g.K) va = *reinterpret_cast<const uint4 *>(g.A + (int64_t)(m0 + r) * g.lda + k0 + k8);
+        if (n0 + r < g.N && k0 + k8 < g.K) vb = *reinterpret_cast<const uint4 *>(g.B + (int64_t)(n0 + r) * g.ldb + k0 + k8);
+        *reinterpret_cast<uint4 *>(&As[r][k8]) = va;
+        *reinterpret_cast<uint4 *>(&Bs[r][k8]) = vb;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 2; i++) {
@@ -514,12 +491,8 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(GemmArgs g)
                 const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
                 const int n = n0 + wn * 32 + j * 16 + (lane & 15);
                 if (m < g.M && n < g.N) {
-                    if (EPI == EPI_F32) {
-                        g.C[blockIdx.z * g.strideC + (int64_t)m * g.ldc + n] = acc[i][j][r];
-                    } else {
-                        const float d = acc[i][j][r] * gelu_grad_f(g.Z[(int64_t)m * g.ldz + n]);
-                        g.Cb[(int64_t)m * g.ldc + n] = to_bf16(d);
-                    }
+                    const float d = acc[i][j][r] * gelu_grad_f(g.Z[(int64_t)m * g.ldz + n]);
+                    g.Cb[(int64_t)m * g.ldc + n] = to_bf16(d);
                 }
             }
 }
@@ -1007,11 +980,10 @@ static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float 
     return PROPS_OK;
 }
 
-template <bool TA, bool TB, int EPI>
-static int gemm(const GemmArgs &g, int splits, hipStream_t s)
+static int gemm_dh(const GemmArgs &g, hipStream_t s)
 {
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, splits);
-    hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, 1);
+    hipLaunchKernelGGL(gemm_dh_kernel, grid, dim3(256), 0, s, g);
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
 }
@@ -1064,10 +1036,10 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
             // dz_{l-1} = (dz W) * gelu'(z_{l-1})  (M = n, N = I = 256, K = O)
             bf16_t *out = (dzl == d->dz) ? d->dz2 : d->dz;
             GemmArgs gh{};
-            gh.M = n, gh.N = I, gh.K = O, gh.kchunk = O;
+            gh.M = n, gh.N = I, gh.K = O;
             gh.A = dzl, gh.lda = O, gh.B = d->nat + kLay::nat(l), gh.ldb = O;
             gh.Cb = out, gh.ldc = I, gh.Z = d->zs[l - 1], gh.ldz = HID;
-            if ((rc = gemm<false, true, EPI_GELU_BWD>(gh, 1, s))) return rc;
+            if ((rc = gemm_dh(gh, s))) return rc;
             dzl = out;
         }
     }
