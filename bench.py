@@ -160,6 +160,37 @@ def copy_bandwidth(nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / float(np.median(t)) / 1e9
 
 
+def pty_section(props, mech, n, Pd, Td, Yd, stream, steps, ncopy=3):
+    """(P, T, Y) -> Z, rho, h, cp, c without transport on the same field (the thermodynamic
+    state of a cell whose pressure and temperature are known): cubic + Gibbs choice +
+    departures, 13 doubles in, 5 out."""
+    import torch
+    dev = Pd.device
+    ins = [{"P": Pd.clone(), "T": Td.clone(), "Y": Yd.clone()} for _ in range(ncopy)]
+    keys = ("Z", "rho", "h", "cp", "c")
+    outs = [{k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys} for _ in range(ncopy)]
+
+    def timed(prec):
+        for i in range(3):
+            props.pr(mech, props.PTY, prec, ins[i % ncopy], outs[i % ncopy], n, stream=stream)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for i in range(steps):
+            props.pr(mech, props.PTY, prec, ins[i % ncopy], outs[i % ncopy], n, stream=stream)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ms64 = timed(props.FP64)
+    ms32 = timed(props.MIXED)
+    bpc = (2 + Yd.shape[0]) * 8 + len(keys) * 8
+    return {"workload": "same field, (P,T,Y) -> Z, rho, h, cp, c (no transport, no status)",
+            "bytes_per_cell": bpc,
+            "fp64": {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "hbm_GBs": bpc * n / (ms64 * 1e-3) / 1e9},
+            "mixed": {"value": n / (ms32 * 1e-3), "ms_per_step": ms32, "hbm_GBs": bpc * n / (ms32 * 1e-3) / 1e9}}
+
+
 def hpy_section(props, mech, n, h0, Pd, Yd, Tg, o_rhoe, stream, steps, ncopy=3):
     """(h, P, Y) mode, the pressure-based solver's state, on the same field: T by Newton
     with the cubic in every evaluation, all outputs plus psi, alpha and h_i/RT."""
@@ -626,6 +657,9 @@ def main():
         ms_ng, _ = timed(props.FP64, max(10, args.steps // 2), 2)
         ins = save
         rec["fp64_no_guess"] = {"value": n / (ms_ng * 1e-3), "ms_per_step": ms_ng}
+        rec["pty"] = pty_section(props, mech, n, Pd, dt(T), Yd, stream, max(10, args.steps // 2))
+        log(f"(P,T,Y) thermo: FP64 {rec['pty']['fp64']['ms_per_step']:.4f} ms, "
+            f"mixed {rec['pty']['mixed']['ms_per_step']:.4f} ms")
         rec["hpy"] = hpy_section(props, mech, n, h0, Pd, Yd, dt(Tg), o_ref, stream, max(10, args.steps // 2))
         log(f"(h,P,Y): FP64 {rec['hpy']['fp64']['ms_per_step']:.4f} ms, "
             f"mixed {rec['hpy']['mixed']['ms_per_step']:.4f} ms")

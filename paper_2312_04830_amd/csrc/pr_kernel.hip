@@ -150,6 +150,38 @@ struct Nasa {
         cp = c0 + T * (c1 + T * (c2 + T * (c3 + T * c4)));
         h = T * (c0 + T * (c1 * 0.5 + T * (c2 * (1.0 / 3.0) + T * (c3 * 0.25 + T * (c4 * 0.2))))) + a6[r];
     }
+    // mixture coefficients of the ranges r0..r1 from the mass fractions y.  The table is read
+    // here through the scalar cache each time: left to itself the compiler hoists the loads
+    // of ~100 table values to the kernel entry while sinking their use, and keeps them alive
+    // in spilled SGPRs across everything in between.
+    template <int NS>
+    __device__ __forceinline__ void build(const ThermoTab<NS> *tt0, const double (&y)[NS], int r0, int r1)
+    {
+        const ThermoTab<NS> *tg = tt0;
+        asm volatile("" : "+s"(tg));
+        const __attribute__((address_space(4))) ThermoTab<NS> *tt =
+            (const __attribute__((address_space(4))) ThermoTab<NS> *)tg;
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            if (r < r0 || r > r1) continue;
+#pragma unroll
+            for (int k = 0; k < 5; k++) {
+                double s = 0.0;
+#pragma unroll
+                for (int i = 0; i < NS; i++) s += y[i] * tt->cp[r][k][i];
+                c[r][k] = s;
+            }
+            double s6 = 0.0;
+#pragma unroll
+            for (int i = 0; i < NS; i++) s6 += y[i] * tt->a6[r][i];
+            a6[r] = s6;
+        }
+        double w = 0.0;
+#pragma unroll
+        for (int i = 0; i < NS; i++) w += y[i] * tt->RW[i];
+        rw = w;
+        Tmid = tt->Tmid;
+    }
 };
 
 // ------------------------------------------------------------------ Chung transport
@@ -438,28 +470,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     double T = nan, P = nan, v = nan;
     double am = 0, am1 = 0, am2 = 0;
     Nasa ig;
-
-    if (!bad) {
-#pragma unroll
-        for (int r = 0; r < 2; r++) {
-#pragma unroll
-            for (int c = 0; c < 5; c++) {
-                double s = 0.0;
-#pragma unroll
-                for (int i = 0; i < NS; i++) s += y[i] * tt->cp[r][c][i];
-                ig.c[r][c] = s;
-            }
-            double s6 = 0.0;
-#pragma unroll
-            for (int i = 0; i < NS; i++) s6 += y[i] * tt->a6[r][i];
-            ig.a6[r] = s6;
-        }
-        double rw = 0.0;
-#pragma unroll
-        for (int i = 0; i < NS; i++) rw += y[i] * tt->RW[i];
-        ig.rw = rw;
-        ig.Tmid = tt->Tmid;
-    }
+    // the inversions evaluate the ideal gas at many T: both NASA ranges up front; the
+    // (P, T, Y) path needs one range, once, and builds it where it is used
+    if (MODE != PROPS_PTY && !bad) ig.build<NS>(tt, y, 0, 1);
 
     if (MODE == PROPS_HPY && !bad) {
         // ---- (h, P, Y): bracketed Newton on h(T) at fixed P, the cubic in every evaluation
@@ -646,6 +659,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     }
 
     // ---- departure functions and derived properties at (v, T)
+    if (MODE == PROPS_PTY) {
+        const int r = (T >= tt->Tmid) ? 1 : 0;
+        ig.build<NS>(tt, y, r, r);
+    }
     double h_ig, cp_ig;
     ig.eval(T, h_ig, cp_ig);
     const double RT = kR * T;
