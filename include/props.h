@@ -81,7 +81,9 @@ void props_mech_destroy(props_mech_t m);
 int props_mech_num_species(props_mech_t m);
 
 /* Newton options of the (rho, e, Y) and (h, P, Y) inversions: max_iter >= 1 (default 100)
- * and the relative step size below which one last Newton step is taken (default 1e-10). */
+ * and the relative step size that ends the iteration (default 1e-10): a Newton step at
+ * most this small is the last one (convergence is quadratic); after a bisection step that
+ * small, one more Newton step is taken. */
 int props_mech_set_newton(props_mech_t m, int max_iter, double rtol);
 
 /* ------------------------------------------------------------------ property evaluation */

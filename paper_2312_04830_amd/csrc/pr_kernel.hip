@@ -524,18 +524,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
             else { conv = true; break; }
             // Newton step when it stays in the closed bracket and at least halves the step
             // taken two iterations before (else Newton can cycle where the slope varies
-            // strongly, as near pseudo-boiling); otherwise bisection.  The last (polishing)
-            // step never bisects: a converged T whose step rounds to nothing sits on a
+            // strongly, as near pseudo-boiling); otherwise bisection.  A Newton step below
+            // rtol ends the iteration: convergence is quadratic, so the updated T is exact
+            // to rounding.  After a small bisection step one more (polishing) step is taken,
+            // which never bisects: a converged T whose step rounds to nothing sits on a
             // bracket end, and bisecting there would throw it away.
             double Tn = T - r * fm::rcp(rp);
-            if (!(rp > 0.0) || !(Tn >= lo && Tn <= hi) || !(fabs(Tn - T) <= 0.5 * dT2))
-                Tn = fin ? T : 0.5 * (lo + hi);
+            const bool newton = (rp > 0.0) && (Tn >= lo && Tn <= hi) && (fabs(Tn - T) <= 0.5 * dT2);
+            if (!newton) Tn = fin ? T : 0.5 * (lo + hi);
             const double dT = Tn - T;
             dT2 = dT1;
             dT1 = fabs(dT);
             T = Tn;
             if (fin) { conv = true; break; }
-            if (fabs(dT) <= rtol * T) fin = true;
+            if (fabs(dT) <= rtol * T) {
+                if (newton) { conv = true; break; }
+                fin = true;
+            }
         }
         if (a.iters) a.iters[k] = (uint8_t)min(it + (conv ? 1 : 0), 255);
         if (!conv) st |= PROPS_ST_NEWTON_MAXIT;
@@ -602,18 +607,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
                 else { conv = true; break; }
                 // Newton step when it stays in the closed bracket and at least halves the step
                 // taken two iterations before (else Newton can cycle where the slope varies
-                // strongly, as near pseudo-boiling); otherwise bisection.  The last (polishing)
-                // step never bisects: a converged T whose step rounds to nothing sits on a
+                // strongly, as near pseudo-boiling); otherwise bisection.  A Newton step below
+                // rtol ends the iteration: convergence is quadratic, so the updated T is exact
+                // to rounding.  After a small bisection step one more (polishing) step is taken,
+                // which never bisects: a converged T whose step rounds to nothing sits on a
                 // bracket end, and bisecting there would throw it away.
                 double Tn = T - r * fm::rcp(rp);
-                if (!(rp > 0.0) || !(Tn >= lo && Tn <= hi) || !(fabs(Tn - T) <= 0.5 * dT2))
-                    Tn = fin ? T : 0.5 * (lo + hi);
+                const bool newton = (rp > 0.0) && (Tn >= lo && Tn <= hi) && (fabs(Tn - T) <= 0.5 * dT2);
+                if (!newton) Tn = fin ? T : 0.5 * (lo + hi);
                 const double dT = Tn - T;
                 dT2 = dT1;
                 dT1 = fabs(dT);
                 T = Tn;
                 if (fin) { conv = true; break; }
-                if (fabs(dT) <= rtol * T) fin = true;
+                if (fabs(dT) <= rtol * T) {
+                    if (newton) { conv = true; break; }
+                    fin = true;
+                }
             }
             if (a.iters) a.iters[k] = (uint8_t)min(it + (conv ? 1 : 0), 255);
             if (!conv) st |= PROPS_ST_NEWTON_MAXIT;
