@@ -3,13 +3,16 @@
 // What a lane computes (paper, Section 2; Eq. (1) is the Peng-Robinson equation):
 //   composition      W = 1/sum(Y_i/W_i), X_i = Y_i W / W_i, b_m = sum X_i b_i
 //   alpha / mixing   g_i = sqrt(a_c,i) |1 + kappa_i (1 - sqrt(T/Tc_i))|,
-//                    a_m = sum_ij X_i X_j (1 - k_ij) g_i g_j and its first two T-derivatives
-//                    as two mat-vecs with the (1 - k_ij) matrix
+//                    a_m = sum_ij X_i X_j (1 - k_ij) g_i g_j, exactly A0 + A1 sqrt(T) + A2 T
+//                    between the temperatures where a factor changes sign: coefficients from
+//                    two mat-vecs with the (1 - k_ij) matrix, then O(1) per evaluation
 //   ideal gas        per-cell NASA-7 mixture coefficients, one Horner each for h, cp
-//   (P,T,Y)          cubic in Z (closed form + Newton polish, double), physical roots Z > B,
-//                    minimum residual Gibbs energy between the liquid- and vapour-like root
+//   (P,T,Y)          cubic in Z (largest root in closed form, deflation for the others,
+//                    Newton polish, double), physical roots Z > B, minimum residual Gibbs
+//                    energy between the liquid- and vapour-like root
 //   (rho,e,Y)        bracketed Newton on e(T; v, Y) = e* (v fixed, so the departure log is
-//                    computed once), bisection whenever a step leaves the bracket
+//                    computed once), bisection whenever a step leaves the bracket or fails
+//                    to halve
 //   (h,P,Y)          the pressure-based solver's state (Section 3): bracketed Newton on
 //                    h(T; P, Y) = h* with the cubic and root choice inside every evaluation
 //                    and the real-fluid cp as the slope
