@@ -86,6 +86,13 @@ def lib():
         L.orc_pr_kappa.restype = ctypes.c_double
         L.orc_pr_kappa.argtypes = [ctypes.c_double]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_omega_d.restype = ctypes.c_double
+        L.orc_omega_d.argtypes = [ctypes.c_double]
+        L.orc_binary_diffusion.restype = ctypes.c_double
+        L.orc_binary_diffusion.argtypes = [ctypes.c_double] * 6
+        L.orc_eval_mixdiff.restype = ctypes.c_int
+        L.orc_eval_mixdiff.argtypes = [ctypes.POINTER(_Mech), ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         assert L.orc_sizeof_cell() == CELL_DTYPE.itemsize, "orc_cell layout mismatch"
         assert L.orc_sizeof_mech() == ctypes.sizeof(_Mech), "orc_mech layout mismatch"
         _lib = L
@@ -143,6 +150,18 @@ class Mech:
     def state_hP(self, h, P, Y, **kw):
         return self.eval(HP, h, P, Y, **kw)
 
+    def mixdiff(self, P, T, Y, nthreads=0):
+        """Mixture-averaged diffusion coefficients [ns, n] (m^2/s) at (P, T, Y)."""
+        P = np.ascontiguousarray(P, dtype=np.float64).ravel()
+        T = np.ascontiguousarray(T, dtype=np.float64).ravel()
+        n = P.size
+        Y = np.ascontiguousarray(np.asarray(Y, dtype=np.float64).reshape(self.ns, n))
+        D = np.zeros((self.ns, n))
+        if lib().orc_eval_mixdiff(ctypes.byref(self._m), n, P.ctypes.data, T.ctypes.data, Y.ctypes.data,
+                                  D.ctypes.data, int(nthreads)) != 0:
+            raise RuntimeError("orc_eval_mixdiff failed")
+        return D
+
     def mix(self, X, T):
         X = np.ascontiguousarray(X, dtype=np.float64)
         out = [ctypes.c_double() for _ in range(4)]
@@ -174,6 +193,14 @@ def chung_lambda(T, rho_molar, Tc, Vc_cm3, M_gmol, omega, mu_r, kappa, Cv):
 
 def omega_v(Ts):
     return lib().orc_omega_v(Ts)
+
+
+def omega_d(Ts):
+    return lib().orc_omega_d(Ts)
+
+
+def binary_diffusion(T, P, Mi, Mj, sigma, eps_k):
+    return lib().orc_binary_diffusion(T, P, Mi, Mj, sigma, eps_k)
 
 
 def max_threads():

@@ -27,6 +27,11 @@
  *   - The extra solver outputs of Section 4.1: psi = (d rho / d p) at constant enthalpy
  *     (and composition), thermal diffusivity lambda / (rho c_p), and each species'
  *     nondimensional standard-state enthalpy h_i/(R T) from its NASA polynomial.
+ *   - Mixture-averaged diffusion coefficients (Section 2 names them, with Takahashi's
+ *     high-pressure correction, whose chart is not available here): Chapman-Enskog binary
+ *     coefficients with Neufeld's collision integral Omega(1,1)*, Lennard-Jones parameters
+ *     from the corresponding-states relations of Chung's model (sigma = 0.809 Vc^(1/3),
+ *     eps/k = Tc/1.2593), combined as D_i = (1 - Y_i) / sum_{j != i} X_j / D_ij.
  *   - Chung et al. (1988) dense-fluid viscosity and thermal conductivity ("modified Chung
  *     with mole-fraction-averaged viscosity", Section 2): Chung's high-pressure model on the
  *     one-fluid pseudo-mixture, with the low-pressure viscosity it builds on taken as the
@@ -453,6 +458,77 @@ void orc_transport(const orc_mech *m, const double *X, double T, double rho, dou
     double murm = 131.3 * mum / sqrt(Vcm * Tcm);
     *mu = orc_chung_mu_eta0(eta0, T, rho, Tcm, Vcm, Mm, wm, murm, km);
     *lam = orc_chung_lambda_eta0(eta0, T, rho, Tcm, Vcm, Mm, wm, murm, km, Cv);
+}
+
+/* ----------------------------------------------------------------------------------- */
+/* Mixture-averaged diffusion (low-pressure Chapman-Enskog)                            */
+/* ----------------------------------------------------------------------------------- */
+
+/* Boltzmann and Avogadro constants (exact in SI since 2019). */
+static const double ORC_KB = 1.380649e-23, ORC_NA = 6.02214076e23;
+
+/* Neufeld, Janzen & Aziz (1972) fit of the Lennard-Jones diffusion collision integral
+ * Omega(1,1)* as a function of T* = k T / eps. */
+double orc_omega_d(double Ts)
+{
+    return 1.06036 / pow(Ts, 0.15610) + 0.19300 / exp(0.47635 * Ts)
+         + 1.03587 / exp(1.52996 * Ts) + 1.76474 / exp(3.89411 * Ts);
+}
+
+/* Chapman-Enskog binary diffusion coefficient [m^2/s] at T [K], P [Pa] for molar masses
+ * Mi, Mj [kg/mol], collision diameter sigma [m] and well depth eps/k [K]:
+ * D = (3/16) sqrt(2 pi (k T)^3 / m_r) / (P pi sigma^2 Omega(1,1)*), m_r the reduced mass. */
+double orc_binary_diffusion(double T, double P, double Mi, double Mj, double sigma, double eps_k)
+{
+    double mr = Mi * Mj / ((Mi + Mj) * ORC_NA);
+    double kT = ORC_KB * T;
+    double pi = acos(-1.0);
+    return 3.0 / 16.0 * sqrt(2.0 * pi * kT * kT * kT / mr) / (P * pi * sigma * sigma * orc_omega_d(T / eps_k));
+}
+
+/* Lennard-Jones parameters of species s from Chung's corresponding-states relations. */
+static void orc_lj(const orc_species *s, double *sigma_m, double *eps_k)
+{
+    *sigma_m = 0.809 * cbrt(s->Vc * 1e6) * 1e-10;
+    *eps_k = s->Tc / 1.2593;
+}
+
+/* D[i] = (1 - Y_i) / sum_{j != i} X_j / D_ij, zero when no other species is present;
+ * pair parameters by the Lorentz-Berthelot rules. */
+void orc_mixdiff(const orc_mech *m, double P, double T, const double *Y, double *D)
+{
+    double X[ORC_MAXNS];
+    orc_molefrac(m, Y, X);
+    for (int i = 0; i < m->ns; i++) {
+        double si, ei;
+        orc_lj(&m->sp[i], &si, &ei);
+        double sum = 0.0;
+        for (int j = 0; j < m->ns; j++) {
+            if (j == i) continue;
+            double sj, ej;
+            orc_lj(&m->sp[j], &sj, &ej);
+            double Dij = orc_binary_diffusion(T, P, m->sp[i].W, m->sp[j].W, 0.5 * (si + sj), sqrt(ei * ej));
+            sum += X[j] / Dij;
+        }
+        D[i] = (sum > 0.0) ? (1.0 - Y[i]) / sum : 0.0;
+    }
+}
+
+int orc_eval_mixdiff(const orc_mech *m, int64_t n, const double *P, const double *T, const double *Y,
+                     double *D, int nthreads)
+{
+    if (m->ns < 1 || m->ns > ORC_MAXNS) return -1;
+#ifdef _OPENMP
+    const int nt = (nthreads > 0) ? nthreads : omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 256) num_threads(nt)
+#endif
+    for (int64_t k = 0; k < n; k++) {
+        double y[ORC_MAXNS], d[ORC_MAXNS];
+        for (int i = 0; i < m->ns; i++) y[i] = Y[(int64_t)i * n + k];
+        orc_mixdiff(m, P[k], T[k], y, d);
+        for (int i = 0; i < m->ns; i++) D[(int64_t)i * n + k] = d[i];
+    }
+    return 0;
 }
 
 /* ----------------------------------------------------------------------------------- */
