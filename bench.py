@@ -191,6 +191,45 @@ def pty_section(props, mech, n, Pd, Td, Yd, stream, steps, ncopy=3):
             "mixed": {"value": n / (ms32 * 1e-3), "ms_per_step": ms32, "hbm_GBs": bpc * n / (ms32 * 1e-3) / 1e9}}
 
 
+def diffusion_section(props, mech, n, Pd, Td, Yd, stream, steps, ncopy=3):
+    """Mixture-averaged diffusion coefficients D_i (props_diffusion) on the same field:
+    P, T, Y in, D [ns][n] and status out."""
+    import torch
+    dev = Pd.device
+    ns = Yd.shape[0]
+    ins = [(Pd.clone(), Td.clone(), Yd.clone()) for _ in range(ncopy)]
+    outs = [torch.empty((ns, n), dtype=torch.float64, device=dev) for _ in range(ncopy)]
+    st = [torch.empty(n, dtype=torch.uint8, device=dev) for _ in range(ncopy)]
+
+    def call(prec, i):
+        P, T, Y = ins[i % ncopy]
+        props.diffusion(mech, prec, P, T, Y, outs[i % ncopy], n, status=st[i % ncopy], stream=stream)
+
+    def timed(prec):
+        for i in range(3):
+            call(prec, i)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for i in range(steps):
+            call(prec, i)
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    ms64 = timed(props.FP64)
+    d64 = outs[(steps - 1) % ncopy].clone()
+    ms32 = timed(props.MIXED)
+    d32 = outs[(steps - 1) % ncopy]
+    rel = float(((d32 - d64).abs() / d64.abs()).max())
+    bpc = (2 + ns) * 8 + ns * 8 + 1
+    return {"workload": "same field, (P,T,Y) -> D_i of every species (Chapman-Enskog, mixture-averaged)",
+            "bytes_per_cell": bpc,
+            "fp64": {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "hbm_GBs": bpc * n / (ms64 * 1e-3) / 1e9},
+            "mixed": {"value": n / (ms32 * 1e-3), "ms_per_step": ms32, "hbm_GBs": bpc * n / (ms32 * 1e-3) / 1e9,
+                      "max_rel_vs_fp64": rel}}
+
+
 def hpy_section(props, mech, n, h0, Pd, Yd, Tg, o_rhoe, stream, steps, ncopy=3):
     """(h, P, Y) mode, the pressure-based solver's state, on the same field: T by Newton
     with the cubic in every evaluation, all outputs plus psi, alpha and h_i/RT."""
@@ -374,13 +413,21 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
     X = torch.empty((10, n_train), dtype=torch.float64, device=dev)
     props.features_hpz(sp, 0, 1, lam, lab["h"], Pd, Yd, n_train, X)
     L = torch.stack([lab["rho"], Td, lab["mu"], hrt[0], lab["psi"], lab["alpha"]]).float().contiguous()
+    # a second network for the diffusion coefficients of the first six species (all six
+    # outputs trained on their logarithm), labels from the Chapman-Enskog kernel
+    Dlab = torch.empty((ns, n_train), dtype=torch.float64, device=dev)
+    props.diffusion(mech, props.FP64, Pd, Td, Yd, Dlab, n_train)
+    LD = Dlab[:6].float().contiguous()
     Xf = X.float().contiguous()
     bad_labels = int((st != 0).sum())
-    del X, lab, hrt, Pd, Td, Yd
+    del X, lab, hrt, Pd, Td, Yd, Dlab
     net = props.Network(seed=2025)
     log(f"(h,P,Z) surrogate: training {epochs} epochs on {n_train} samples")
     rep, losses = net.train(Xf, L, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=7)
-    del Xf, L
+    netD = props.Network(seed=2026)
+    netD.set_log_outputs(0x3F)
+    repD, lossesD = netD.train(Xf, LD, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=8)
+    del Xf, L, LD
     # inference field and the (h, P, Y) reference
     Pf, Tf, Yf = synth.flame_field(res, seed=4)
     n = Tf.size
@@ -412,12 +459,18 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
         net.features(X, Yo, n)
 
     ms_dnn = timeit(surrogate)
+    YD = torch.empty((6, n), dtype=torch.float64, device=dev)
+    ms_dnnD = timeit(lambda: netD.features(X, YD, n))
     ms_hpy64 = timeit(lambda: props.pr(mech, props.HPY, props.FP64, hin, ref, n))
     out32 = {k: torch.empty_like(v) for k, v in ref.items()}
     ms_hpy32 = timeit(lambda: props.pr(mech, props.HPY, props.MIXED, hin, out32, n))
     props.pr(mech, props.HPY, props.FP64, hin, ref, n)
     surrogate()
+    netD.features(X, YD, n)
+    Dref = torch.empty((ns, n), dtype=torch.float64, device=dev)
+    ms_diff64 = timeit(lambda: props.diffusion(mech, props.FP64, Pd, ref["T"], Yd, Dref, n))
     torch.cuda.synchronize()
+    errD = {sp[i]["name"]: _rel_stats(YD[i], Dref[i], "D") for i in range(6)}
     refs = {"rho": ref["rho"], "T": ref["T"], "mu": ref["mu"], "hRT0": ref["hRT"][0], "psi": ref["psi"],
             "alpha": ref["alpha"]}
     err = {}
@@ -437,7 +490,14 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
             "rel_err_vs_pr_hpy_fp64": err,
             "train": {"samples": n_train, "epochs": epochs, "seconds": rep["seconds"],
                       "samples_per_s": rep["samples_per_s"], "loss_first": float(losses[0]),
-                      "loss_last": float(losses[-1]), "label_flags": bad_labels}}
+                      "loss_last": float(losses[-1]), "label_flags": bad_labels},
+            "diffusion_net": {
+                "workload": "same features -> D_i of CH4, O2, CO2, H2O, CO, H2 (log outputs), second network",
+                "value": n / (ms_dnnD * 1e-3), "unit": "cells/s", "ms": ms_dnnD,
+                "pr_diffusion_fp64_cells_per_s": n / (ms_diff64 * 1e-3),
+                "rel_err_vs_chapman_enskog_at_hpy_T": errD,
+                "train": {"seconds": repD["seconds"], "loss_first": float(lossesD[0]),
+                          "loss_last": float(lossesD[-1])}}}
 
 
 def serving_section(props, synth, mech, net, n_sub=64, reqs_per_sub=50, loads=(0.5, 0.8)):
@@ -663,6 +723,9 @@ def main():
         rec["hpy"] = hpy_section(props, mech, n, h0, Pd, Yd, dt(Tg), o_ref, stream, max(10, args.steps // 2))
         log(f"(h,P,Y): FP64 {rec['hpy']['fp64']['ms_per_step']:.4f} ms, "
             f"mixed {rec['hpy']['mixed']['ms_per_step']:.4f} ms")
+        rec["diffusion"] = diffusion_section(props, mech, n, Pd, dt(T), Yd, stream, max(10, args.steps // 2))
+        log(f"diffusion: FP64 {rec['diffusion']['fp64']['ms_per_step']:.4f} ms, "
+            f"mixed {rec['diffusion']['mixed']['ms_per_step']:.4f} ms")
         cbw = copy_bandwidth()
         rec["roofline"]["copy_GBs"] = cbw
         rec["roofline"]["hbm_frac_of_copy"] = hbm / cbw

@@ -134,6 +134,23 @@ typedef struct {
 int props_pr(props_mech_t m, int mode, int prec, const props_in *in, const props_out *out,
              int64_t n, uint8_t *status, void *hip_stream);
 
+/* Mixture-averaged diffusion coefficients D_i [m^2/s] of every species (Section 2, the
+ * species transport closure), low-pressure Chapman-Enskog form:
+ *   D_ij = (3/16) sqrt(2 pi (k T)^3 / m_ij) / (P pi sigma_ij^2 Omega_D(k T / eps_ij)),
+ *   D_i  = (1 - Y_i) / sum_{j != i} X_j / D_ij,   D_i = 0 if no other species is present,
+ * with m_ij the reduced molecular mass, Neufeld's fit of the collision integral Omega_D,
+ * Lennard-Jones parameters from Chung's critical-point relations (sigma_i = 0.809
+ * Vc_i^(1/3), eps_i/k = Tc_i/1.2593) combined by Lorentz-Berthelot.  Takahashi's
+ * high-pressure correction is not applied.
+ * P [n] (Pa), T [n] (K), Y [ns][n] species-major, D [ns][n] species-major: device
+ * arrays owned by the caller.  prec = PROPS_FP64, or PROPS_MIXED for the pair sums in
+ * single precision.  Cells with NaN or non-positive P or T, Y_i < -1e-12 or
+ * |sum Y - 1| > 1e-6 get D = NaN and PROPS_ST_NONPHYS in the optional status [n];
+ * other cells get status 0.  Asynchronous on hip_stream.  Returns PROPS_EINVAL for a
+ * NULL mechanism or array, an unknown precision or n < 0. */
+int props_diffusion(props_mech_t m, int prec, const double *P, const double *T, const double *Y,
+                    double *D, int64_t n, uint8_t *status, void *hip_stream);
+
 
 /* ------------------------------------------------------------------ MLP surrogate */
 /* The surrogate of Section 4: a multilayer perceptron with GELU activations mapping a
@@ -166,7 +183,19 @@ int props_dnn_get_scalers(props_dnn_t net, double *in_lo, double *in_hi, double 
 int props_dnn_set_scalers(props_dnn_t net, const double *in_lo, const double *in_hi,
                           const double *out_lo, const double *out_hi);
 
-/* Checkpoint: FP32 master weights, Adam moments and step, epoch counter, scalers.
+/* Which of the six outputs the network is trained on, and predicts, as a logarithm: bit j
+ * for output j.  The default 0x35 (outputs 0, 2, 4, 5) is that of the (P, T, Y) surrogate
+ * (rho, cp, mu, lambda log-transformed; h and c linear) and the only mask props_dnn
+ * accepts; networks trained on other targets (for instance diffusion coefficients, all
+ * positive and spanning decades) set their own mask before train_dnn, which fits the
+ * output box on the transformed targets, and are evaluated with props_dnn_features.
+ * Returns PROPS_EINVAL for bits beyond output 5.  Changing the mask of a trained network
+ * invalidates its output box. */
+int props_dnn_set_log_outputs(props_dnn_t net, unsigned mask);
+int props_dnn_get_log_outputs(props_dnn_t net, unsigned *mask);
+
+/* Checkpoint: FP32 master weights, Adam moments and step, epoch counter, log-output
+ * mask, scalers.
  * A load followed by further training continues bit for bit. */
 int props_dnn_save(props_dnn_t net, const char *path);
 int props_dnn_load(const char *path, props_dnn_t *out);
@@ -184,8 +213,8 @@ int props_dnn(props_dnn_t net, props_mech_t fallback, const props_in *in, const 
 
 /* Evaluate the surrogate on raw features: X is a device array [PROPS_DNN_IN][n] (feature-
  * major, double), Y a device array [PROPS_DNN_OUT][n] that receives the six outputs in the
- * network's target units (outputs 0, 2, 4 and 5 were trained on their logarithm and are
- * returned through exp).  Inputs are min-max scaled by the network's input box; no hull
+ * network's target units (outputs trained on their logarithm, see
+ * props_dnn_set_log_outputs, are returned through exp).  Inputs are min-max scaled by the network's input box; no hull
  * test, status or fallback.  This is the entry for networks trained on other inputs than
  * (P, T, Y), such as the (h, P, Z) features below.  Asynchronous on hip_stream. */
 int props_dnn_features(props_dnn_t net, const double *X, double *Y, int64_t n, void *hip_stream);

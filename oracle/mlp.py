@@ -66,27 +66,32 @@ def scale_inputs(X, lo, hi):
     return np.where(rng > 0, (X - lo) / safe, 0.0)
 
 
-def transform_outputs(Y, lo, hi):
-    """Raw outputs [n, 6] -> targets in [0, 1] (log first for the LOG_OUTPUTS)."""
+def log_flags(mask):
+    """Per-output log flags from a bit mask (bit j: output j is log-transformed)."""
+    return tuple(bool(mask >> j & 1) for j in range(len(LOG_OUTPUTS)))
+
+
+def transform_outputs(Y, lo, hi, log_outputs=LOG_OUTPUTS):
+    """Raw outputs [n, 6] -> targets in [0, 1] (log first for the flagged outputs)."""
     T = np.array(Y, dtype=np.float64, copy=True)
-    for j, lg in enumerate(LOG_OUTPUTS):
+    for j, lg in enumerate(log_outputs):
         if lg:
             T[:, j] = np.log(T[:, j])
     return (T - lo) / (hi - lo)
 
 
-def untransform_outputs(S, lo, hi):
+def untransform_outputs(S, lo, hi, log_outputs=LOG_OUTPUTS):
     T = lo + S * (hi - lo)
-    for j, lg in enumerate(LOG_OUTPUTS):
+    for j, lg in enumerate(log_outputs):
         if lg:
             T[:, j] = np.exp(T[:, j])
     return T
 
 
-def fit_scalers(X, Y):
+def fit_scalers(X, Y, log_outputs=LOG_OUTPUTS):
     """Min-max box of the inputs and of the (log-)transformed outputs."""
     T = np.array(Y, dtype=np.float64, copy=True)
-    for j, lg in enumerate(LOG_OUTPUTS):
+    for j, lg in enumerate(log_outputs):
         if lg:
             T[:, j] = np.log(T[:, j])
     return X.min(0), X.max(0), T.min(0), T.max(0)

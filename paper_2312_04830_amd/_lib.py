@@ -108,6 +108,7 @@ def lib():
         L.props_mech_set_newton.argtypes = [_P, ctypes.c_int, ctypes.c_double]
         L.props_pr.argtypes = [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(PropsIn),
                                ctypes.POINTER(PropsOut), ctypes.c_int64, _P, _P]
+        L.props_diffusion.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int64, _P, _P]
         L.props_dnn_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(_P)]
         L.props_dnn_destroy.argtypes = [_P]
         L.props_dnn_destroy.restype = None
@@ -115,6 +116,8 @@ def lib():
         L.props_dnn_set_layer.argtypes = [_P, ctypes.c_int, _P, _P]
         L.props_dnn_get_scalers.argtypes = [_P, _P, _P, _P, _P]
         L.props_dnn_set_scalers.argtypes = [_P, _P, _P, _P, _P]
+        L.props_dnn_set_log_outputs.argtypes = [_P, ctypes.c_uint]
+        L.props_dnn_get_log_outputs.argtypes = [_P, ctypes.POINTER(ctypes.c_uint)]
         L.props_dnn_save.argtypes = [_P, ctypes.c_char_p]
         L.props_dnn_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_P)]
         L.props_dnn.argtypes = [_P, _P, ctypes.POINTER(PropsIn), ctypes.POINTER(PropsOut),
@@ -204,6 +207,12 @@ def pr(mech, mode, prec, inputs, outputs, n, status=None, stream=None):
                          int(n), _ptr(status), _stream(stream)))
 
 
+def diffusion(mech, prec, P, T, Y, D, n, status=None, stream=None):
+    """props_diffusion: P, T [n], Y and D [ns, n] are contiguous float64 device tensors."""
+    check(lib().props_diffusion(mech.handle, int(prec), _ptr(P), _ptr(T), _ptr(Y), _ptr(D), int(n),
+                                _ptr(status), _stream(stream)))
+
+
 def features_hpz(species, fuel, oxidizer, bc_lambda, h, P, Y, n, X, stream=None):
     """props_features_hpz: species dicts give W and "atoms" {C, H, O}; h, P [n], Y [ns, n]
     and X [10, n] are float64 device tensors."""
@@ -257,6 +266,15 @@ class Network:
         import numpy as np
         a = [np.ascontiguousarray(x, dtype=np.float64) for x in (in_lo, in_hi, out_lo, out_hi)]
         check(lib().props_dnn_set_scalers(self.handle, *[x.ctypes.data for x in a]))
+
+    def set_log_outputs(self, mask):
+        """Bit j: output j is trained on and predicted as its logarithm (before train)."""
+        check(lib().props_dnn_set_log_outputs(self.handle, int(mask)))
+
+    def get_log_outputs(self):
+        m = ctypes.c_uint()
+        check(lib().props_dnn_get_log_outputs(self.handle, ctypes.byref(m)))
+        return m.value
 
     def __call__(self, inputs, outputs, n, fallback=None, status=None, stream=None):
         """props_dnn: inputs P, T, Y; outputs rho, h, cp, c, mu, lambda (device tensors)."""

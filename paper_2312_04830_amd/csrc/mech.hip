@@ -70,12 +70,8 @@ static void fill_mix(MixTab<R, NS> &t, const props_species_desc *sp, int ns, con
             if (j < i) continue;
             double f = (i == j) ? 1.0 : 2.0;
             double sij = std::sqrt(sig[i] * sig[j]), eij = std::sqrt(eps[i] * eps[j]);
-            double sij3 = sij * sij * sij;
-            double wij = 0.5 * (sp[i].omega + sp[j].omega);
             double Mi = sp[i].W * 1e3, Mj = sp[j].W * 1e3;
             double Mij = 2.0 * Mi * Mj / (Mi + Mj);
-            (void)sij3;
-            (void)wij;
             t.ESM[i][j] = (R)(f * eij * sij * sij * std::sqrt(Mij));
         }
     }
@@ -109,16 +105,50 @@ static void fill_thermo(ThermoTab<NS> &t, const props_species_desc *sp, int ns)
     t.Tmid = sp[0].Tmid;
 }
 
+// Chapman-Enskog pair constants.  Lennard-Jones parameters come from the same Chung
+// corresponding-states relations as the viscosity (sigma_i = 0.809 Vc_i^(1/3) Angstrom with
+// Vc in cm^3/mol, eps_i/k = Tc_i/1.2593) and combine by Lorentz-Berthelot:
+// sigma_ij = (sigma_i + sigma_j)/2, eps_ij = sqrt(eps_i eps_j).
+template <typename R, int NS>
+static void fill_diff(DiffTab<R, NS> &t, const props_species_desc *sp, int ns)
+{
+    std::memset(&t, 0, sizeof(t));
+    constexpr double kB = 1.380649e-23, kNA = 6.02214076e23;   // exact SI values
+    const double pi = std::acos(-1.0);
+    int p = 0;
+    for (int i = 0; i < NS; i++) {
+        for (int j = i + 1; j < NS; j++, p++) {
+            if (i >= ns || j >= ns) continue;
+            const double si = 0.809e-10 * std::cbrt(sp[i].Vc * 1e6), sj = 0.809e-10 * std::cbrt(sp[j].Vc * 1e6);
+            const double sij = 0.5 * (si + sj);
+            const double eij = std::sqrt((sp[i].Tc / 1.2593) * (sp[j].Tc / 1.2593));
+            const double mij = sp[i].W * sp[j].W / ((sp[i].W + sp[j].W) * kNA);
+            const double G = 16.0 / 3.0 * sij * sij * std::sqrt(pi * mij / (2.0 * kB * kB * kB));
+            t.c0[p] = (R)(1.06036 * G * std::pow(eij, 0.15610));
+            t.c1[p] = (R)(0.19300 * G);
+            t.c2[p] = (R)(1.03587 * G);
+            t.c3[p] = (R)(1.76474 * G);
+            t.x1[p] = (R)(-0.47635 / eij);
+            t.x2[p] = (R)(-1.52996 / eij);
+            t.x3[p] = (R)(-3.89411 / eij);
+        }
+    }
+}
+
 template <int NS>
 static int build_tables(props_mech_s *m)
 {
     size_t o1 = align256(sizeof(ThermoTab<NS>));
     size_t o2 = o1 + align256(sizeof(MixTab<double, NS>));
-    size_t bytes = o2 + align256(sizeof(MixTab<float, NS>));
+    size_t o3 = o2 + align256(sizeof(MixTab<float, NS>));
+    size_t o4 = o3 + align256(sizeof(DiffTab<double, NS>));
+    size_t bytes = o4 + align256(sizeof(DiffTab<float, NS>));
     std::vector<unsigned char> host(bytes, 0);
     fill_thermo<NS>(*reinterpret_cast<ThermoTab<NS> *>(host.data()), m->sp, m->ns);
     fill_mix<double, NS>(*reinterpret_cast<MixTab<double, NS> *>(host.data() + o1), m->sp, m->ns, m->kij);
     fill_mix<float, NS>(*reinterpret_cast<MixTab<float, NS> *>(host.data() + o2), m->sp, m->ns, m->kij);
+    fill_diff<double, NS>(*reinterpret_cast<DiffTab<double, NS> *>(host.data() + o3), m->sp, m->ns);
+    fill_diff<float, NS>(*reinterpret_cast<DiffTab<float, NS> *>(host.data() + o4), m->sp, m->ns);
     void *d = nullptr;
     hipError_t e = hipMalloc(&d, bytes);
     if (e != hipSuccess) return fail(PROPS_ENOMEM, "hipMalloc(%zu) for mechanism tables: %s", bytes, hipGetErrorString(e));
@@ -130,6 +160,8 @@ static int build_tables(props_mech_s *m)
     m->d_tab = d;
     m->off_mixd = o1;
     m->off_mixf = o2;
+    m->off_diffd = o3;
+    m->off_difff = o4;
     m->bytes = bytes;
     return PROPS_OK;
 }
@@ -234,6 +266,22 @@ int props_pr(props_mech_t m, int mode, int prec, const props_in *in, const props
     if (dev != m->device)
         return fail(PROPS_EINVAL, "props_pr: mechanism lives on device %d, current device is %d", m->device, dev);
     return launch_pr(m, mode, prec, in, out, n, status, (hipStream_t)hip_stream);
+}
+
+int props_diffusion(props_mech_t m, int prec, const double *P, const double *T, const double *Y,
+                    double *D, int64_t n, uint8_t *status, void *hip_stream)
+{
+    if (!m) return fail(PROPS_EINVAL, "props_diffusion: null mechanism");
+    if (prec != PROPS_FP64 && prec != PROPS_MIXED)
+        return fail(PROPS_EINVAL, "props_diffusion: unknown precision %d", prec);
+    if (n < 0) return fail(PROPS_EINVAL, "props_diffusion: n = %lld < 0", (long long)n);
+    if (n == 0) return PROPS_OK;
+    if (!P || !T || !Y || !D) return fail(PROPS_EINVAL, "props_diffusion: P, T, Y and D are required");
+    int dev = -1;
+    PROPS_HIP_TRY(hipGetDevice(&dev));
+    if (dev != m->device)
+        return fail(PROPS_EINVAL, "props_diffusion: mechanism lives on device %d, current device is %d", m->device, dev);
+    return launch_diffusion(m, prec, P, T, Y, D, n, status, (hipStream_t)hip_stream);
 }
 
 }  // extern "C"

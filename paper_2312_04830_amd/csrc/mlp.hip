@@ -51,6 +51,9 @@ constexpr int CELLS_PER_WAVE = 32;
 constexpr int TILE_CELLS = FWD_WAVES * CELLS_PER_WAVE;   // 256
 constexpr int MAX_BATCH = 65536;
 constexpr int SPLITW = 64;     // batch splits of the weight-gradient GEMMs
+// Outputs of the (P, T, Y) surrogate trained on their logarithm: rho, cp, mu, lambda
+// (bits 0, 2, 4, 5; h and c cross or approach zero and stay linear).
+constexpr unsigned kPTYLogMask = 0x35u;
 
 // padded (out, in) of each weight layer and its offsets in the FP32 master vector
 __host__ __device__ constexpr int lout(int l) { return l == 0 ? HID : (l == NL - 1 ? OUT_PAD : HID); }
@@ -157,6 +160,7 @@ struct FwdArgs {
     const float *bias;   // FP32 master vector (biases read from their offsets)
     const double *in_lo, *in_inv;   // [10] input box
     const double *out_lo, *out_rng; // [6] target box
+    unsigned logmask;               // bit j: output j was trained on its logarithm
     // ... or inference on raw feature-major inputs [10][n], outputs [6][n]
     const double *Xd;
     double *Yd;
@@ -386,14 +390,15 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
                                 f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
                     } else if (a.Yd) {
                         // feature-major outputs in target units: lanes of half 0 hold rows
-                        // 0..3, half 1 rows 4, 5; rows 0, 2, 4, 5 were trained on their log
+                        // 0..3, half 1 rows 4, 5; the rows flagged in logmask were trained
+                        // on their logarithm
                         const int j0 = 4 * h;
 #pragma unroll
                         for (int v = 0; v < 4; v++) {
                             const int j = j0 + v;
                             if (j < NOUT) {
                                 const double y = a.out_lo[j] + (double)acc[v] * a.out_rng[j];
-                                a.Yd[(int64_t)j * a.n + cell] = (j == 1 || j == 3) ? y : exp(y);
+                                a.Yd[(int64_t)j * a.n + cell] = (a.logmask >> j & 1u) ? exp(y) : y;
                             }
                         }
                     } else if (h == 0) {
@@ -503,7 +508,7 @@ __global__ __launch_bounds__(256) void gemm_dh_kernel(GemmArgs g)
 __global__ __launch_bounds__(256) void l1_grad_kernel(const float *y, const float *Yraw, int64_t nx,
                                                       uint64_t pa, uint64_t pc, int64_t row0, int n,
                                                       const double *out_lo, const double *out_inv,
-                                                      bf16_t *dz, float *part)
+                                                      unsigned logmask, bf16_t *dz, float *part)
 {
     __shared__ float red[256];
     const int i = blockIdx.x * 256 + threadIdx.x;
@@ -516,7 +521,7 @@ __global__ __launch_bounds__(256) void l1_grad_kernel(const float *y, const floa
             float d = 0.f;
             if (j < NOUT) {
                 double tr = (double)Yraw[(int64_t)j * nx + sidx];
-                if (j == 0 || j == 2 || j == 4 || j == 5) tr = log(tr);
+                if (logmask >> j & 1u) tr = log(tr);
                 const float t = (float)((tr - out_lo[j]) * out_inv[j]);
                 const float diff = y[(int64_t)i * OUT_PAD + j] - t;
                 s += fabsf(diff);
@@ -697,6 +702,7 @@ struct props_dnn_s {
     bf16_t *nat = nullptr, *fused = nullptr;
     double *scal = nullptr;        // device: in_lo[10], in_inv[10], out_lo[6], out_rng[6], out_inv[6]
     double in_lo[NIN], in_hi[NIN], out_lo[NOUT], out_hi[NOUT];
+    unsigned logmask = kPTYLogMask;   // outputs trained on their logarithm
     int64_t step = 0;
     int epoch = 0;
     // forward/backward scratch for one batch
@@ -1014,7 +1020,7 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
     if ((rc = launch_fwd(true, a, s))) return rc;
     const int nb = (n + 255) / 256;
     hipLaunchKernelGGL(l1_grad_kernel, dim3(nb), dim3(256), 0, s, d->y, Y, nx, pa, pc, row0, n,
-                       d->scal + 2 * NIN, d->scal + 2 * NIN + 2 * NOUT, d->dzo, d->lpart);
+                       d->scal + 2 * NIN, d->scal + 2 * NIN + 2 * NOUT, d->logmask, d->dzo, d->lpart);
     PROPS_HIP_TRY(hipGetLastError());
     // layer by layer, output to input
     const bf16_t *dzl = d->dzo;
@@ -1092,6 +1098,9 @@ int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_o
              uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s)
 {
     if (!in->P || !in->T || !in->Y) return fail(PROPS_EINVAL, "props_dnn: needs P, T and Y");
+    if (d->logmask != kPTYLogMask)
+        return fail(PROPS_EINVAL, "props_dnn: the network's log outputs (mask 0x%x) are not those of "
+                    "(rho, h, cp, c, mu, lambda); evaluate it with props_dnn_features", d->logmask);
     if (fb && fb->ns != NIN - 2)
         return fail(PROPS_EINVAL, "props_dnn: fallback mechanism has %d species, the network %d", fb->ns, NIN - 2);
     if (fb && (!fb_idx || !fb_count)) return fail(PROPS_EINVAL, "props_dnn: fallback needs index scratch");
@@ -1224,6 +1233,21 @@ int props_dnn_set_scalers(props_dnn_t d, const double *in_lo, const double *in_h
     return upload_scalers(d);
 }
 
+int props_dnn_set_log_outputs(props_dnn_t d, unsigned mask)
+{
+    if (!d) return fail(PROPS_EINVAL, "props_dnn_set_log_outputs: null network");
+    if (mask >> NOUT) return fail(PROPS_EINVAL, "props_dnn_set_log_outputs: mask 0x%x has bits beyond output %d", mask, NOUT - 1);
+    d->logmask = mask;
+    return PROPS_OK;
+}
+
+int props_dnn_get_log_outputs(props_dnn_t d, unsigned *mask)
+{
+    if (!d || !mask) return fail(PROPS_EINVAL, "props_dnn_get_log_outputs: null argument");
+    *mask = d->logmask;
+    return PROPS_OK;
+}
+
 int props_dnn(props_dnn_t d, props_mech_t fb, const props_in *in, const props_out *out, int64_t n,
               uint8_t *status, void *hip_stream)
 {
@@ -1257,6 +1281,7 @@ int props_dnn_features(props_dnn_t d, const double *X, double *Y, int64_t n, voi
     a.Wf = d->fused, a.bias = d->master;
     a.in_lo = d->scal, a.in_inv = d->scal + NIN;
     a.out_lo = d->scal + 2 * NIN, a.out_rng = d->scal + 2 * NIN + NOUT;
+    a.logmask = d->logmask;
     return launch_fwd(false, a, (hipStream_t)hip_stream);
 }
 
@@ -1301,7 +1326,7 @@ static int fit_scalers_dev(props_dnn_s *d, const float *X, const float *Y, int64
     int rc;
     if ((rc = dalloc(&part, (size_t)B * 2 * (NIN + NOUT)))) return rc;
     hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, NIN), dim3(256), 0, s, X, n, NIN, 0u, per, part);
-    hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, NOUT), dim3(256), 0, s, Y, n, NOUT, 0x35u, per,
+    hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, NOUT), dim3(256), 0, s, Y, n, NOUT, d->logmask, per,
                        part + (size_t)B * 2 * NIN);
     std::vector<double> h((size_t)B * 2 * (NIN + NOUT));
     hipError_t e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
@@ -1421,7 +1446,8 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
     return PROPS_OK;
 }
 
-// ---- checkpoint: "PROPSDNN" v1 | step | epoch | scalers | master | m | v
+// ---- checkpoint: "PROPSDNN" v2 | step | epoch | log-output mask | scalers | master | m | v
+// (v1, without the mask, loads with the (P, T, Y) surrogate's mask)
 int props_dnn_save(props_dnn_t d, const char *path)
 {
     if (!d || !path) return fail(PROPS_EINVAL, "props_dnn_save: null argument");
@@ -1434,10 +1460,12 @@ int props_dnn_save(props_dnn_t d, const char *path)
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(PROPS_EINVAL, "props_dnn_save: cannot open %s", path);
     const char magic[8] = {'P', 'R', 'O', 'P', 'S', 'D', 'N', 'N'};
-    const uint32_t ver = 1;
+    const uint32_t ver = 2;
     const uint64_t np = P;
+    const uint32_t mask = d->logmask;
     bool ok = std::fwrite(magic, 8, 1, f) == 1 && std::fwrite(&ver, 4, 1, f) == 1 && std::fwrite(&np, 8, 1, f) == 1 &&
               std::fwrite(&d->step, 8, 1, f) == 1 && std::fwrite(&d->epoch, 4, 1, f) == 1 &&
+              std::fwrite(&mask, 4, 1, f) == 1 &&
               std::fwrite(d->in_lo, sizeof(d->in_lo), 1, f) == 1 && std::fwrite(d->in_hi, sizeof(d->in_hi), 1, f) == 1 &&
               std::fwrite(d->out_lo, sizeof(d->out_lo), 1, f) == 1 && std::fwrite(d->out_hi, sizeof(d->out_hi), 1, f) == 1 &&
               std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
@@ -1462,9 +1490,11 @@ int props_dnn_load(const char *path, props_dnn_t *out)
     }
     const size_t P = kLay::total;
     std::vector<float> buf(3 * P);
+    uint32_t mask = kPTYLogMask;
     bool ok = std::fread(magic, 8, 1, f) == 1 && std::memcmp(magic, "PROPSDNN", 8) == 0 && std::fread(&ver, 4, 1, f) == 1 &&
-              ver == 1 && std::fread(&np, 8, 1, f) == 1 && np == P && std::fread(&d->step, 8, 1, f) == 1 &&
-              std::fread(&d->epoch, 4, 1, f) == 1 && std::fread(d->in_lo, sizeof(d->in_lo), 1, f) == 1 &&
+              (ver == 1 || ver == 2) && std::fread(&np, 8, 1, f) == 1 && np == P && std::fread(&d->step, 8, 1, f) == 1 &&
+              std::fread(&d->epoch, 4, 1, f) == 1 && (ver == 1 || std::fread(&mask, 4, 1, f) == 1) &&
+              (mask >> NOUT) == 0 && std::fread(d->in_lo, sizeof(d->in_lo), 1, f) == 1 &&
               std::fread(d->in_hi, sizeof(d->in_hi), 1, f) == 1 && std::fread(d->out_lo, sizeof(d->out_lo), 1, f) == 1 &&
               std::fread(d->out_hi, sizeof(d->out_hi), 1, f) == 1 && std::fread(buf.data(), 4, buf.size(), f) == buf.size();
     std::fclose(f);
@@ -1472,6 +1502,7 @@ int props_dnn_load(const char *path, props_dnn_t *out)
         props_dnn_destroy(d);
         return fail(PROPS_EINVAL, "props_dnn_load: %s is not a valid checkpoint", path);
     }
+    d->logmask = mask;
     if (hipMemcpy(d->master, buf.data(), P * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d->m, buf.data() + P, P * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d->v, buf.data() + 2 * P, P * 4, hipMemcpyHostToDevice) != hipSuccess ||

@@ -80,6 +80,20 @@ struct MixTab {
     R ESM[NS][NS];   // eps_ij sigma_ij^2 sqrt(M_ij), upper-triangular, doubled off-diagonal
 };
 
+// Mixture-averaged diffusion (Chapman-Enskog), per unordered species pair p = (i < j),
+// upper triangle in row-major order.  The binary coefficient is
+//   D_ij = T^1.5 / (P G_ij Omega_D(T / eps_ij)),  G_ij = (16/3) sigma_ij^2 sqrt(pi m_ij / (2 k^3)),
+// m_ij the reduced molecular mass.  With Neufeld's fit of Omega_D the product G_ij Omega_D is
+//   c0 T^-0.15610 + c1 exp(x1 T) + c2 exp(x2 T) + c3 exp(x3 T).
+// Pairs with a padding species hold zeros.
+template <typename R, int NS>
+struct DiffTab {
+    static constexpr int NP = (NS * (NS - 1) / 2 > 0) ? NS * (NS - 1) / 2 : 1;
+    R c0[NP];                // 1.06036 G_ij eps_ij^0.15610
+    R c1[NP], c2[NP], c3[NP];  // 0.19300 G_ij, 1.03587 G_ij, 1.76474 G_ij
+    R x1[NP], x2[NP], x3[NP];  // -0.47635/eps_ij, -1.52996/eps_ij, -3.89411/eps_ij  [1/K]
+};
+
 }  // namespace props
 
 // ---------------------------------------------------------------- handles
@@ -89,8 +103,9 @@ struct props_mech_s {
     int device = 0;
     int maxit = 100;
     double rtol = 1e-10;
-    void *d_tab = nullptr;  // one allocation: ThermoTab | MixTab<double> | MixTab<float>
-    size_t off_mixd = 0, off_mixf = 0, bytes = 0;
+    // one allocation: ThermoTab | MixTab<double> | MixTab<float> | DiffTab<double> | DiffTab<float>
+    void *d_tab = nullptr;
+    size_t off_mixd = 0, off_mixf = 0, off_diffd = 0, off_difff = 0, bytes = 0;
     props_species_desc sp[PROPS_MAX_SPECIES];
     double kij[PROPS_MAX_SPECIES * PROPS_MAX_SPECIES];
 };
@@ -106,6 +121,9 @@ int launch_pr_indirect(const props_mech_s *m, int mode, int prec, const props_in
                        uint8_t *status, uint8_t st_or, hipStream_t stream);
 // The surrogate with caller-provided fallback scratch (idx: n ints, count: 1 int), so
 // that concurrent evaluations on different streams never share scratch (mlp.hip).
+// Mixture-averaged diffusion coefficients (diffusion.hip).
+int launch_diffusion(const props_mech_s *m, int prec, const double *P, const double *T,
+                     const double *Y, double *D, int64_t n, uint8_t *status, hipStream_t stream);
 int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_out *out, int64_t n,
              uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s);
 }  // namespace props

@@ -114,3 +114,56 @@ def test_dnn_features_equal_props_dnn_on_the_same_inputs(props, sp8):
     g = Yd.cpu().numpy()
     for j, k in enumerate(KEYS6):
         assert np.array_equal(g[j], outs[k].cpu().numpy()), k
+
+
+@pytest.mark.parametrize("mask", [0x3F, 0x00, 0x0A])
+def test_dnn_features_log_mask_match_bf16_oracle(props, mask):
+    """Networks trained on other targets choose which outputs are logarithms: inference
+    on raw features applies exp to exactly the flagged outputs."""
+    import torch
+    rng = np.random.default_rng(20 + mask)
+    n = 3000
+    X = np.zeros((10, n))
+    X[0] = rng.uniform(-6e6, 3e6, n)
+    X[1] = rng.uniform(9.9e6, 1.01e7, n)
+    X[2] = rng.uniform(-4.0, 0.0, n)
+    L = np.exp(rng.normal(-14.0, 1.5, (6, n)))     # positive, spanning decades
+    flags = omlp.log_flags(mask)
+    ilo, ihi, olo, ohi = omlp.fit_scalers(X.T, L.T, flags)
+    params = [(W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64))
+              for W, b in omlp.init_params(np.random.default_rng(mask))]
+    net = props.Network(seed=5)
+    assert net.get_log_outputs() == 0x35
+    net.set_log_outputs(mask)
+    assert net.get_log_outputs() == mask
+    for l, (W, b) in enumerate(params):
+        net.set_layer(l, W.astype(np.float32), b.astype(np.float32))
+    net.set_scalers(ilo, ihi, olo, ohi)
+    Yd = torch.empty((6, n), dtype=torch.float64, device="cuda:0")
+    net.features(dev(X), Yd, n)
+    torch.cuda.synchronize()
+    g = Yd.cpu().numpy().T
+    ys, _ = omlp.forward_bf16(params, omlp.scale_inputs(X.T, ilo, ihi))
+    gs = omlp.transform_outputs(g, olo, ohi, flags)
+    d = np.abs(gs - ys)
+    assert d.max() < 1e-2 and np.sqrt((d ** 2).mean()) < 1e-3
+    for j, lg in enumerate(flags):
+        if lg:
+            assert np.all(g[:, j] > 0)
+
+
+def test_log_mask_rules_and_checkpoint(props, tmp_path):
+    import torch
+    net = props.Network(seed=6)
+    with pytest.raises(props.PropsError):
+        net.set_log_outputs(0x40)                  # beyond output 5
+    net.set_log_outputs(0x3F)
+    z = torch.ones(4, dtype=torch.float64, device="cuda:0")
+    Yz = torch.full((8, 4), 0.125, dtype=torch.float64, device="cuda:0")
+    out = {"rho": torch.empty(4, dtype=torch.float64, device="cuda:0")}
+    with pytest.raises(props.PropsError):
+        net({"P": z, "T": z, "Y": Yz}, out, 4)     # props_dnn needs the (P, T, Y) mask
+    path = str(tmp_path / "net.ckpt")
+    net.save(path)
+    back = props.Network.load(path)
+    assert back.get_log_outputs() == 0x3F
