@@ -12,8 +12,8 @@
 // names, is not applied: its correlation chart is not reproduced here.
 //
 // Each unordered pair is visited once and its term feeds both species' sums.  Per cell:
-// one log and one exp for T^-0.15610, three exponentials per pair; FP64 uses the device
-// library's exp, the mixed variant the hardware v_exp_f32.  Memory: P, T, Y read and D
+// one log and one exp for T^-0.15610, three exponentials per pair; FP64 uses the
+// branch-free exp of fastmath.hpp, the mixed variant the hardware v_exp_f32.  Memory: P, T, Y read and D
 // written once, species-major and unit-stride across a wavefront; the pair table (a few
 // hundred values) comes through the scalar cache.
 #include <cmath>
@@ -28,7 +28,7 @@ namespace {
 
 struct D64 {
     using R = double;
-    static __device__ __forceinline__ R exp_(R x) { return exp(x); }
+    static __device__ __forceinline__ R exp_(R x) { return fm::exp(x); }
     static __device__ __forceinline__ R log_(R x) { return fm::log(x); }
 };
 

@@ -34,14 +34,14 @@
 namespace props {
 
 // ------------------------------------------------------------------ precision policies
-// Double precision: the device library's exp and expm1 (cheapest measured in our gfx950
-// build), the lean log and refined reciprocals of fastmath.hpp (a few ulp; outputs stay
-// within 1e-15 relative of correctly rounded maths).
+// Double precision: the branch-free exp, the lean log and the refined reciprocal of
+// fastmath.hpp, the device library's expm1 (a few ulp; outputs stay within 1e-15 relative
+// of correctly rounded maths).
 struct P64 {
     using R = double;
     static __device__ __forceinline__ R sqrt_(R x) { return sqrt(x); }
     static __device__ __forceinline__ R log_(R x) { return fm::log(x); }
-    static __device__ __forceinline__ R exp_(R x) { return exp(x); }
+    static __device__ __forceinline__ R exp_(R x) { return fm::exp(x); }
     static __device__ __forceinline__ R expm1_(R x) { return expm1(x); }
     static __device__ __forceinline__ R cbrt_(R x) { return cbrt(x); }
     static __device__ __forceinline__ R div(R a, R b) { return a * fm::rcp(b); }

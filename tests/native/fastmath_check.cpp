@@ -32,7 +32,23 @@ int main()
         double z = 1.0 + 1e-6 * T;
         e_log = std::fmax(e_log, ulp_err(props::fm::log(z), logl((long double)z)));
     }
+    // exp: normal results, the kernels' arguments (exponents of collision-integral and
+    // Chung terms, -800..0 and small positives), and subnormal results by absolute error
+    double e_exp = 0, e_sub = 0;
+    std::uniform_real_distribution<double> ue(-708.0, 709.0);
+    for (int i = 0; i < 2000000; i++) {
+        double x = ue(g);
+        e_exp = std::fmax(e_exp, ulp_err(props::fm::exp(x), expl((long double)x)));
+    }
+    for (double x = -60.0; x < 40.0; x += 1.37e-4)
+        e_exp = std::fmax(e_exp, ulp_err(props::fm::exp(x), expl((long double)x)));
+    for (double x = -745.0; x < -708.5; x += 1e-3)
+        e_sub = std::fmax(e_sub, std::fabs((double)((long double)props::fm::exp(x) - expl((long double)x))) / 4.9406564584124654e-324);
     std::printf("log_max_ulp %.3f\n", e_log);
+    std::printf("exp_max_ulp %.3f exp_sub_max_denorm_ulp %.3f\n", e_exp, e_sub);
+    std::printf("exp_under_zero %d exp_over_inf %d exp_nan %d exp_zero_one %d\n",
+                (int)(props::fm::exp(-800.0) == 0.0), (int)std::isinf(props::fm::exp(710.0)),
+                (int)std::isnan(props::fm::exp(NAN)), (int)(props::fm::exp(0.0) == 1.0));
     std::printf("log_neg_nan %d log_zero_nan %d\n", (int)std::isnan(props::fm::log(-1.0)),
                 (int)std::isnan(props::fm::log(0.0)));
     return 0;

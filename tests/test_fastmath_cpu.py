@@ -1,4 +1,4 @@
-"""Host build of the kernels' double-precision log (fastmath.hpp): error in units of the
+"""Host build of the kernels' double-precision log and exp (fastmath.hpp): error in units of the
 last place against long-double libm over seeded arguments (CPU only; the device build runs
 the same arithmetic, and the GPU parity tests cover it end to end)."""
 import os
@@ -28,3 +28,13 @@ def test_log_within_two_ulp(report):
 
 def test_log_of_non_positive_is_nan(report):
     assert report["log_neg_nan"] == 1 and report["log_zero_nan"] == 1
+
+
+def test_exp_within_two_ulp(report):
+    assert report["exp_max_ulp"] <= 2.0
+    assert report["exp_sub_max_denorm_ulp"] <= 1.0
+
+
+def test_exp_limits(report):
+    assert report["exp_under_zero"] == 1 and report["exp_over_inf"] == 1
+    assert report["exp_nan"] == 1 and report["exp_zero_one"] == 1
