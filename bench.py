@@ -248,6 +248,29 @@ def diffusion_section(props, mech, n, Pd, Td, Yd, stream, steps, ncopy=3):
                       "max_rel_vs_fp64": rel}}
 
 
+def shard_section(props, mech, ins0, n, stream, steps, parts=8, ncopy=3):
+    """One GPU's share when the field is split over `parts` GPUs: the headline launch on a
+    contiguous slab of n/parts cells (cells are independent; no exchange step)."""
+    import torch
+    m = n // parts
+    ins = [{k: (v[:, :m] if v.dim() == 2 else v[:m]).contiguous().clone() for k, v in ins0.items()}
+           for _ in range(ncopy)]
+    outs = [{k: torch.empty(m, dtype=torch.float64, device=ins0["rho"].device)
+             for k in ("T", "P", "Z", "rho", "h", "e", "cp", "c", "mu", "lambda")} for _ in range(ncopy)]
+    for i in range(3):
+        props.pr(mech, props.RHOEY, props.FP64, ins[i % ncopy], outs[i % ncopy], m, stream=stream)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for i in range(steps):
+        props.pr(mech, props.RHOEY, props.FP64, ins[i % ncopy], outs[i % ncopy], m, stream=stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    return {"workload": f"1/{parts} of the field ({m} cells, a contiguous slab), same launch as the headline",
+            "cells": m, "ms_per_step": ms, "value": m / (ms * 1e-3), "unit": "cells/s"}
+
+
 def hpy_section(props, mech, n, h0, Pd, Yd, Tg, o_rhoe, stream, steps, ncopy=3):
     """(h, P, Y) mode, the pressure-based solver's state, on the same field: T by Newton
     with the cubic in every evaluation, all outputs plus psi, alpha and h_i/RT."""
@@ -414,8 +437,10 @@ def dnn_section(props, synth, mech, sp, epochs, n_train, res, reps=5):
 
 def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps=5):
     """The paper's own surrogate inputs (Section 4.1): (h, P, Box-Cox Bilger Z) -> T, rho, mu,
-    psi, thermal diffusivity and h_CH4/RT, one network with six outputs, trained on PR labels
-    and compared with the (h, P, Y) Newton path on a res^3 field."""
+    psi, thermal diffusivity and h_CH4/RT (first network), D_i of six species (second, log
+    outputs) and h_i/RT of six more species (third, linear outputs), each trained on labels
+    from the library's FP64 paths and compared with the (h, P, Y) Newton path on a res^3
+    field."""
     import torch
     dev = torch.device("cuda:0")
     ns = len(sp)
@@ -436,6 +461,8 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
     Dlab = torch.empty((ns, n_train), dtype=torch.float64, device=dev)
     props.diffusion(mech, props.FP64, Pd, Td, Yd, Dlab, n_train)
     LD = Dlab[:6].float().contiguous()
+    # a third network for h_i/RT of the next six species (linear outputs: they cross zero)
+    LH = hrt[1:7].float().contiguous()
     Xf = X.float().contiguous()
     bad_labels = int((st != 0).sum())
     del X, lab, hrt, Pd, Td, Yd, Dlab
@@ -445,7 +472,10 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
     netD = props.Network(seed=2026)
     netD.set_log_outputs(0x3F)
     repD, lossesD = netD.train(Xf, LD, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=8)
-    del Xf, L, LD
+    netH = props.Network(seed=2027)
+    netH.set_log_outputs(0)
+    repH, lossesH = netH.train(Xf, LH, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=9)
+    del Xf, L, LD, LH
     # inference field and the (h, P, Y) reference
     Pf, Tf, Yf = synth.flame_field(res, seed=4)
     n = Tf.size
@@ -479,16 +509,25 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
     ms_dnn = timeit(surrogate)
     YD = torch.empty((6, n), dtype=torch.float64, device=dev)
     ms_dnnD = timeit(lambda: netD.features(X, YD, n))
+    YH = torch.empty((6, n), dtype=torch.float64, device=dev)
+    ms_dnnH = timeit(lambda: netH.features(X, YH, n))
     ms_hpy64 = timeit(lambda: props.pr(mech, props.HPY, props.FP64, hin, ref, n))
     out32 = {k: torch.empty_like(v) for k, v in ref.items()}
     ms_hpy32 = timeit(lambda: props.pr(mech, props.HPY, props.MIXED, hin, out32, n))
     props.pr(mech, props.HPY, props.FP64, hin, ref, n)
     surrogate()
     netD.features(X, YD, n)
+    netH.features(X, YH, n)
     Dref = torch.empty((ns, n), dtype=torch.float64, device=dev)
     ms_diff64 = timeit(lambda: props.diffusion(mech, props.FP64, Pd, ref["T"], Yd, Dref, n))
     torch.cuda.synchronize()
     errD = {sp[i]["name"]: _rel_stats(YD[i], Dref[i], "D") for i in range(6)}
+    errH = {}
+    for j in range(6):
+        r = ref["hRT"][1 + j]
+        d = (YH[j] - r).abs() / (r.abs() + 1.0)
+        r2 = 1.0 - float(((YH[j] - r) ** 2).sum() / ((r - r.mean()) ** 2).sum())
+        errH[sp[1 + j]["name"]] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt()), "r2": r2}
     refs = {"rho": ref["rho"], "T": ref["T"], "mu": ref["mu"], "hRT0": ref["hRT"][0], "psi": ref["psi"],
             "alpha": ref["alpha"]}
     err = {}
@@ -515,7 +554,13 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
                 "pr_diffusion_fp64_cells_per_s": n / (ms_diff64 * 1e-3),
                 "rel_err_vs_chapman_enskog_at_hpy_T": errD,
                 "train": {"seconds": repD["seconds"], "loss_first": float(lossesD[0]),
-                          "loss_last": float(lossesD[-1])}}}
+                          "loss_last": float(lossesD[-1])}},
+            "enthalpy_net": {
+                "workload": "same features -> h_i/RT of O2, CO2, H2O, CO, H2, OH (linear outputs), third network",
+                "value": n / (ms_dnnH * 1e-3), "unit": "cells/s", "ms": ms_dnnH,
+                "rel_err_vs_pr_hpy_fp64": errH,
+                "train": {"seconds": repH["seconds"], "loss_first": float(lossesH[0]),
+                          "loss_last": float(lossesH[-1])}}}
 
 
 def serving_section(props, synth, mech, net, n_sub=64, reqs_per_sub=50, loads=(0.5, 0.8)):
@@ -736,6 +781,8 @@ def main():
         ms_ng, _ = timed(props.FP64, max(10, args.steps // 2), 2)
         ins = save
         rec["fp64_no_guess"] = {"value": n / (ms_ng * 1e-3), "ms_per_step": ms_ng}
+        rec["shard_1_of_8"] = shard_section(props, mech, ins[0], n, stream, args.steps)
+        log(f"1/8 shard: {rec['shard_1_of_8']['ms_per_step']:.4f} ms, {rec['shard_1_of_8']['value']:.3e} cells/s")
         rec["pty"] = pty_section(props, mech, n, Pd, dt(T), Yd, stream, max(10, args.steps // 2))
         log(f"(P,T,Y) thermo: FP64 {rec['pty']['fp64']['ms_per_step']:.4f} ms, "
             f"mixed {rec['pty']['mixed']['ms_per_step']:.4f} ms")
