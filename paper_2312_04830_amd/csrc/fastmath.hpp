@@ -19,11 +19,6 @@
 
 #include <cmath>
 
-#if defined(__HIP_DEVICE_COMPILE__)
-#define FM_QUAL __device__ __forceinline__
-#else
-#define FM_QUAL inline
-#endif
 #if defined(__HIPCC__)
 #define FM_HD __host__ __device__
 #else
