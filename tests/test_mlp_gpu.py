@@ -88,18 +88,25 @@ def test_forward_matches_bf16_oracle(props, orc, sp8):
     assert d64.max() < 5e-2
 
 
-def test_gradient_matches_bf16_oracle(props, orc, sp8):
+@pytest.mark.parametrize("mask", [0x35, 0x3F, 0x00])
+def test_gradient_matches_bf16_oracle(props, orc, sp8, mask):
+    """The L1 gradient on the scaled targets, for the default log outputs (rho, cp, mu,
+    lambda) and for networks that log-transform all or none of their outputs."""
     X, L = labelled_states(orc, sp8, 4096, seed=32)
-    ilo, ihi, olo, ohi = omlp.fit_scalers(X.T, L.T)
+    if mask == 0x3F:
+        L = np.abs(L) + 1.0                       # every target positive
+    flags = omlp.log_flags(mask)
+    ilo, ihi, olo, ohi = omlp.fit_scalers(X.T, L.T, flags)
     params = rounded_params(omlp.init_params(np.random.default_rng(6)))
     net = props.Network(seed=2)
+    net.set_log_outputs(mask)
     set_params(net, params)
     net.set_scalers(ilo, ihi, olo, ohi)
     n = X.shape[1]
     Xd, Ld = dev(X.astype(np.float32)), dev(L.astype(np.float32))
     loss, g = net.grad(Xd, Ld, n)
     xs = omlp.scale_inputs(X.astype(np.float32).astype(np.float64).T, ilo, ihi)
-    t = omlp.transform_outputs(L.astype(np.float32).astype(np.float64).T, olo, ohi)
+    t = omlp.transform_outputs(L.astype(np.float32).astype(np.float64).T, olo, ohi, flags)
     y, cache = omlp.forward_bf16(params, xs)
     grads = omlp.backward_bf16(params, cache, y, t)
     y64, c64 = omlp.forward(params, xs)
@@ -116,9 +123,25 @@ def test_gradient_matches_bf16_oracle(props, orc, sp8):
         cos = float((gw * dW).sum() / (np.linalg.norm(gw) * np.linalg.norm(dW)))
         rel64 = np.linalg.norm(gw - dW64) / np.linalg.norm(dW64)
         relb = np.linalg.norm(gb - db) / max(np.linalg.norm(db), 1e-30)
-        print(f"[mlp grad] layer {l}: |dW-dW_bf16|/|dW| {rel:.2e} cos {cos:.6f} vs fp64 {rel64:.2e} db {relb:.2e}")
+        print(f"[mlp grad mask {mask:#x}] layer {l}: |dW-dW_bf16|/|dW| {rel:.2e} cos {cos:.6f} vs fp64 {rel64:.2e} db {relb:.2e}")
         assert rel < 2e-2 and cos > 0.999 and relb < 2e-2
     assert off == g.size
+
+
+def test_training_fits_the_box_of_the_log_targets(props):
+    """train_dnn fits the output box on the transformed targets: with every output flagged,
+    the box is [log min, log max] of the (float) targets."""
+    rng = np.random.default_rng(44)
+    n = 2 * 4096 + 77
+    X = rng.uniform(0, 1, (10, n)).astype(np.float32)
+    Yl = np.exp(rng.normal(-12.0, 2.0, (6, n))).astype(np.float32)
+    net = props.Network(seed=4)
+    net.set_log_outputs(0x3F)
+    net.train(dev(X), dev(Yl), n, epochs=1, batch=4096, lr=1e-3, lr_min=1e-4, seed=3)
+    ilo, ihi, olo, ohi = net.get_scalers()
+    T = np.log(Yl.astype(np.float64))
+    assert np.allclose(olo, T.min(1), rtol=1e-14, atol=0) and np.allclose(ohi, T.max(1), rtol=1e-14, atol=0)
+    assert np.array_equal(ilo, X.astype(np.float64).min(1)) and np.array_equal(ihi, X.astype(np.float64).max(1))
 
 
 def test_training_resume_is_bitwise(props, tmp_path):
