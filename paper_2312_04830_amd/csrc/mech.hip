@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "props_internal.hpp"
+#include "trace.hpp"
 
 namespace props {
 
@@ -178,6 +179,7 @@ const char *props_version(void) { return "props-mi355x 0.1 (gfx950)"; }
 
 int props_mech_create(const props_species_desc *sp, int ns, const double *kij, props_mech_t *out)
 {
+    ApiRange range_("props_mech_create");
     if (!out) return fail(PROPS_EINVAL, "props_mech_create: out is NULL");
     *out = nullptr;
     if (!sp) return fail(PROPS_EINVAL, "props_mech_create: species array is NULL");
@@ -251,6 +253,7 @@ int props_mech_set_newton(props_mech_t m, int max_iter, double rtol)
 int props_pr(props_mech_t m, int mode, int prec, const props_in *in, const props_out *out,
              int64_t n, uint8_t *status, void *hip_stream)
 {
+    ApiRange range_("props_pr");
     if (!m || !in || !out) return fail(PROPS_EINVAL, "props_pr: null mechanism, input or output");
     if (mode != PROPS_PTY && mode != PROPS_RHOEY && mode != PROPS_HPY)
         return fail(PROPS_EINVAL, "props_pr: unknown mode %d", mode);
@@ -271,6 +274,7 @@ int props_pr(props_mech_t m, int mode, int prec, const props_in *in, const props
 int props_diffusion(props_mech_t m, int prec, const double *P, const double *T, const double *Y,
                     double *D, int64_t n, uint8_t *status, void *hip_stream)
 {
+    ApiRange range_("props_diffusion");
     if (!m) return fail(PROPS_EINVAL, "props_diffusion: null mechanism");
     if (prec != PROPS_FP64 && prec != PROPS_MIXED)
         return fail(PROPS_EINVAL, "props_diffusion: unknown precision %d", prec);

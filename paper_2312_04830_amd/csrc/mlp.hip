@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "props_internal.hpp"
+#include "trace.hpp"
 
 namespace props {
 
@@ -1251,6 +1252,7 @@ int props_dnn_get_log_outputs(props_dnn_t d, unsigned *mask)
 int props_dnn(props_dnn_t d, props_mech_t fb, const props_in *in, const props_out *out, int64_t n,
               uint8_t *status, void *hip_stream)
 {
+    ApiRange range_("props_dnn");
     if (!d || !in || !out) return fail(PROPS_EINVAL, "props_dnn: null network, input or output");
     if (n < 0) return fail(PROPS_EINVAL, "props_dnn: n < 0");
     if (n == 0) return PROPS_OK;
@@ -1272,6 +1274,7 @@ int props_dnn(props_dnn_t d, props_mech_t fb, const props_in *in, const props_ou
 
 int props_dnn_features(props_dnn_t d, const double *X, double *Y, int64_t n, void *hip_stream)
 {
+    ApiRange range_("props_dnn_features");
     if (!d || !X || !Y) return fail(PROPS_EINVAL, "props_dnn_features: null network, input or output");
     if (n < 0) return fail(PROPS_EINVAL, "props_dnn_features: n < 0");
     if (n == 0) return PROPS_OK;
@@ -1288,6 +1291,7 @@ int props_dnn_features(props_dnn_t d, const double *X, double *Y, int64_t n, voi
 int props_features_hpz(const int *atoms, const double *W, int ns, int fuel, int oxidizer, double bc_lambda,
                        const double *h, const double *P, const double *Y, int64_t n, double *X, void *hip_stream)
 {
+    ApiRange range_("props_features_hpz");
     if (!atoms || !W || !h || !P || !Y || !X) return fail(PROPS_EINVAL, "props_features_hpz: null argument");
     if (ns < 1 || ns > PROPS_MAX_SPECIES) return fail(PROPS_EINVAL, "props_features_hpz: ns = %d", ns);
     if (fuel < 0 || fuel >= ns || oxidizer < 0 || oxidizer >= ns)
@@ -1349,6 +1353,7 @@ static int fit_scalers_dev(props_dnn_s *d, const float *X, const float *Y, int64
 int props_dnn_grad(props_dnn_t d, const float *X, const float *Y, int64_t n, float *grad, float *loss,
                    void *hip_stream)
 {
+    ApiRange range_("props_dnn_grad");
     if (!d || !X || !Y || !grad) return fail(PROPS_EINVAL, "props_dnn_grad: null argument");
     if (n < 1 || n > MAX_BATCH) return fail(PROPS_EINVAL, "props_dnn_grad: need 1 <= n <= %d", MAX_BATCH);
     hipStream_t s = (hipStream_t)hip_stream;
@@ -1376,6 +1381,7 @@ int props_dnn_grad(props_dnn_t d, const float *X, const float *Y, int64_t n, flo
 int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const props_train_cfg *cfg,
               props_train_report *rep, void *hip_stream)
 {
+    ApiRange range_("train_dnn");
     if (!d || !X || !Y || !cfg) return fail(PROPS_EINVAL, "train_dnn: null argument");
     if (n < 1) return fail(PROPS_EINVAL, "train_dnn: n < 1");
     const int batch = cfg->batch ? cfg->batch : MAX_BATCH;
@@ -1450,6 +1456,7 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
 // (v1, without the mask, loads with the (P, T, Y) surrogate's mask)
 int props_dnn_save(props_dnn_t d, const char *path)
 {
+    ApiRange range_("props_dnn_save");
     if (!d || !path) return fail(PROPS_EINVAL, "props_dnn_save: null argument");
     const size_t P = kLay::total;
     std::vector<float> buf(3 * P);
@@ -1475,6 +1482,7 @@ int props_dnn_save(props_dnn_t d, const char *path)
 
 int props_dnn_load(const char *path, props_dnn_t *out)
 {
+    ApiRange range_("props_dnn_load");
     if (!path || !out) return fail(PROPS_EINVAL, "props_dnn_load: null argument");
     *out = nullptr;
     FILE *f = std::fopen(path, "rb");

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "props_internal.hpp"
+#include "trace.hpp"
 
 namespace {
 
@@ -319,6 +320,7 @@ extern "C" {
 
 int serve_create(const props_serve_cfg *cfg, props_mech_t mech, props_dnn_t dnn, props_server_t *out)
 {
+    ApiRange range_("serve_create");
     if (!out) return fail(PROPS_EINVAL, "serve_create: out is NULL");
     *out = nullptr;
     if (!cfg) return fail(PROPS_EINVAL, "serve_create: cfg is required");
@@ -373,6 +375,7 @@ int serve_create(const props_serve_cfg *cfg, props_mech_t mech, props_dnn_t dnn,
 
 int serve_submit(props_server_t S, const props_request *req, uint64_t *ticket)
 {
+    ApiRange range_("serve_submit");
     if (!S || !req || !ticket) return fail(PROPS_EINVAL, "serve_submit: null argument");
     const props_request &q = *req;
     if (q.n <= 0) return fail(PROPS_EINVAL, "serve_submit: n = %lld", (long long)q.n);
@@ -405,6 +408,7 @@ int serve_submit(props_server_t S, const props_request *req, uint64_t *ticket)
 
 int serve_wait(props_server_t S, uint64_t ticket, int64_t timeout_us, props_result *res)
 {
+    ApiRange range_("serve_wait");
     if (!S) return fail(PROPS_EINVAL, "serve_wait: null server");
     std::unique_lock<std::mutex> lk(S->mu);
     auto it = S->reqs.find(ticket);
@@ -465,6 +469,7 @@ int serve_stats(props_server_t S, props_serve_stats *st)
 
 void serve_destroy(props_server_t S)
 {
+    ApiRange range_("serve_destroy");
     if (!S) return;
     {
         std::lock_guard<std::mutex> lk(S->mu);

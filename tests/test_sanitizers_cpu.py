@@ -65,7 +65,8 @@ def test_serving_scheduler_under_thread_sanitizer(tmp_path):
         assert rc == 0, out
         objs.append(obj)
     exe = str(tmp_path / "serve_tsan")
-    rc, out = _run([HIPCC, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=thread", "-o", exe] + objs + ["-lpthread"])
+    rc, out = _run([HIPCC, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=thread", "-o", exe] + objs +
+                   ["-lpthread", "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"])
     assert rc == 0, out
     env = dict(os.environ, TSAN_OPTIONS="halt_on_error=1 exitcode=66")
     rc, out = _run([exe], timeout=300, env=env)
