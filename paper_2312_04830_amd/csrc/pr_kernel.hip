@@ -322,7 +322,8 @@ __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restri
 // discriminant is positive, else the largest trigonometric root 2 r cos(phi/3)), polished by
 // Newton on the cubic, and the cubic is deflated by it to a quadratic whose two roots, when
 // real, are the smaller pair (each polished on the full cubic).  One transcendental chain
-// per cell instead of three cosines and three polishes.
+// per cell instead of three cosines and three polishes; the trigonometric start is taken
+// in single precision and polished to double.
 struct Cubic {
     double c2, c1, c0;
     __device__ __forceinline__ double f(double x) const { return ((x + c2) * x + c1) * x + c0; }
@@ -362,10 +363,16 @@ __device__ __forceinline__ int cubic_roots(double A, double B, double z[3])
         const double r = sqrt(-p * (1.0 / 3.0));
         double arg = (r > 0.0) ? -0.5 * q * fm::rcp(r * r * r) : 0.0;
         arg = fmin(1.0, fmax(-1.0, arg));
-        zx = 2.0 * r * cos(acos(arg) * (1.0 / 3.0)) - sh;
+        // cos(arccos(arg)/3) in single precision (the hardware cosine: 26 instructions
+        // against 241 for the double-precision pair) is a start good to ~1e-6; the Newton
+        // polish below carries it to double.  Where the two larger roots nearly coincide
+        // (arg -> -1) arccos amplifies the rounding of arg, and double precision is kept.
+        const double c = (arg > -0.999) ? (double)__cosf(acosf((float)arg) * (1.0f / 3.0f))
+                                        : cos(acos(arg) * (1.0 / 3.0));
+        zx = 2.0 * r * c - sh;
         nr = 3;
     }
-    zx = cb.polish(cb.polish(zx));
+    zx = cb.polish(cb.polish(cb.polish(zx)));
     z[2] = zx;
     if (nr == 3) {
         // Z^3 + c2 Z^2 + c1 Z + c0 = (Z - zx)(Z^2 + b1 Z + b0)
