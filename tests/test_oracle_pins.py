@@ -194,6 +194,37 @@ def test_gibbs_energy_equal_at_maxwell_psat(orc):
     assert abs(gl - gv) < 1e-8
 
 
+def test_gibbs_tie_flag_at_the_switch_pressure(orc):
+    """Bisecting P for the root switch of pure O2 at 120 K ends at two adjacent doubles; there
+    the two residual Gibbs energies agree to rounding, so the tie flag is set and the
+    vapour-like root taken; a part in 1e6 away there is no tie.  The switch pressure is the
+    Maxwell one."""
+    s = synth.load_species(["O2"])
+    m = orc.Mech(s)
+    T = 120.0
+    lo, hi = 1.0e6, 2.0e6                            # vapour-like at lo, liquid-like at hi
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if mid in (lo, hi):
+            break
+        z = m.state_PT([mid], [T], [[1.0]], transport=False)
+        if z["Z"][0] > 0.3:
+            lo = mid
+        else:
+            hi = mid
+    assert np.nextafter(lo, np.inf) == hi
+    at = m.state_PT([lo, hi], [T, T], [[1.0, 1.0]], transport=False)
+    # the switch is the upper edge of the tie band: a tie (vapour-like root) below it,
+    # the liquid-like root without a tie above it
+    assert at["status"][0] & orc.GIBBS_TIE and at["Z"][0] > 0.3
+    assert at["status"][1] & orc.GIBBS_TIE == 0 and at["Z"][1] < 0.3
+    off = m.state_PT([lo * (1 - 1e-6), hi * (1 + 1e-6)], [T, T], [[1.0, 1.0]], transport=False)
+    assert np.all(off["status"] & orc.GIBBS_TIE == 0)
+    assert off["Z"][0] > 0.3 and off["Z"][1] < 0.3
+    am, _, _, bm = m.mix(np.array([1.0]), T)
+    assert lo == pytest.approx(_maxwell_psat(am, bm, T), rel=1e-9)
+
+
 # ---------------------------------------------------------------------------------------
 # Ideal-gas parts (NASA-7)
 # ---------------------------------------------------------------------------------------

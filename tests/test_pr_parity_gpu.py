@@ -171,6 +171,41 @@ def test_three_root_gibbs_selection(props, orc):
         assert max(worst.values()) <= 1.0, worst
 
 
+def test_gibbs_tie_at_the_saturation_pressure(props, orc):
+    """Pure O2 at 120 K: at the pressure where the two residual Gibbs energies cross (found
+    by bisection on their difference with the oracle) both sides flag a tie and take the
+    vapour-like root; five parts in 1e12 to either side neither flags one, and the roots
+    differ (vapour below, liquid above)."""
+    sp = synth.load_species(["O2"])
+    om = orc.Mech(sp)
+    T = 120.0
+    am, _, _, bm = om.mix(np.array([1.0]), T)
+    R = 8.31446261815324
+
+    def dg(P):
+        A, B = am * P / (R * T) ** 2, bm * P / (R * T)
+        r = orc.cubic_roots(A, B)
+        return orc.gdep_RT(r[0], A, B) - orc.gdep_RT(r[-1], A, B)
+
+    lo, hi = 1.0e6, 1.05e6
+    assert dg(lo) > 0 > dg(hi)
+    while np.nextafter(lo, np.inf) < hi:
+        mid = 0.5 * (lo + hi)
+        if mid in (lo, hi):
+            break
+        lo, hi = (mid, hi) if dg(mid) > 0 else (lo, mid)
+    P = np.array([lo, lo * (1 - 5e-12), lo * (1 + 5e-12)])
+    Tv = np.full(3, T)
+    Y = np.ones((1, 3))
+    ref = om.state_PT(P, Tv, Y)
+    g = run_gpu(props, props.Mechanism(sp), props.PTY, props.FP64, 3, {"P": P, "T": Tv, "Y": Y})
+    assert np.array_equal(g["status"], ref["status"]), (g["status"], ref["status"])
+    assert ref["status"][0] & 16 and not (ref["status"][1] & 16) and not (ref["status"][2] & 16)
+    assert g["Z"][0] > 0.3 and g["Z"][1] > 0.3 and g["Z"][2] < 0.3
+    worst = compare(g, ref, 0, FP64_RTOL)
+    assert max(worst.values()) <= 1.0, worst
+
+
 def test_nonphysical_and_bracket_flags(props, orc, sp8, kij8):
     n = 8
     Y = np.zeros((8, n))
