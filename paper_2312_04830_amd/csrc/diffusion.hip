@@ -13,9 +13,9 @@
 //
 // Each unordered pair is visited once and its term feeds both species' sums.  Per cell:
 // one log and one exp for T^-0.15610, three exponentials per pair; FP64 uses the
-// branch-free exp of fastmath.hpp, the mixed variant the hardware v_exp_f32.  Memory: P, T, Y read and D
-// written once, species-major and unit-stride across a wavefront; the pair table (a few
-// hundred values) comes through the scalar cache.
+// branch-free exp of fastmath.hpp, the mixed variant the hardware v_exp_f32.  Memory: P, T,
+// Y read and D written once, species-major and unit-stride across a wavefront; the pair
+// table (a few hundred values) comes through the scalar cache.
 #include <cmath>
 #include <type_traits>
 
