@@ -22,7 +22,9 @@ def declared_functions():
 
 def test_header_declares_the_boundary():
     names = declared_functions()
-    for must in ("props_mech_create", "props_mech_destroy", "props_pr", "props_last_error"):
+    for must in ("props_mech_create", "props_mech_destroy", "props_pr", "props_diffusion", "props_dnn",
+                 "props_dnn_features", "props_dnn_set_log_outputs", "props_features_hpz", "train_dnn",
+                 "serve_create", "props_last_error"):
         assert must in names
 
 
@@ -42,3 +44,6 @@ def test_error_path_without_gpu():
     assert b"NULL" in L.props_last_error()
     assert L.props_pr(None, 0, 0, None, None, 10, None, None) == -1
     assert L.props_version().startswith(b"props-mi355x")
+    assert L.props_diffusion(None, 0, None, None, None, None, 10, None, None) == -1
+    assert b"null mechanism" in L.props_last_error()
+    assert L.props_dnn_set_log_outputs(None, 0x3F) == -1
