@@ -603,21 +603,29 @@ __global__ __launch_bounds__(256) void colsum_partial_kernel(const bf16_t *dz, i
 
 // dst[c] = sum_p part[p][c] in the order p = 0, 1, ... (one thread per column, eight
 // partial rows loaded at a time)
+// dst[c] = sum over the P partial rows of column c.  A block takes 64 columns; its four
+// wave-sized groups sum every fourth row (eight loads in flight), then one group adds the
+// four group sums in a fixed order, so the result is the same bits on every run.
 __global__ __launch_bounds__(256) void sum_rows_kernel(const float *part, int P, int ncol, float *dst)
 {
-    const int c = threadIdx.x;
-    if (c >= ncol) return;
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int g = threadIdx.x >> 6;
     float s = 0.f;
-    int p = 0;
-    for (; p + 8 <= P; p += 8) {
-        float v[8];
+    if (c < ncol) {
+        int p = g;
+        for (; p + 28 < P; p += 32) {
+            float v[8];
 #pragma unroll
-        for (int j = 0; j < 8; j++) v[j] = part[(p + j) * ncol + c];
+            for (int j = 0; j < 8; j++) v[j] = part[(int64_t)(p + 4 * j) * ncol + c];
 #pragma unroll
-        for (int j = 0; j < 8; j++) s += v[j];
+            for (int j = 0; j < 8; j++) s += v[j];
+        }
+        for (; p < P; p += 4) s += part[(int64_t)p * ncol + c];
     }
-    for (; p < P; p++) s += part[p * ncol + c];
-    dst[c] = s;
+    red[g][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (g == 0 && c < ncol) dst[c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
 }
 
 __global__ void adam_kernel(float *w, const float *gr, float *m, float *v, int64_t n, float lr,
@@ -1045,7 +1053,7 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
         // db = column sums of dz
         const int rows = 256, P = (n + rows - 1) / rows;
         hipLaunchKernelGGL(colsum_partial_kernel, dim3(P), dim3(256), 0, s, dzl, n, O, rows, d->cpart);
-        hipLaunchKernelGGL(sum_rows_kernel, dim3(1), dim3(256), 0, s, d->cpart, P, O, d->grad + kLay::b(l));
+        hipLaunchKernelGGL(sum_rows_kernel, dim3((O + 63) / 64), dim3(256), 0, s, d->cpart, P, O, d->grad + kLay::b(l));
         PROPS_HIP_TRY(hipGetLastError());
         if (l > 0) {
             // dz_{l-1} = (dz W) * gelu'(z_{l-1})  (M = n, N = I = 256, K = O)
