@@ -62,6 +62,7 @@ class TrainReport(ctypes.Structure):
 
 
 DNN_LAYERS = ((256, 10), (256, 256), (256, 256), (256, 256), (6, 256))
+NIN, NOUT = 10, 6     # PROPS_DNN_IN, PROPS_DNN_OUT
 
 ROUTE_PR_FP64, ROUTE_PR_MIXED, ROUTE_DNN = 0, 1, 2
 EXEC_GPU, EXEC_MOCK = 0, 1
@@ -153,6 +154,23 @@ def _ptr(t):
     return t.data_ptr()
 
 
+def _arg(t, count, dtype, name):
+    """Device pointer of a tensor the library will read or write `count` elements of: the
+    tensor must be a contiguous CUDA tensor of `dtype` with at least `count` elements (a
+    short, host or mistyped array would otherwise be read or written out of bounds on the
+    device).  None -> NULL."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: expected a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if t.numel() < count:
+        raise ValueError(f"{name}: {t.numel()} elements, the call needs {count}")
+    return _ptr(t)
+
+
 def _stream(stream):
     import torch
     if stream is None:
@@ -200,27 +218,39 @@ class Mechanism:
 
 def pr(mech, mode, prec, inputs, outputs, n, status=None, stream=None):
     """props_pr: ``inputs``/``outputs`` map C field names to contiguous float64 device
-    tensors (missing or None = NULL)."""
-    pin = PropsIn(**{k: _ptr(inputs.get(k)) for k in IN_FIELDS})
-    pout = PropsOut(**{k: _ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",) + EXTRA_OUT_FIELDS})
+    tensors (missing or None = NULL); Y and hRT hold [ns, n], iters and status uint8 [n]."""
+    import torch
+    n = int(n)
+    size = lambda k: mech.ns * n if k in ("Y", "hRT") else n  # noqa: E731
+    pin = PropsIn(**{k: _arg(inputs.get(k), size(k), torch.float64, k) for k in IN_FIELDS})
+    pout = PropsOut(**{k: _arg(outputs.get(k), size(k), torch.uint8 if k == "iters" else torch.float64, k)
+                       for k in OUT_FIELDS + ("iters",) + EXTRA_OUT_FIELDS})
     check(lib().props_pr(mech.handle, int(mode), int(prec), ctypes.byref(pin), ctypes.byref(pout),
-                         int(n), _ptr(status), _stream(stream)))
+                         n, _arg(status, n, torch.uint8, "status"), _stream(stream)))
 
 
 def diffusion(mech, prec, P, T, Y, D, n, status=None, stream=None):
     """props_diffusion: P, T [n], Y and D [ns, n] are contiguous float64 device tensors."""
-    check(lib().props_diffusion(mech.handle, int(prec), _ptr(P), _ptr(T), _ptr(Y), _ptr(D), int(n),
-                                _ptr(status), _stream(stream)))
+    import torch
+    n, f8 = int(n), torch.float64
+    m = mech.ns * n
+    check(lib().props_diffusion(mech.handle, int(prec), _arg(P, n, f8, "P"), _arg(T, n, f8, "T"),
+                                _arg(Y, m, f8, "Y"), _arg(D, m, f8, "D"), n,
+                                _arg(status, n, torch.uint8, "status"), _stream(stream)))
 
 
 def features_hpz(species, fuel, oxidizer, bc_lambda, h, P, Y, n, X, stream=None):
     """props_features_hpz: species dicts give W and "atoms" {C, H, O}; h, P [n], Y [ns, n]
     and X [10, n] are float64 device tensors."""
     import numpy as np
+    import torch
     atoms = np.ascontiguousarray([[s["atoms"][e] for e in ("C", "H", "O")] for s in species], dtype=np.int32)
     W = np.ascontiguousarray([s["W"] for s in species], dtype=np.float64)
+    n, f8 = int(n), torch.float64
     check(lib().props_features_hpz(atoms.ctypes.data, W.ctypes.data, len(species), int(fuel), int(oxidizer),
-                                   float(bc_lambda), _ptr(h), _ptr(P), _ptr(Y), int(n), _ptr(X), _stream(stream)))
+                                   float(bc_lambda), _arg(h, n, f8, "h"), _arg(P, n, f8, "P"),
+                                   _arg(Y, len(species) * n, f8, "Y"), n, _arg(X, 10 * n, f8, "X"),
+                                   _stream(stream)))
 
 
 class Network:
@@ -277,15 +307,24 @@ class Network:
         return m.value
 
     def __call__(self, inputs, outputs, n, fallback=None, status=None, stream=None):
-        """props_dnn: inputs P, T, Y; outputs rho, h, cp, c, mu, lambda (device tensors)."""
-        pin = PropsIn(**{k: _ptr(inputs.get(k)) for k in IN_FIELDS})
-        pout = PropsOut(**{k: _ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)})
+        """props_dnn: inputs P, T, Y [8, n]; outputs rho, h, cp, c, mu, lambda (float64 device
+        tensors); status uint8 [n]."""
+        import torch
+        n = int(n)
+        ns = NIN - 2
+        pin = PropsIn(**{k: _arg(inputs.get(k), ns * n if k == "Y" else n, torch.float64, k) for k in IN_FIELDS})
+        pout = PropsOut(**{k: _arg(outputs.get(k), n, torch.uint8 if k == "iters" else torch.float64, k)
+                           for k in OUT_FIELDS + ("iters",)})
         check(lib().props_dnn(self.handle, fallback.handle if fallback is not None else None,
-                              ctypes.byref(pin), ctypes.byref(pout), int(n), _ptr(status), _stream(stream)))
+                              ctypes.byref(pin), ctypes.byref(pout), n, _arg(status, n, torch.uint8, "status"),
+                              _stream(stream)))
 
     def features(self, X, Y, n, stream=None):
         """props_dnn_features: X [10, n] raw features, Y [6, n] outputs (float64 device tensors)."""
-        check(lib().props_dnn_features(self.handle, _ptr(X), _ptr(Y), int(n), _stream(stream)))
+        import torch
+        n = int(n)
+        check(lib().props_dnn_features(self.handle, _arg(X, NIN * n, torch.float64, "X"),
+                                       _arg(Y, NOUT * n, torch.float64, "Y"), n, _stream(stream)))
 
     def grad(self, X, Y, n, stream=None):
         """props_dnn_grad on device X [10, n], Y [6, n] (float32): (loss, flat gradient)."""
@@ -293,7 +332,10 @@ class Network:
         total = sum(o * i + o for o, i in DNN_LAYERS)
         g = np.zeros(total, dtype=np.float32)
         loss = ctypes.c_float()
-        check(lib().props_dnn_grad(self.handle, _ptr(X), _ptr(Y), int(n), g.ctypes.data,
+        import torch
+        n = int(n)
+        check(lib().props_dnn_grad(self.handle, _arg(X, NIN * n, torch.float32, "X"),
+                                   _arg(Y, NOUT * n, torch.float32, "Y"), n, g.ctypes.data,
                                    ctypes.byref(loss), _stream(stream)))
         return loss.value, g
 
@@ -306,7 +348,10 @@ class Network:
                        fit_scalers=int(bool(fit_scalers)))
         losses = np.zeros(max(1, int(epochs)), dtype=np.float32)
         rep = TrainReport(loss=losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
-        check(lib().train_dnn(self.handle, _ptr(X), _ptr(Y), int(n), ctypes.byref(cfg),
+        import torch
+        n = int(n)
+        check(lib().train_dnn(self.handle, _arg(X, NIN * n, torch.float32, "X"),
+                              _arg(Y, NOUT * n, torch.float32, "Y"), n, ctypes.byref(cfg),
                               ctypes.byref(rep), _stream(stream)))
         return {"epochs": rep.epochs_run, "steps": rep.steps, "seconds": rep.seconds,
                 "samples_per_s": rep.samples_per_s}, losses[:int(epochs)]
@@ -323,17 +368,22 @@ class Network:
             pass
 
 
-def _host_ptr(a):
-    """Address of a host array (numpy or CPU tensor); None -> NULL."""
+def _host_ptr(a, count=0, itemsize=8, name="array"):
+    """Address of a host array (numpy or CPU tensor) the server will read or write `count`
+    elements of (`itemsize` bytes each: float64, or uint8 for status); None -> NULL."""
     if a is None:
         return None
     if hasattr(a, "data_ptr"):
         if a.is_cuda or not a.is_contiguous():
             raise ValueError("serving requests take contiguous host arrays")
-        return a.data_ptr()
-    if not a.flags["C_CONTIGUOUS"]:
-        raise ValueError("serving requests take contiguous host arrays")
-    return a.ctypes.data
+        size, isz, ptr = a.numel(), a.element_size(), a.data_ptr()
+    else:
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("serving requests take contiguous host arrays")
+        size, isz, ptr = a.size, a.itemsize, a.ctypes.data
+    if isz != itemsize or size < count:
+        raise ValueError(f"{name}: needs {count} elements of {itemsize} bytes, got {size} of {isz}")
+    return ptr
 
 
 class Server:
@@ -348,14 +398,18 @@ class Server:
         check(lib().serve_create(ctypes.byref(cfg), mech.handle if mech is not None else None,
                                  dnn.handle if dnn is not None else None, ctypes.byref(h)))
         self.handle = h
+        self.ns = mech.ns if mech is not None else int(mock_species)
         self._keep = {}
 
     def submit(self, mode, route, n, inputs, outputs, status=None):
         """Non-blocking; host arrays must stay alive until wait() returns."""
-        req = Request(mode=int(mode), route=int(route), n=int(n),
-                      inp=PropsIn(**{k: _host_ptr(inputs.get(k)) for k in IN_FIELDS}),
-                      out=PropsOut(**{k: _host_ptr(outputs.get(k)) for k in OUT_FIELDS + ("iters",)}),
-                      status=_host_ptr(status))
+        n = int(n)
+        req = Request(mode=int(mode), route=int(route), n=n,
+                      inp=PropsIn(**{k: _host_ptr(inputs.get(k), self.ns * n if k == "Y" else n, 8, k)
+                                     for k in IN_FIELDS}),
+                      out=PropsOut(**{k: _host_ptr(outputs.get(k), n, 1 if k == "iters" else 8, k)
+                                      for k in OUT_FIELDS + ("iters",)}),
+                      status=_host_ptr(status, n, 1, "status"))
         t = ctypes.c_uint64()
         check(lib().serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = (inputs, outputs, status)

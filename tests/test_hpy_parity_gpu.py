@@ -285,7 +285,7 @@ def test_hpy_newton_iteration_limit_and_empty_launch(props, orc, sp8, kij8):
     m.set_newton(100, 1e-10)
     g = run_gpu(props, m, props.HPY, props.FP64, T.size, {"h": h, "P": P, "Y": Y}, fields=("T",))
     assert np.all(g["status"] == 0)
-    z = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    z = torch.zeros(8, dtype=torch.float64, device="cuda:0")
     props.pr(m, props.HPY, props.FP64, {"h": z, "P": z, "Y": z}, {"T": z}, 0)
     with pytest.raises(props.PropsError):
         props.pr(m, props.HPY, props.FP64, {"P": z, "Y": z}, {"T": z}, 1)    # h missing

@@ -1,6 +1,10 @@
 """Size limits of the C ABI: a cell count beyond what one launch can address is refused
 with PROPS_ETOOBIG before anything is launched (the arrays passed here are tiny and are
-never touched).  The largest count each entry point accepts is stated in props.h."""
+never touched).  The largest count each entry point accepts is stated in props.h.  The
+calls go straight to the C functions: the Python binding would already refuse arrays
+shorter than the count."""
+import ctypes
+
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -34,23 +38,41 @@ def mech(props):
 
 @pytest.mark.parametrize("mode", ["PTY", "RHOEY", "HPY"])
 def test_pr_refuses_a_grid_beyond_the_launch_limit(props, mech, tiny, mode):
-    ins = {"P": tiny, "T": tiny, "rho": tiny, "e": tiny, "h": tiny, "Y": tiny}
-    with pytest.raises(props.PropsError) as e:
-        props.pr(mech, getattr(props, mode), props.FP64, ins, {"T": tiny}, HUGE_GRID)
-    assert e.value.code == ETOOBIG
+    p = tiny.data_ptr()
+    pin = props._lib.PropsIn(P=p, T=p, rho=p, e=p, Y=p, h=p)
+    pout = props._lib.PropsOut(T=p)
+    rc = props.lib().props_pr(mech.handle, getattr(props, mode), props.FP64, ctypes.byref(pin), ctypes.byref(pout),
+                              HUGE_GRID, None, None)
+    assert rc == ETOOBIG, props.lib().props_last_error()
 
 
 def test_diffusion_refuses_a_grid_beyond_the_launch_limit(props, mech, tiny):
-    with pytest.raises(props.PropsError) as e:
-        props.diffusion(mech, props.FP64, tiny, tiny, tiny, tiny, HUGE_GRID)
-    assert e.value.code == ETOOBIG
+    p = tiny.data_ptr()
+    rc = props.lib().props_diffusion(mech.handle, props.FP64, p, p, p, p, HUGE_GRID, None, None)
+    assert rc == ETOOBIG, props.lib().props_last_error()
 
 
 def test_surrogate_refuses_counts_beyond_32_bit_indices(props, mech, tiny):
     net = props.Network(seed=1)
-    with pytest.raises(props.PropsError) as e:
-        net({"P": tiny, "T": tiny, "Y": tiny}, {"rho": tiny}, HUGE_INT, fallback=mech)
-    assert e.value.code == ETOOBIG
-    with pytest.raises(props.PropsError) as e:
-        net.features(tiny, tiny, HUGE_INT)
-    assert e.value.code == ETOOBIG
+    p = tiny.data_ptr()
+    pin = props._lib.PropsIn(P=p, T=p, Y=p)
+    pout = props._lib.PropsOut(rho=p)
+    rc = props.lib().props_dnn(net.handle, mech.handle, ctypes.byref(pin), ctypes.byref(pout), HUGE_INT, None, None)
+    assert rc == ETOOBIG, props.lib().props_last_error()
+    rc = props.lib().props_dnn_features(net.handle, p, p, HUGE_INT, None)
+    assert rc == ETOOBIG, props.lib().props_last_error()
+
+
+def test_binding_refuses_short_host_or_mistyped_arrays(props, mech, tiny):
+    """The binding checks each device array against the element count the call will touch."""
+    import torch
+    ins = {"P": tiny, "T": tiny, "Y": tiny}
+    with pytest.raises(ValueError, match="elements"):
+        props.pr(mech, props.PTY, props.FP64, ins, {"rho": tiny}, 4)          # Y needs 8 x 4
+    with pytest.raises(ValueError, match="device"):
+        props.pr(mech, props.PTY, props.FP64, {"P": tiny.cpu(), "T": tiny, "Y": tiny}, {}, 1)
+    with pytest.raises(ValueError, match="float64"):
+        props.diffusion(mech, props.FP64, tiny.float(), tiny, tiny, tiny, 1)
+    with pytest.raises(ValueError, match="status"):
+        props.diffusion(mech, props.FP64, tiny, tiny, tiny, tiny, 2, status=torch.zeros(1, dtype=torch.uint8,
+                                                                                     device="cuda:0"))

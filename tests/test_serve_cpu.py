@@ -205,3 +205,19 @@ def test_close_drains_work_in_flight():
     s.submit(P.PTY, 0, 30_000, ins, outs)
     s.close()
     np.testing.assert_array_equal(outs["rho"], expected(ins, P.PTY, 0)["rho"])
+
+
+def test_submit_refuses_short_or_mistyped_host_arrays():
+    """The binding checks each host array against the cells the server will touch."""
+    s = server(streams=1)
+    ins, outs, st = make_request(100, 7)
+    bad = dict(ins, Y=ins["Y"][:, :50].copy())
+    with pytest.raises(ValueError, match="Y"):
+        s.submit(P.PTY, 0, 100, bad, outs, st)
+    with pytest.raises(ValueError, match="status"):
+        s.submit(P.PTY, 0, 100, ins, outs, st.astype(np.float64))
+    with pytest.raises(ValueError, match="rho"):
+        s.submit(P.PTY, 0, 100, ins, dict(outs, rho=np.zeros(99)), st)
+    r = s.wait(s.submit(P.PTY, 0, 100, ins, outs, st))
+    assert r["rc"] == 0
+    s.close()
