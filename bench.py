@@ -24,8 +24,9 @@ sys.path.insert(0, ROOT)
 
 # FP64 VALU instructions per call of each special function in this library's gfx950 build,
 # amortised over several calls in one kernel (measured from our own assembly): the device
-# library's expm1, sqrt and cbrt; the library's own exp, log and refined reciprocal.
-SP_COST = {"rcp": 6, "sqrt": 20, "exp": 20, "cbrt": 30, "expm1": 33, "log": 40}
+# library's expm1, sqrt and cbrt; the library's own log, refined reciprocal and exp (the
+# table-driven one of the transport and diffusion terms: 15 instructions and one LDS read).
+SP_COST = {"rcp": 6, "sqrt": 20, "exp": 15, "cbrt": 30, "expm1": 33, "log": 40}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops (FMA).
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0

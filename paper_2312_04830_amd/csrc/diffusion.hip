@@ -13,7 +13,7 @@
 //
 // Each unordered pair is visited once and its term feeds both species' sums.  Per cell:
 // one log and one exp for T^-0.15610, three exponentials per pair; FP64 uses the
-// branch-free exp of fastmath.hpp, the mixed variant the hardware v_exp_f32.  Memory: P, T,
+// table-driven exp of fastmath.hpp (table in LDS), the mixed variant the hardware v_exp_f32.  Memory: P, T,
 // Y read and D written once, species-major and unit-stride across a wavefront; the pair
 // table (a few hundred values) comes through the scalar cache.
 #include <cmath>
@@ -28,13 +28,13 @@ namespace {
 
 struct D64 {
     using R = double;
-    static __device__ __forceinline__ R exp_(R x) { return fm::exp(x); }
+    static __device__ __forceinline__ R exp_(R x, const double *e2) { return fm::exp_tab(x, e2); }
     static __device__ __forceinline__ R log_(R x) { return fm::log(x); }
 };
 
 struct D32 {
     using R = float;
-    static __device__ __forceinline__ R exp_(R x) { return __expf(x); }
+    static __device__ __forceinline__ R exp_(R x, const double *) { return __expf(x); }
     static __device__ __forceinline__ R log_(R x) { return __logf(x); }
 };
 
@@ -57,6 +57,12 @@ __global__ __launch_bounds__(256) void diffusion_kernel(const ThermoTab<NS> *__r
     const DiffTab<R, NS> *__restrict__ td;
     if constexpr (PREC == PROPS_FP64) td = tdd; else td = tdf;
 
+    // 2^(j/64) for the double-precision exponentials, staged in LDS before any lane leaves
+    __shared__ double e2s[64];
+    if constexpr (PREC == PROPS_FP64) {
+        if (threadIdx.x < 64) e2s[threadIdx.x] = tt->exp2j[threadIdx.x];
+        __syncthreads();
+    }
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= a.n) return;
     const int64_t n = a.n;
@@ -87,7 +93,7 @@ __global__ __launch_bounds__(256) void diffusion_kernel(const ThermoTab<NS> *__r
     }
 
     const R Tr = (R)T;
-    const R Tm = PM::exp_(R(-0.15610) * PM::log_(Tr));   // T^-0.15610
+    const R Tm = PM::exp_(R(-0.15610) * PM::log_(Tr), e2s);   // T^-0.15610
     R S[NS];
 #pragma unroll
     for (int i = 0; i < NS; i++) S[i] = R(0);
@@ -106,9 +112,9 @@ __global__ __launch_bounds__(256) void diffusion_kernel(const ThermoTab<NS> *__r
             const __attribute__((address_space(4))) DiffTab<R, NS> *t =
                 (const __attribute__((address_space(4))) DiffTab<R, NS> *)tg;
             R h = t->c0[p] * Tm;
-            h += t->c1[p] * PM::exp_(t->x1[p] * Tr);
-            h += t->c2[p] * PM::exp_(t->x2[p] * Tr);
-            h += t->c3[p] * PM::exp_(t->x3[p] * Tr);
+            h += t->c1[p] * PM::exp_(t->x1[p] * Tr, e2s);
+            h += t->c2[p] * PM::exp_(t->x2[p] * Tr, e2s);
+            h += t->c3[p] * PM::exp_(t->x3[p] * Tr, e2s);
             S[i] += yw[j] * h;
             S[j] += yw[i] * h;
             prev = h;

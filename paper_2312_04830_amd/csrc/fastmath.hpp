@@ -7,6 +7,7 @@
 //           |f| <= 0.1716, by the odd series of atanh to f^21 (truncation < 1e-18), and
 //           e ln2 with ln2 split into a 24-bit head and a tail.
 //   rcp   — hardware reciprocal refined by two Newton-Raphson steps.
+//   exp_tab — the same with 64 table values 2^(j/64) and a degree-5 polynomial (below).
 //   exp   — x = n ln2 + r with n = rint(x log2 e), |r| <= ln2/2 (ln 2 split as for log),
 //           e^r by its Taylor series to r^13 (truncation below 5e-18 relative), scaled
 //           by 2^n with ldexp; no special-case branches (the device library's exp
@@ -81,6 +82,32 @@ FM_HD inline double exp(double x)
     p = std::fma(p, r, 1.0);
     p = std::fma(p, r, 1.0);
     return std::ldexp(p, (int)n);
+}
+
+// exp with a table of the 64 values 2^(j/64) (correctly rounded), typically an LDS copy:
+// x = (64 m + j) ln2/64 + r with |r| <= ln2/128 (ln2/64 split into a 35-bit head and a
+// tail), e^x = 2^m 2^(j/64) e^r, e^r by its Taylor series to r^5 (truncation below 4e-17
+// relative).  Fourteen instructions and one table read against twenty for exp; the same
+// range behaviour (overflow inf, underflow 0 through subnormals, NaN stays NaN).
+constexpr double k64Log2e = 92.33248261689366;            // 64/ln2
+constexpr double kLn2o64Hi = 0.010830424696450791;        // ln2/64 to 35 significant bits
+constexpr double kLn2o64Lo = -2.0164562921995537e-13;     // ln2/64 - kLn2o64Hi
+
+FM_HD inline double exp_tab(double x, const double *tab64)
+{
+    const double k = std::rint(x * k64Log2e);
+    const int ki = (int)k;
+    double r = std::fma(-k, kLn2o64Hi, x);
+    r = std::fma(-k, kLn2o64Lo, r);
+    // e^r - 1 = r + r (r/2 + r^2/6 + r^3/24 + r^4/120), then t + t (e^r - 1): one rounding
+    double q = 1.0 / 120.0;
+    q = std::fma(q, r, 1.0 / 24.0);
+    q = std::fma(q, r, 1.0 / 6.0);
+    q = std::fma(q, r, 0.5);
+    q = q * r;
+    q = std::fma(q, r, r);
+    const double t = tab64[ki & 63];
+    return std::ldexp(std::fma(t, q, t), ki >> 6);
 }
 
 FM_HD inline double rcp(double x)

@@ -104,6 +104,7 @@ static void fill_thermo(ThermoTab<NS> &t, const props_species_desc *sp, int ns)
         t.a6[1][i] = t.RW[i] * s.nasa_hi[5];
     }
     t.Tmid = sp[0].Tmid;
+    for (int j = 0; j < 64; j++) t.exp2j[j] = (double)exp2l((long double)j / 64.0L);
 }
 
 // Chapman-Enskog pair constants.  Lennard-Jones parameters come from the same Chung

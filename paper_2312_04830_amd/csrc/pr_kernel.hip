@@ -34,14 +34,14 @@
 namespace props {
 
 // ------------------------------------------------------------------ precision policies
-// Double precision: the branch-free exp, the lean log and the refined reciprocal of
-// fastmath.hpp, the device library's expm1 (a few ulp; outputs stay within 1e-15 relative
-// of correctly rounded maths).
+// Double precision: the table-driven exp (table in LDS), the lean log and the refined
+// reciprocal of fastmath.hpp, the device library's expm1 (a few ulp; outputs stay within
+// 1e-15 relative of correctly rounded maths).
 struct P64 {
     using R = double;
     static __device__ __forceinline__ R sqrt_(R x) { return sqrt(x); }
     static __device__ __forceinline__ R log_(R x) { return fm::log(x); }
-    static __device__ __forceinline__ R exp_(R x) { return fm::exp(x); }
+    static __device__ __forceinline__ R exp_(R x, const double *e2) { return fm::exp_tab(x, e2); }
     static __device__ __forceinline__ R expm1_(R x) { return expm1(x); }
     static __device__ __forceinline__ R cbrt_(R x) { return cbrt(x); }
     static __device__ __forceinline__ R div(R a, R b) { return a * fm::rcp(b); }
@@ -52,7 +52,7 @@ struct P32 {
     using R = float;
     static __device__ __forceinline__ R sqrt_(R x) { return __builtin_sqrtf(x); }
     static __device__ __forceinline__ R log_(R x) { return __logf(x); }
-    static __device__ __forceinline__ R exp_(R x) { return __expf(x); }
+    static __device__ __forceinline__ R exp_(R x, const double *) { return __expf(x); }
     static __device__ __forceinline__ R expm1_(R x) { return expm1f(x); }
     static __device__ __forceinline__ R cbrt_(R x) { return cbrtf(x); }
     static __device__ __forceinline__ R div(R a, R b) { return a * __builtin_amdgcn_rcpf(b); }
@@ -205,11 +205,11 @@ __constant__ double kChungB[7][4] = {
 // Chung's density function G2 for coefficients c1..c5 (c = pointer to the 5 values).
 template <class PM>
 __device__ __forceinline__ typename PM::R chung_G2(typename PM::R y, typename PM::R G1,
-                                                   typename PM::R iy, const typename PM::R *c)
+                                                   typename PM::R iy, const typename PM::R *c, const double *e2)
 {
     using R = typename PM::R;
     R t1 = c[0] * (-PM::expm1_(-c[3] * y)) * iy;
-    R num = t1 + c[1] * G1 * PM::exp_(c[4] * y) + c[2] * G1;
+    R num = t1 + c[1] * G1 * PM::exp_(c[4] * y, e2) + c[2] * G1;
     return PM::div(num, c[0] * c[3] + c[1] + c[2]);
 }
 
@@ -234,19 +234,19 @@ template <class PM, int NS>
 __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restrict__ t0,
                                       const typename PM::R (&X)[NS], typename PM::R T,
                                       typename PM::R rhom, typename PM::R Cv, bool want_mu,
-                                      bool want_lam, double *omu, double *olam)
+                                      bool want_lam, double *omu, double *olam, const double *e2)
 {
     using R = typename PM::R;
     const MixTab<R, NS> *__restrict__ t = t0;
     // mole-fraction-averaged low-pressure viscosity; T*^-0.14874 shared by all species
     const R sT = PM::sqrt_(T);
-    const R Tp = PM::exp_(R(-0.14874) * PM::log_(T));
+    const R Tp = PM::exp_(R(-0.14874) * PM::log_(T), e2);
     R eta0 = 0;
 #pragma unroll
     for (int i = 0; i < NS; i++) {
         R ts = t->tsc[i] * T;
-        R om = t->tsp[i] * Tp + R(0.52487) * PM::exp_(R(-0.77320) * ts) +
-               R(2.16178) * PM::exp_(R(-2.43787) * ts);
+        R om = t->tsp[i] * Tp + R(0.52487) * PM::exp_(R(-0.77320) * ts, e2) +
+               R(2.16178) * PM::exp_(R(-2.43787) * ts, e2);
         eta0 += PM::div(X[i] * t->mu0A[i], om);
     }
     eta0 *= sT;
@@ -289,9 +289,9 @@ __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restri
 #pragma unroll
         for (int i = 0; i < 10; i++)
             E[i] = R(kChungE[i][0]) + R(kChungE[i][1]) * wm + R(kChungE[i][2]) * mr4 + R(kChungE[i][3]) * km;
-        const R G2 = chung_G2<PM>(y, G1, iy, E);
+        const R G2 = chung_G2<PM>(y, G1, iy, E, e2);
         const R its = PM::div(em, T);  // 1/T*, T* = T/(eps/k)_m
-        const R muss = E[6] * y * y * G2 * PM::exp_(E[7] + E[8] * its + E[9] * its * its);
+        const R muss = E[6] * y * y * G2 * PM::exp_(E[7] + E[8] * its + E[9] * its * its, e2);
         const R mu = eta0 * (PM::div(R(1), G2) + E[5] * y) +
                      PM::div(R(36.344e-7) * muss * PM::sqrt_(Mm * Tcm), Vc23);
         *omu = (double)mu;
@@ -301,7 +301,7 @@ __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restri
 #pragma unroll
         for (int i = 0; i < 7; i++)
             Bc[i] = R(kChungB[i][0]) + R(kChungB[i][1]) * wm + R(kChungB[i][2]) * mr4 + R(kChungB[i][3]) * km;
-        const R G2 = chung_G2<PM>(y, G1, iy, Bc);
+        const R G2 = chung_G2<PM>(y, G1, iy, Bc, e2);
         const R Tr = PM::div(T, Tcm);
         const R al = Cv * R(1.0 / kR) - R(1.5);
         const R be = R(0.7862) - R(0.7109) * wm + R(1.3168) * wm * wm;
@@ -438,6 +438,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     constexpr bool SOLVER = (OUTS & kOutSolver) != 0;
     const MixTab<R, NS> *__restrict__ tm;
     if constexpr (PREC == PROPS_FP64) tm = tmd; else tm = tmf;
+
+    // the double-precision transport's exponentials read 2^(j/64) from LDS (staged before
+    // any lane leaves)
+    __shared__ double e2s[64];
+    if constexpr (TRANSPORT && PREC == PROPS_FP64) {
+        if (threadIdx.x < 64) e2s[threadIdx.x] = tt->exp2j[threadIdx.x];
+        __syncthreads();
+    }
 
     int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a.idx) {
@@ -741,7 +749,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     if constexpr (TRANSPORT) {
         double mu = 0, lam = 0;
         chung<PM, NS>(tm, Xr, (R)T, (R)(1.0 / v), (R)(W * (cp_ig - ig.rw)), a.omu != nullptr,
-                      a.olam != nullptr || (SOLVER && a.oalpha != nullptr), &mu, &lam);
+                      a.olam != nullptr || (SOLVER && a.oalpha != nullptr), &mu, &lam, e2s);
         if (a.omu) a.omu[k] = mu;
         if (a.olam) a.olam[k] = lam;
         if (SOLVER && a.oalpha) a.oalpha[k] = lam * v * fm::rcp(W * cp);

@@ -51,6 +51,7 @@ struct ThermoTab {
     double a6[2][NS];     // (R/W_i) a6 per range, J/kg
     double WR[NS];        // W_i/R [kg K/J], turns a species' h [J/kg] at T into h/(R T) * T
     double Tmid;
+    double exp2j[64];     // 2^(j/64), j = 0..63, correctly rounded: the table of fm::exp_tab
 };
 
 // Mixing and transport constants, in the working precision R of the algebra.

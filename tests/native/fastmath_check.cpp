@@ -44,7 +44,22 @@ int main()
         e_exp = std::fmax(e_exp, ulp_err(props::fm::exp(x), expl((long double)x)));
     for (double x = -745.0; x < -708.5; x += 1e-3)
         e_sub = std::fmax(e_sub, std::fabs((double)((long double)props::fm::exp(x) - expl((long double)x))) / 4.9406564584124654e-324);
+    // exp_tab with its table of 2^(j/64) rounded from long double
+    double tab[64];
+    for (int j = 0; j < 64; j++) tab[j] = (double)exp2l((long double)j / 64.0L);
+    double e_tab = 0, e_tsub = 0;
+    for (int i = 0; i < 2000000; i++) {
+        double x = ue(g);
+        e_tab = std::fmax(e_tab, ulp_err(props::fm::exp_tab(x, tab), expl((long double)x)));
+    }
+    for (double x = -60.0; x < 40.0; x += 1.37e-4)
+        e_tab = std::fmax(e_tab, ulp_err(props::fm::exp_tab(x, tab), expl((long double)x)));
+    for (double x = -745.0; x < -708.5; x += 1e-3)
+        e_tsub = std::fmax(e_tsub, std::fabs((double)((long double)props::fm::exp_tab(x, tab) - expl((long double)x))) / 4.9406564584124654e-324);
     std::printf("log_max_ulp %.3f\n", e_log);
+    std::printf("exptab_max_ulp %.3f exptab_sub_max_denorm_ulp %.3f exptab_limits %d\n", e_tab, e_tsub,
+                (int)(props::fm::exp_tab(-800.0, tab) == 0.0 && std::isinf(props::fm::exp_tab(710.0, tab)) &&
+                      props::fm::exp_tab(0.0, tab) == 1.0));
     std::printf("exp_max_ulp %.3f exp_sub_max_denorm_ulp %.3f\n", e_exp, e_sub);
     std::printf("exp_under_zero %d exp_over_inf %d exp_nan %d exp_zero_one %d\n",
                 (int)(props::fm::exp(-800.0) == 0.0), (int)std::isinf(props::fm::exp(710.0)),

@@ -1,4 +1,4 @@
-"""Host build of the kernels' double-precision log and exp (fastmath.hpp): error in units of the
+"""Host build of the kernels' double-precision log, exp and table exp (fastmath.hpp): error in units of the
 last place against long-double libm over seeded arguments (CPU only; the device build runs
 the same arithmetic, and the GPU parity tests cover it end to end)."""
 import os
@@ -38,3 +38,10 @@ def test_exp_within_two_ulp(report):
 def test_exp_limits(report):
     assert report["exp_under_zero"] == 1 and report["exp_over_inf"] == 1
     assert report["exp_nan"] == 1 and report["exp_zero_one"] == 1
+
+
+def test_table_exp_within_two_ulp(report):
+    """exp_tab with its table of 2^(j/64): the transport and diffusion exponentials."""
+    assert report["exptab_max_ulp"] <= 2.0
+    assert report["exptab_sub_max_denorm_ulp"] <= 1.0
+    assert report["exptab_limits"] == 1
