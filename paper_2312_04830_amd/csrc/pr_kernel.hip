@@ -487,6 +487,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     const double nan = __builtin_nan("");
     double T = nan, P = nan, v = nan;
     double am = 0, am1 = 0, am2 = 0;
+    double Lv = 0.0;   // (rho, e, Y): the departure log at the fixed v, reused by the epilogue
     Nasa ig;
     // the inversions evaluate the ideal gas at many T: both NASA ranges up front; the
     // (P, T, Y) path needs one range, once, and builds it where it is used
@@ -594,6 +595,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
         } else {
             const double estar = in1;
             const double L = fm::log((v + (1.0 + kSqrt2) * bm) * fm::rcp(v + (1.0 - kSqrt2) * bm));
+            Lv = L;
             const R Lw = (R)(L * fm::rcp(2.0 * kSqrt2 * bm) * syw);  // departure (per mole) -> J/kg factor
             double lo = kTlo, hi = kThi;
             T = kThi;
@@ -700,7 +702,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     {
         const R rv = (R)v, rb = (R)bm, rT = (R)T, rden = (R)den, rvb = (R)vb;
         const R ram = (R)am, ram1 = (R)am1, ram2 = (R)am2;
-        const R L = PM::log_(PM::div(rv + R(1.0 + kSqrt2) * rb, rv + R(1.0 - kSqrt2) * rb));
+        // v is the input's in (rho, e, Y) mode: its departure log is the one of the iteration
+        const R L = (MODE == PROPS_RHOEY) ? (R)Lv
+                                          : PM::log_(PM::div(rv + R(1.0 + kSqrt2) * rb, rv + R(1.0 - kSqrt2) * rb));
         const R Lb = PM::div(L, R(2.0 * kSqrt2) * rb);
         const R edep = (rT * ram1 - ram) * Lb;                 // J/mol
         const R cvdep = rT * ram2 * Lb;                        // J/(mol K)
