@@ -110,6 +110,22 @@ FM_HD inline double exp_tab(double x, const double *tab64)
     return std::ldexp(std::fma(t, q, t), ki >> 6);
 }
 
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton-Raphson steps
+// (r <- r + r (1 - x r^2)/2, the relative error squaring each time), within two ulp;
+// sqrt(x) then follows as x * rsqrt(x) without the correctly rounded square root's cost.
+FM_HD inline double rsqrt(double x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    double r = __builtin_amdgcn_rsq(x);
+    double e = std::fma(-x * r, r, 1.0);
+    r = std::fma(0.5 * r, e, r);
+    e = std::fma(-x * r, r, 1.0);
+    return std::fma(0.5 * r, e, r);
+#else
+    return 1.0 / std::sqrt(x);
+#endif
+}
+
 FM_HD inline double rcp(double x)
 {
 #if defined(__HIP_DEVICE_COMPILE__)

@@ -512,9 +512,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
         mq.build(tm, Xr, T);
         for (; it < a.maxit; it++) {
             if (!mq.valid(T)) mq.build(tm, Xr, T);
-            const double sT = sqrt(T);
+            const double rsT = fm::rsqrt(T), sT = T * rsT;
             R ram, ram1, ram2;
-            mq.eval((R)T, (R)sT, (R)fm::rcp(sT), ram, ram1, ram2);
+            mq.eval((R)T, (R)sT, (R)rsT, ram, ram1, ram2);
             const double RT = kR * T;
             const double iRT = fm::rcp(RT);
             const double A = (double)ram * P * iRT * iRT;
@@ -576,9 +576,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
         }
         MixQuad<PM, NS> mq;
         mq.build(tm, Xr, T);
-        const double sT = sqrt(T);
+        const double rsT = fm::rsqrt(T), sT = T * rsT;
         R ram, ram1, ram2;
-        mq.eval((R)T, (R)sT, (R)fm::rcp(sT), ram, ram1, ram2);
+        mq.eval((R)T, (R)sT, (R)rsT, ram, ram1, ram2);
         am = ram, am1 = ram1, am2 = ram2;
         const double RT = kR * T;
         const double iRT = fm::rcp(RT);
@@ -613,9 +613,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
             mq.build(tm, Xr, T);
             for (; it < a.maxit; it++) {
                 if (!mq.valid(T)) mq.build(tm, Xr, T);
-                const double sT = sqrt(T);
+                const double rsT = fm::rsqrt(T), sT = T * rsT;
                 R ram, ram1, ram2;
-                mq.eval((R)T, (R)sT, (R)fm::rcp(sT), ram, ram1, ram2);
+                mq.eval((R)T, (R)sT, (R)rsT, ram, ram1, ram2);
                 double h_ig, cp_ig;
                 ig.eval(T, h_ig, cp_ig);
                 const double edep = (double)(((R)T * ram1 - ram) * Lw);
@@ -652,9 +652,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
                 bad = true;
             } else {
                 if (!mq.valid(T)) mq.build(tm, Xr, T);
-                const double sT = sqrt(T);
+                const double rsT = fm::rsqrt(T), sT = T * rsT;
                 R ram, ram1, ram2;
-                mq.eval((R)T, (R)sT, (R)fm::rcp(sT), ram, ram1, ram2);
+                mq.eval((R)T, (R)sT, (R)rsT, ram, ram1, ram2);
                 am = ram, am1 = ram1, am2 = ram2;
                 const double den = v * v + 2.0 * bm * v - bm * bm;
                 P = kR * T * fm::rcp(v - bm) - am * fm::rcp(den);
