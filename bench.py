@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 # amortised over several calls in one kernel (measured from our own assembly): the device
 # library's expm1, sqrt and cbrt; the library's own log, refined reciprocal and exp (the
 # table-driven one of the transport and diffusion terms: 15 instructions and one LDS read).
-SP_COST = {"rcp": 6, "sqrt": 20, "exp": 15, "cbrt": 30, "expm1": 33, "log": 40}
+SP_COST = {"rcp": 6, "rsqrt": 9, "sqrt": 20, "exp": 15, "cbrt": 30, "expm1": 33, "log": 40}
 # MI355X FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz x 2 flops (FMA).
 FP64_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
@@ -48,19 +48,19 @@ def ops_per_cell(ns, evals, transport=True):
     ops += 12 * ns + ns                               # NASA-7 mixture coefficients (2 ranges)
     ops += 8 + sp(rcp=3, log=1)                       # v, departure log L at fixed v
     ops += 8 * ns + 2 * ns * ns + 3 * ns + 3          # A0, A1, A2 of the mixing sum
-    per_eval = 8 + 14 + 10 + 3 + sp(sqrt=1, rcp=2)    # a_m and derivatives, h_ig, c_p, residual, step
+    per_eval = 9 + 14 + 10 + 3 + sp(rsqrt=1, rcp=1)   # a_m and derivatives, h_ig, c_p, residual, step
     ops += evals * per_eval
-    ops += per_eval + 45 + sp(rcp=10, log=1)          # final state, P, h, e, c_p, c
+    ops += per_eval + 45 + sp(rcp=12, sqrt=1)         # final state, P, h, e, c_p, c (L is the iteration's)
     if transport:
-        ops += 2 + sp(sqrt=1, log=1, exp=1)
-        ops += ns * (6 + 2 * SP_COST["exp"] + SP_COST["rcp"])     # species low-pressure viscosity
+        ops += 4 + sp(rsqrt=1, log=1, exp=1)          # sqrt(T), 1/T, T^-0.14874
+        ops += ns * (10 + 2 * SP_COST["exp"])         # species low-pressure viscosity terms
+        ops += 2 + sp(rcp=1)                          # their one quotient
         ops += 5 * ns + (ns * (ns + 1) // 2 + ns)    # four single sums + the molar-mass quadratic form
-        ops += 20 + sp(rcp=4, cbrt=1)                 # pseudo-critical constants
+        ops += 33 + sp(rcp=2, cbrt=1, rsqrt=1)        # pseudo-critical constants, y, 1/y, G1
         ops += 30 + 21                                # Chung E and B coefficients
-        ops += 6 + sp(rcp=2)                          # y, 1/y, G1
-        ops += 2 * (8 + sp(expm1=1, exp=1, rcp=1))    # G2 for viscosity and conductivity
-        ops += 14 + sp(exp=1, rcp=3, sqrt=1)          # viscosity
-        ops += 30 + sp(rcp=5, sqrt=2)                 # conductivity
+        ops += 2 * (15 + sp(expm1=1, exp=1, rcp=1))   # G2 and 1/G2 for viscosity and conductivity
+        ops += 15 + sp(exp=1)                         # viscosity
+        ops += 37 + sp(rcp=1)                         # conductivity
     return ops
 
 

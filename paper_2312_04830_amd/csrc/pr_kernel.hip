@@ -40,6 +40,7 @@ namespace props {
 struct P64 {
     using R = double;
     static __device__ __forceinline__ R sqrt_(R x) { return sqrt(x); }
+    static __device__ __forceinline__ R rsqrt_(R x) { return fm::rsqrt(x); }
     static __device__ __forceinline__ R log_(R x) { return fm::log(x); }
     static __device__ __forceinline__ R exp_(R x, const double *e2) { return fm::exp_tab(x, e2); }
     static __device__ __forceinline__ R expm1_(R x) { return expm1(x); }
@@ -51,6 +52,7 @@ struct P64 {
 struct P32 {
     using R = float;
     static __device__ __forceinline__ R sqrt_(R x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ R rsqrt_(R x) { return __builtin_amdgcn_rsqf(x); }
     static __device__ __forceinline__ R log_(R x) { return __logf(x); }
     static __device__ __forceinline__ R exp_(R x, const double *) { return __expf(x); }
     static __device__ __forceinline__ R expm1_(R x) { return expm1f(x); }
@@ -202,15 +204,20 @@ __constant__ double kChungB[7][4] = {
     {0.79274, 0.82019, -0.69369, 6.3173},  {-5.8634, 12.801, 9.5893, 65.529},
     {91.089, 128.11, -54.217, 523.81}};
 
-// Chung's density function G2 for coefficients c1..c5 (c = pointer to the 5 values).
+// Chung's density function G2 for coefficients c1..c5 (c = pointer to the 5 values), with
+// its reciprocal: G2 = num/S and 1/G2 = S/num from the one reciprocal 1/(num S).
 template <class PM>
-__device__ __forceinline__ typename PM::R chung_G2(typename PM::R y, typename PM::R G1,
-                                                   typename PM::R iy, const typename PM::R *c, const double *e2)
+__device__ __forceinline__ void chung_G2(typename PM::R y, typename PM::R G1, typename PM::R iy,
+                                         const typename PM::R *c, const double *e2, typename PM::R &G2,
+                                         typename PM::R &iG2)
 {
     using R = typename PM::R;
     R t1 = c[0] * (-PM::expm1_(-c[3] * y)) * iy;
     R num = t1 + c[1] * G1 * PM::exp_(c[4] * y, e2) + c[2] * G1;
-    return PM::div(num, c[0] * c[3] + c[1] + c[2]);
+    const R S = c[0] * c[3] + c[1] + c[2];
+    const R r = PM::div(R(1), num * S);
+    G2 = num * num * r;
+    iG2 = S * S * r;
 }
 
 template <class PM, int NS>
@@ -230,6 +237,11 @@ __device__ __forceinline__ typename PM::R qform(const typename PM::R (&C)[NS][NS
 }
 
 // mu [Pa s] and lambda [W/(m K)] at T, molar density rhom [mol/m^3], ideal-gas molar Cv.
+// The pseudo-mixture quantities are rearranged with exact identities so that few divisions
+// and square roots remain: sigma_m^3 = s3 gives Vc_m = s3/0.809^3 and Vc_m Tc_m =
+// 1.2593 es3/0.809^3 without the cube root, sqrt(M_m) is the quotient mq itself, one
+// reciprocal square root gives sqrt(T) and 1/T and another sqrt(Tc_m) and 1/Tc_m, and
+// independent reciprocals are taken in pairs (1/a = b/(ab), 1/b = a/(ab)).
 template <class PM, int NS>
 __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restrict__ t0,
                                       const typename PM::R (&X)[NS], typename PM::R T,
@@ -238,18 +250,23 @@ __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restri
 {
     using R = typename PM::R;
     const MixTab<R, NS> *__restrict__ t = t0;
-    // mole-fraction-averaged low-pressure viscosity; T*^-0.14874 shared by all species
-    const R sT = PM::sqrt_(T);
+    const R rsT = PM::rsqrt_(T);
+    const R sT = T * rsT;
+    const R iT = rsT * rsT;
+    // mole-fraction-averaged low-pressure viscosity, sum_i X_i mu0_i/Omega_v,i, accumulated
+    // as one numerator over one denominator (each Omega_v lies in about [0.5, 3]) so that a
+    // single division serves every species; T*^-0.14874 is shared by all species
     const R Tp = PM::exp_(R(-0.14874) * PM::log_(T), e2);
-    R eta0 = 0;
+    R en = 0, ed = 1;
 #pragma unroll
     for (int i = 0; i < NS; i++) {
         R ts = t->tsc[i] * T;
         R om = t->tsp[i] * Tp + R(0.52487) * PM::exp_(R(-0.77320) * ts, e2) +
                R(2.16178) * PM::exp_(R(-2.43787) * ts, e2);
-        eta0 += PM::div(X[i] * t->mu0A[i], om);
+        en = en * om + ed * (X[i] * t->mu0A[i]);
+        ed = ed * om;
     }
-    eta0 *= sT;
+    const R eta0 = sT * PM::div(en, ed);
     // pseudo-mixture parameters (Chung's mixing rules; see MixTab for the factorisation)
     R sp = 0, sq = 0, swp = 0, sm = 0, sk = 0;
 #pragma unroll
@@ -260,40 +277,43 @@ __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restri
         sm += X[i] * t->cp_m[i];
         sk += X[i] * t->cp_k[i];
     }
-    const R s3 = sp * sp;
-    const R es3 = sq * sq;
+    const R s3 = sp * sp;                         // sigma_m^3
+    const R es3 = sq * sq;                        // (eps/k)_m sigma_m^3
     const R ws3 = swp * sp;
     const R esm = qform<PM, NS>(t->ESM, X);
     const R mu4 = sm * sm;
     const R km = sk * sk;
-    const R is3 = PM::div(R(1), s3);
+    const R rpq = PM::div(R(1), sp * sq);
+    const R isp = sq * rpq, isq = sp * rpq;
+    const R is3 = isp * isp;
+    const R ies3 = isq * isq;
     const R sgm = PM::cbrt_(s3);                  // sigma_m
     const R em = es3 * is3;                       // (eps/k)_m
-    const R mq = PM::div(esm, em * sgm * sgm);
-    const R Mm = mq * mq;                         // g/mol
+    const R mq = esm * sgm * ies3;                // sqrt(M_m) = esm/((eps/k)_m sigma_m^2)
     const R wm = ws3 * is3;
-    const R vs = sgm * R(1.0 / 0.809);
-    const R Vc23 = vs * vs;                       // Vc_m^(2/3), cm^2/mol^(2/3)
-    const R Vcm = Vc23 * vs;                      // cm^3/mol
+    const R iVc23 = R(0.809 * 0.809) * sgm * is3; // Vc_m^(-2/3) = 0.809^2/sigma_m^2, mol^(2/3)/cm^2
     const R Tcm = R(1.2593) * em;
-    // mu_rm^4 = (131.3 mu_m)^4 / (Vcm Tcm)^2, mu_m^4 = s3 * mu4
-    const R vt = Vcm * Tcm;
-    const R c131 = R(131.3 * 131.3 * 131.3 * 131.3);
-    const R mr4 = PM::div(c131 * s3 * mu4, vt * vt);
-    const R y = rhom * R(1e-6) * Vcm * R(1.0 / 6.0);
-    const R iy = PM::div(R(1), y);
+    const R rsTc = PM::rsqrt_(Tcm);
+    const R sTc = Tcm * rsTc;
+    // mu_rm^4 = (131.3 mu_m)^4/(Vc_m Tc_m)^2 with mu_m^4 = s3 mu4
+    const R mr4 = R(131.3 * 131.3 * 131.3 * 131.3 * (0.809 * 0.809 * 0.809) * (0.809 * 0.809 * 0.809) /
+                    (1.2593 * 1.2593)) * s3 * mu4 * ies3 * ies3;
+    const R y = rhom * s3 * R(1e-6 / (6.0 * 0.809 * 0.809 * 0.809));   // rho Vc_m/6
     const R om1 = R(1) - y;
-    const R G1 = PM::div(R(1) - R(0.5) * y, om1 * om1 * om1);
+    const R om13 = om1 * om1 * om1;
+    const R ry = PM::div(R(1), y * om13);
+    const R iy = om13 * ry;
+    const R G1 = (R(1) - R(0.5) * y) * y * ry;
     if (want_mu) {
         R E[10];
 #pragma unroll
         for (int i = 0; i < 10; i++)
             E[i] = R(kChungE[i][0]) + R(kChungE[i][1]) * wm + R(kChungE[i][2]) * mr4 + R(kChungE[i][3]) * km;
-        const R G2 = chung_G2<PM>(y, G1, iy, E, e2);
-        const R its = PM::div(em, T);  // 1/T*, T* = T/(eps/k)_m
+        R G2, iG2;
+        chung_G2<PM>(y, G1, iy, E, e2, G2, iG2);
+        const R its = em * iT;  // 1/T*, T* = T/(eps/k)_m
         const R muss = E[6] * y * y * G2 * PM::exp_(E[7] + E[8] * its + E[9] * its * its, e2);
-        const R mu = eta0 * (PM::div(R(1), G2) + E[5] * y) +
-                     PM::div(R(36.344e-7) * muss * PM::sqrt_(Mm * Tcm), Vc23);
+        const R mu = eta0 * (iG2 + E[5] * y) + R(36.344e-7) * muss * mq * sTc * iVc23;
         *omu = (double)mu;
     }
     if (want_lam) {
@@ -301,17 +321,21 @@ __device__ __forceinline__ void chung(const MixTab<typename PM::R, NS> *__restri
 #pragma unroll
         for (int i = 0; i < 7; i++)
             Bc[i] = R(kChungB[i][0]) + R(kChungB[i][1]) * wm + R(kChungB[i][2]) * mr4 + R(kChungB[i][3]) * km;
-        const R G2 = chung_G2<PM>(y, G1, iy, Bc, e2);
-        const R Tr = PM::div(T, Tcm);
+        R G2, iG2;
+        chung_G2<PM>(y, G1, iy, Bc, e2, G2, iG2);
+        const R Tr = T * rsTc * rsTc;
         const R al = Cv * R(1.0 / kR) - R(1.5);
         const R be = R(0.7862) - R(0.7109) * wm + R(1.3168) * wm * wm;
         const R Zr = R(2.0) + R(10.5) * Tr * Tr;
-        const R psi = R(1) + al * PM::div(R(0.215) + R(0.28288) * al - R(1.061) * be + R(0.26665) * Zr,
-                                          R(0.6366) + be * Zr + R(1.061) * al * be);
-        const R Mkg = Mm * R(1e-3);
-        const R q = PM::div(R(3.586e-3) * PM::sqrt_(PM::div(Tcm, Mkg)), Vc23);
-        const R lam = PM::div(R(31.2) * eta0 * psi, Mkg) * (PM::div(R(1), G2) + Bc[5] * y) +
-                      q * Bc[6] * y * y * PM::sqrt_(Tr) * G2;
+        const R pn = R(0.215) + R(0.28288) * al - R(1.061) * be + R(0.26665) * Zr;
+        const R pd = R(0.6366) + be * Zr + R(1.061) * al * be;
+        const R rpm = PM::div(R(1), pd * mq);
+        const R psi = R(1) + al * pn * mq * rpm;
+        const R imq = pd * rpm;
+        const R iMkg = R(1e3) * imq * imq;       // 1/M_m in mol/kg
+        // 3.586e-3 sqrt(Tc_m/M_m[kg/mol])/Vc_m^(2/3); 0.1133992768936381 = 3.586e-3/sqrt(1e-3)
+        const R q = R(0.1133992768936381) * sTc * imq * iVc23;
+        const R lam = R(31.2) * eta0 * psi * iMkg * (iG2 + Bc[5] * y) + q * Bc[6] * y * y * sT * rsTc * G2;
         *olam = (double)lam;
     }
 }
@@ -752,7 +776,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     }
     if constexpr (TRANSPORT) {
         double mu = 0, lam = 0;
-        chung<PM, NS>(tm, Xr, (R)T, (R)(1.0 / v), (R)(W * (cp_ig - ig.rw)), a.omu != nullptr,
+        chung<PM, NS>(tm, Xr, (R)T, (R)fm::rcp(v), (R)(W * (cp_ig - ig.rw)), a.omu != nullptr,
                       a.olam != nullptr || (SOLVER && a.oalpha != nullptr), &mu, &lam, e2s);
         if (a.omu) a.omu[k] = mu;
         if (a.olam) a.olam[k] = lam;
