@@ -155,6 +155,15 @@ struct Nasa {
         cp = c0 + T * (c1 + T * (c2 + T * (c3 + T * c4)));
         h = T * (c0 + T * (c1 * 0.5 + T * (c2 * (1.0 / 3.0) + T * (c3 * 0.25 + T * (c4 * 0.2))))) + a6[r];
     }
+    // the same with d c_p/dT
+    __device__ __forceinline__ void eval(double T, double &h, double &cp, double &dcp) const
+    {
+        const int r = (T >= Tmid) ? 1 : 0;
+        const double c0 = c[r][0], c1 = c[r][1], c2 = c[r][2], c3 = c[r][3], c4 = c[r][4];
+        cp = c0 + T * (c1 + T * (c2 + T * (c3 + T * c4)));
+        dcp = c1 + T * (2.0 * c2 + T * (3.0 * c3 + T * (4.0 * c4)));
+        h = T * (c0 + T * (c1 * 0.5 + T * (c2 * (1.0 / 3.0) + T * (c3 * 0.25 + T * (c4 * 0.2))))) + a6[r];
+    }
     // mixture coefficients of the ranges r0..r1 from the mass fractions y.  The table is read
     // here through the scalar cache each time: left to itself the compiler hoists the loads
     // of ~100 table values to the kernel entry while sinking their use, and keeps them alive
@@ -441,6 +450,10 @@ __device__ __forceinline__ double stable_root(double A, double B, uint8_t &st)
 }
 
 // ------------------------------------------------------------------ the kernel
+// Look-ahead stop of the (h, P, Y) inversion: the iteration also ends when the error that
+// quadratic convergence predicts after the last step is below kStopAhead rtol T (with
+// rtol = 1e-10, 1e-15 relative: rounding level).
+constexpr double kStopAhead = 1e-5;
 // Minimum waves per SIMD the register allocation must allow (1: the compiler's choice;
 // forcing 4 or 5 for the 8-species FP64 kernel spills and measured slower).
 #ifndef PR_WAVES_PER_EU
@@ -528,7 +541,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
             const double g = a.Tg[k];
             if (g > kTlo && g < kThi) T = g;
         }
-        bool fin = false, conv = false;
+        bool fin = false, conv = false, lastN = false, lastN2 = false;
         double dT1 = __builtin_inf(), dT2 = __builtin_inf();   // sizes of the last two steps
         int it = 0;
         const double rtol = (PREC == PROPS_FP64) ? a.rtol : fmax(a.rtol, 1e-6);
@@ -569,18 +582,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
             // taken two iterations before (else Newton can cycle where the slope varies
             // strongly, as near pseudo-boiling); otherwise bisection.  A Newton step below
             // rtol ends the iteration: convergence is quadratic, so the updated T is exact
-            // to rounding.  After a small bisection step one more (polishing) step is taken,
-            // which never bisects: a converged T whose step rounds to nothing sits on a
-            // bracket end, and bisecting there would throw it away.
+            // to rounding.  So does the third of three Newton steps d2, d1, d whose
+            // contraction rates d1/d2^2 and d/d1^2 agree within a factor 4 (the quadratic
+            // regime, away from the kinks of h(T) at a phase-choice switch, the NASA range
+            // boundary or a sign change in the mixing sum) once the error left behind it,
+            // about d^3/d1^2, is below kStopAhead rtol T.  After a small bisection step one
+            // more (polishing) step is taken, which never bisects: a converged T whose step
+            // rounds to nothing sits on a bracket end, and bisecting there would throw it away.
             double Tn = T - r * fm::rcp(rp);
             const bool newton = (rp > 0.0) && (Tn >= lo && Tn <= hi) && (fabs(Tn - T) <= 0.5 * dT2);
             if (!newton) Tn = fin ? T : 0.5 * (lo + hi);
-            const double dT = Tn - T;
+            const double dT = Tn - T, adT = fabs(dT);
+            const double d13 = dT1 * dT1 * dT1, r3 = adT * dT2 * dT2;   // r3/d13: ratio of the rates
+            const bool ahead = newton && lastN && lastN2 && r3 >= 0.25 * d13 && r3 <= 4.0 * d13 &&
+                               adT * adT * adT <= kStopAhead * rtol * Tn * dT1 * dT1;
+            lastN2 = lastN;
+            lastN = newton;
             dT2 = dT1;
-            dT1 = fabs(dT);
+            dT1 = adT;
             T = Tn;
             if (fin) { conv = true; break; }
-            if (fabs(dT) <= rtol * T) {
+            if (adT <= rtol * T || ahead) {
                 if (newton) { conv = true; break; }
                 fin = true;
             }
@@ -640,31 +662,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
                 const double rsT = fm::rsqrt(T), sT = T * rsT;
                 R ram, ram1, ram2;
                 mq.eval((R)T, (R)sT, (R)rsT, ram, ram1, ram2);
-                double h_ig, cp_ig;
-                ig.eval(T, h_ig, cp_ig);
+                double h_ig, cp_ig, dcp_ig;
+                ig.eval(T, h_ig, cp_ig, dcp_ig);
                 const double edep = (double)(((R)T * ram1 - ram) * Lw);
                 const double cvdep = (double)((R)T * ram2 * Lw);
                 const double r = h_ig - ig.rw * T + edep - estar;
                 const double rp = cp_ig - ig.rw + cvdep;
+                // d c_v/dT: with a_m'' proportional to T^(-3/2) within the mixing piece,
+                // d(T a_m'')/dT = -a_m''/2
+                const double rpp = dcp_ig - 0.5 * (double)(ram2 * Lw);
                 if (r > 0.0) hi = T;
                 else if (r < 0.0) lo = T;
                 else { conv = true; break; }
-                // Newton step when it stays in the closed bracket and at least halves the step
-                // taken two iterations before (else Newton can cycle where the slope varies
-                // strongly, as near pseudo-boiling); otherwise bisection.  A Newton step below
-                // rtol ends the iteration: convergence is quadratic, so the updated T is exact
-                // to rounding.  After a small bisection step one more (polishing) step is taken,
+                // Chebyshev's third-order step d (1 + q), d = r/r' the Newton step and
+                // q = r r''/(2 r'^2) (the plain Newton step where |q| > 1/2), taken when it
+                // stays in the closed bracket and at least halves the step taken two
+                // iterations before (else the iteration can cycle where the slope varies
+                // strongly, as near pseudo-boiling); otherwise bisection.  Such a step below
+                // rtol ends the iteration: convergence is cubic, so the updated T is exact to
+                // rounding.  After a small bisection step one more (polishing) step is taken,
                 // which never bisects: a converged T whose step rounds to nothing sits on a
                 // bracket end, and bisecting there would throw it away.
-                double Tn = T - r * fm::rcp(rp);
+                const double irp = fm::rcp(rp);
+                const double dN = r * irp;
+                const double q = 0.5 * dN * rpp * irp;
+                double Tn = T - ((fabs(q) <= 0.5) ? dN * (1.0 + q) : dN);
                 const bool newton = (rp > 0.0) && (Tn >= lo && Tn <= hi) && (fabs(Tn - T) <= 0.5 * dT2);
                 if (!newton) Tn = fin ? T : 0.5 * (lo + hi);
-                const double dT = Tn - T;
+                const double dT = Tn - T, adT = fabs(dT);
                 dT2 = dT1;
-                dT1 = fabs(dT);
+                dT1 = adT;
                 T = Tn;
                 if (fin) { conv = true; break; }
-                if (fabs(dT) <= rtol * T) {
+                if (adT <= rtol * T) {
                     if (newton) { conv = true; break; }
                     fin = true;
                 }
