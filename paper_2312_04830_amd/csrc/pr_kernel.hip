@@ -113,17 +113,44 @@ struct MixQuad {
             be[i] = sg * xs * t->k2[i];
         }
         R a0 = 0, a1 = 0, a2 = 0;
+        if constexpr (sizeof(R) == 4) {
+            // K is symmetric with a unit diagonal (k_ii = 0, enforced when the mechanism is
+            // made), so each quadratic form is its diagonal plus twice the sum over i < j:
+            //   alpha.K.beta = sum_i [alpha_i (beta_i + wb_i) + beta_i wa_i],
+            // wa_i = sum_{j>i} K_ij alpha_j, wb_i = sum_{j>i} K_ij beta_j.  Each row's values
+            // are loaded once the previous row is done (the opaque pointer depends on its
+            // result), so that few of them are live in scalar registers.  (In double
+            // precision the full mat-vecs measured faster: the triangular form there changes
+            // the register allocation of the whole kernel for the worse.)
 #pragma unroll
-        for (int i = 0; i < NS; i++) {
-            R wa = 0, wb = 0;
+            for (int i = 0; i < NS; i++) {
+                const MixTab<R, NS> *tr = t0;
+                asm volatile("" : "+s"(tr) : "v"(a2));
+                const __attribute__((address_space(4))) MixTab<R, NS> *tk =
+                    (const __attribute__((address_space(4))) MixTab<R, NS> *)tr;
+                R wa = 0, wb = 0;
 #pragma unroll
-            for (int j = 0; j < NS; j++) {
-                wa += t->K[i][j] * al[j];
-                wb += t->K[i][j] * be[j];
+                for (int j = i + 1; j < NS; j++) {
+                    wa += tk->K[i][j] * al[j];
+                    wb += tk->K[i][j] * be[j];
+                }
+                a0 += al[i] * (al[i] + R(2) * wa);
+                a1 += al[i] * (be[i] + wb) + be[i] * wa;
+                a2 += be[i] * (be[i] + R(2) * wb);
             }
-            a0 += al[i] * wa;
-            a1 += al[i] * wb;
-            a2 += be[i] * wb;
+        } else {
+#pragma unroll
+            for (int i = 0; i < NS; i++) {
+                R wa = 0, wb = 0;
+#pragma unroll
+                for (int j = 0; j < NS; j++) {
+                    wa += t->K[i][j] * al[j];
+                    wb += t->K[i][j] * be[j];
+                }
+                a0 += al[i] * wa;
+                a1 += al[i] * wb;
+                a2 += be[i] * wb;
+            }
         }
         A0 = a0;
         A1 = R(-2) * a1;
@@ -200,14 +227,14 @@ struct Nasa {
 
 // ------------------------------------------------------------------ Chung transport
 // Chung et al. (1988) viscosity coefficients E_i = a + b omega + c mu_r^4 + d kappa.
-__constant__ double kChungE[10][4] = {
+constexpr double kChungE[10][4] = {
     {6.324, 50.412, -51.680, 1189.0},      {1.210e-3, -1.154e-3, -6.257e-3, 0.03728},
     {5.283, 254.209, -168.48, 3898.0},     {6.623, 38.096, -8.464, 31.42},
     {19.745, 7.630, -14.354, 31.53},       {-1.900, -12.537, 4.985, -18.15},
     {24.275, 3.450, -11.291, 69.35},       {0.7972, 1.117, 0.01235, -4.117},
     {-0.2382, 0.06770, -0.8163, 4.025},    {0.06863, 0.3479, 0.5926, -0.727}};
 // Chung et al. (1988) conductivity coefficients B_i.
-__constant__ double kChungB[7][4] = {
+constexpr double kChungB[7][4] = {
     {2.4166, 0.74824, -0.91858, 121.72},   {-0.50924, -1.5094, -49.991, 69.983},
     {6.6107, 5.6207, 64.760, 27.039},      {14.543, -8.9139, -5.6379, 74.344},
     {0.79274, 0.82019, -0.69369, 6.3173},  {-5.8634, 12.801, 9.5893, 65.529},
