@@ -447,15 +447,20 @@ __device__ __forceinline__ int cubic_roots(double A, double B, double z[3])
     return nr;
 }
 
-__device__ __forceinline__ double gdep_RT(double Z, double A, double B)
+// Residual Gibbs energy g_dep/RT = Z - 1 - ln(Z - B) - A/(2 sqrt2 B) ln[(Z + (1+sqrt2)B)/(Z + (1-sqrt2)B)]
+// in single precision with the hardware base-2 logarithm (its arguments are normal numbers
+// here): it only sets the width of the tie band below.
+__device__ __forceinline__ float gdep_RT_f(double Z, float c, double B)
 {
-    return Z - 1.0 - fm::log(Z - B) -
-           A * fm::rcp(2.0 * kSqrt2 * B) * fm::log((Z + (1.0 + kSqrt2) * B) * fm::rcp(Z + (1.0 - kSqrt2) * B));
+    const float q = (float)(Z + (1.0 + kSqrt2) * B) * __builtin_amdgcn_rcpf((float)(Z + (1.0 - kSqrt2) * B));
+    return (float)(Z - 1.0) - 0.6931472f * (__builtin_amdgcn_logf((float)(Z - B)) + c * __builtin_amdgcn_logf(q));
 }
 
 // Z of the stable phase at (A, B): the physical roots are those above B; of the smallest
-// and the largest, the one of lower residual Gibbs energy (a tie within 1e-12 takes the
-// vapour-like root).  NaN if there is no physical root.  Sets THREE_ROOT / GIBBS_TIE in st.
+// and the largest, the one of lower residual Gibbs energy (a tie within
+// 1e-12 max(1, |g_l|, |g_v|) takes the vapour-like root).  NaN if there is no physical root.
+// Sets THREE_ROOT / GIBBS_TIE in st.  The difference g_l - g_v is taken in one expression
+// (two logarithms of ratios instead of four logarithms, and no cancellation between them).
 __device__ __forceinline__ double stable_root(double A, double B, uint8_t &st)
 {
     double z[3];
@@ -467,13 +472,17 @@ __device__ __forceinline__ double stable_root(double A, double B, uint8_t &st)
     if (np == 1) return zv;
     const double zl = (z[0] > B) ? z[0] : z[1];
     if (np == 3) st |= PROPS_ST_THREE_ROOT;
-    const double gl = gdep_RT(zl, A, B), gv = gdep_RT(zv, A, B);
-    const double tie = 1e-12 * fmax(1.0, fmax(fabs(gl), fabs(gv)));
-    if (fabs(gl - gv) <= tie) {
+    const double c = A * fm::rcp(2.0 * kSqrt2 * B);
+    const double lp = zl + (1.0 + kSqrt2) * B, lm = zl + (1.0 - kSqrt2) * B;
+    const double vp = zv + (1.0 + kSqrt2) * B, vm = zv + (1.0 - kSqrt2) * B;
+    const double dg = (zl - zv) - fm::log((zl - B) * fm::rcp(zv - B)) - c * fm::log((lp * vm) * fm::rcp(lm * vp));
+    const float cf = (float)c;
+    const double tie = 1e-12 * (double)fmaxf(1.0f, fmaxf(fabsf(gdep_RT_f(zl, cf, B)), fabsf(gdep_RT_f(zv, cf, B))));
+    if (fabs(dg) <= tie) {
         st |= PROPS_ST_GIBBS_TIE;
         return zv;
     }
-    return (gl < gv) ? zl : zv;
+    return (dg < 0.0) ? zl : zv;
 }
 
 // ------------------------------------------------------------------ the kernel
@@ -793,7 +802,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
         const R dPdv = -PM::div((R)RT, rvb * rvb) + PM::div(R(2) * ram * (rv + rb), rden * rden);
         const R cvm = (R)(W * (cp_ig - ig.rw)) + cvdep;
         const R cpm = cvm - PM::div(rT * dPdT * dPdT, dPdv);
-        const R c2 = -PM::div(rv * rv, (R)W) * PM::div(cpm, cvm) * dPdv;
+        const R c2 = -(rv * rv * (R)syw) * PM::div(cpm, cvm) * dPdv;   // 1/W = sum Y_i/W_i
         const double hdep = (double)edep + P * v - RT;
         h = h_ig + hdep * syw;
         e = h_ig - ig.rw * T + (double)edep * syw;
@@ -812,7 +821,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     if (a.oT) a.oT[k] = T;
     if (a.oP) a.oP[k] = P;
     if (a.oZ) a.oZ[k] = P * v * fm::rcp(RT);
-    if (a.orho) a.orho[k] = W * fm::rcp(v);
+    // in (rho, e, Y) mode the density is the input; 1/v = rho/W = rho sum Y_i/W_i
+    const double iv = (MODE == PROPS_RHOEY) ? in0 * syw : fm::rcp(v);
+    if (a.orho) a.orho[k] = (MODE == PROPS_RHOEY) ? in0 : W * iv;
     if (a.oh) a.oh[k] = h;
     if (a.oe) a.oe[k] = e;
     if (a.ocp) a.ocp[k] = cp;
@@ -833,7 +844,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PE
     }
     if constexpr (TRANSPORT) {
         double mu = 0, lam = 0;
-        chung<PM, NS>(tm, Xr, (R)T, (R)fm::rcp(v), (R)(W * (cp_ig - ig.rw)), a.omu != nullptr,
+        chung<PM, NS>(tm, Xr, (R)T, (R)iv, (R)(W * (cp_ig - ig.rw)), a.omu != nullptr,
                       a.olam != nullptr || (SOLVER && a.oalpha != nullptr), &mu, &lam, e2s);
         if (a.omu) a.omu[k] = mu;
         if (a.olam) a.olam[k] = lam;
