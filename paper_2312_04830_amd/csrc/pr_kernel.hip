@@ -491,16 +491,21 @@ __device__ __forceinline__ double stable_root(double A, double B, uint8_t &st)
 // rtol = 1e-10, 1e-15 relative: rounding level).
 constexpr double kStopAhead = 1e-5;
 // Minimum waves per SIMD the register allocation must allow (1: the compiler's choice;
-// forcing 4 or 5 for the 8-species FP64 kernel spills and measured slower).
+// forcing 4 or 5 for the 8-species FP64 kernel spills and measured slower).  The (h, P, Y)
+// kernels, left to themselves at 185-213 VGPRs (2 waves), are held to 3 waves: a spill of
+// a few values to scratch, mixed precision 3 % faster, double precision unchanged.
 #ifndef PR_WAVES_PER_EU
 #define PR_WAVES_PER_EU 1
+#endif
+#ifndef PR_HPY_WAVES
+#define PR_HPY_WAVES 3
 #endif
 // OUTS selects optional output groups at compile time, so that a launch carries only the
 // code (and the register pressure) of what it writes: bit 0 the transport model (mu,
 // lambda, alpha), bit 1 the solver outputs (psi, alpha, h_i/RT).
 constexpr int kOutTransport = 1, kOutSolver = 2;
 template <int NS, int MODE, int PREC, int OUTS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PR_WAVES_PER_EU))) void pr_kernel(const ThermoTab<NS> *__restrict__ tt,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PROPS_HPY ? PR_HPY_WAVES : PR_WAVES_PER_EU))) void pr_kernel(const ThermoTab<NS> *__restrict__ tt,
                                                  const MixTab<double, NS> *__restrict__ tmd,
                                                  const MixTab<float, NS> *__restrict__ tmf,
                                                  PRArgs a)
