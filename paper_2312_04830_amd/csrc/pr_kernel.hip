@@ -83,7 +83,7 @@ struct PRArgs {
 // and a_m' = A1/(2s) + A2, a_m'' = -A1/(4 s T).  The two mat-vecs are done once per sign
 // pattern; every Newton evaluation is then O(1).  MixQuad::lo/hi bound the T interval in
 // which the pattern holds.
-template <class PM, int NS>
+template <class PM, int NS, bool TRI>
 struct MixQuad {
     using R = typename PM::R;
     R A0, A1, A2;
@@ -113,15 +113,13 @@ struct MixQuad {
             be[i] = sg * xs * t->k2[i];
         }
         R a0 = 0, a1 = 0, a2 = 0;
-        if constexpr (sizeof(R) == 4) {
+        if constexpr (TRI) {
             // K is symmetric with a unit diagonal (k_ii = 0, enforced when the mechanism is
             // made), so each quadratic form is its diagonal plus twice the sum over i < j:
             //   alpha.K.beta = sum_i [alpha_i (beta_i + wb_i) + beta_i wa_i],
             // wa_i = sum_{j>i} K_ij alpha_j, wb_i = sum_{j>i} K_ij beta_j.  Each row's values
             // are loaded once the previous row is done (the opaque pointer depends on its
-            // result), so that few of them are live in scalar registers.  (In double
-            // precision the full mat-vecs measured faster: the triangular form there changes
-            // the register allocation of the whole kernel for the worse.)
+            // result), so that few of them are live in scalar registers.
 #pragma unroll
             for (int i = 0; i < NS; i++) {
                 const MixTab<R, NS> *tr = t0;
@@ -533,6 +531,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
         return;
     }
     const int64_t n = a.n;
+    // mixing build over the pairs i < j (see MixQuad::build) in single precision and in the
+    // (P, T, Y) kernels (measured: (P, T, Y) with transport 3 % faster; the double-precision
+    // (rho, e, Y) and (h, P, Y) kernels 12 % and 1.5 % slower, so they keep the full mat-vecs)
+    constexpr bool kTriMix = (PREC == PROPS_MIXED) || (MODE == PROPS_PTY);
 
     // ---- composition and input checks
     double y[NS];
@@ -586,7 +588,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
         double dT1 = __builtin_inf(), dT2 = __builtin_inf();   // sizes of the last two steps
         int it = 0;
         const double rtol = (PREC == PROPS_FP64) ? a.rtol : fmax(a.rtol, 1e-6);
-        MixQuad<PM, NS> mq;
+        MixQuad<PM, NS, kTriMix> mq;
         mq.build(tm, Xr, T);
         for (; it < a.maxit; it++) {
             if (!mq.valid(T)) mq.build(tm, Xr, T);
@@ -661,7 +663,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
             P = in0;
             T = in1;
         }
-        MixQuad<PM, NS> mq;
+        MixQuad<PM, NS, kTriMix> mq;
         mq.build(tm, Xr, T);
         const double rsT = fm::rsqrt(T), sT = T * rsT;
         R ram, ram1, ram2;
@@ -696,7 +698,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
             // With single-precision departures the residual carries ~1e-7 relative noise,
             // so the step criterion is held at 1e-6 there (the double path keeps rtol).
             const double rtol = (PREC == PROPS_FP64) ? a.rtol : fmax(a.rtol, 1e-6);
-            MixQuad<PM, NS> mq;
+            MixQuad<PM, NS, kTriMix> mq;
             mq.build(tm, Xr, T);
             for (; it < a.maxit; it++) {
                 if (!mq.valid(T)) mq.build(tm, Xr, T);
