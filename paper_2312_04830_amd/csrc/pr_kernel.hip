@@ -5,14 +5,15 @@
 //   alpha / mixing   g_i = sqrt(a_c,i) |1 + kappa_i (1 - sqrt(T/Tc_i))|,
 //                    a_m = sum_ij X_i X_j (1 - k_ij) g_i g_j, exactly A0 + A1 sqrt(T) + A2 T
 //                    between the temperatures where a factor changes sign: coefficients from
-//                    two mat-vecs with the (1 - k_ij) matrix, then O(1) per evaluation
+//                    two mat-vecs with the (1 - k_ij) matrix (over the pairs i < j in some
+//                    kernels), then O(1) per evaluation
 //   ideal gas        per-cell NASA-7 mixture coefficients, one Horner each for h, cp
 //   (P,T,Y)          cubic in Z (largest root in closed form, deflation for the others,
 //                    Newton polish, double), physical roots Z > B, minimum residual Gibbs
 //                    energy between the liquid- and vapour-like root
-//   (rho,e,Y)        bracketed Newton on e(T; v, Y) = e* (v fixed, so the departure log is
-//                    computed once), bisection whenever a step leaves the bracket or fails
-//                    to halve
+//   (rho,e,Y)        bracketed Newton-type iteration (Chebyshev's third-order step) on
+//                    e(T; v, Y) = e* (v fixed, so the departure log is computed once),
+//                    bisection whenever a step leaves the bracket or fails to halve
 //   (h,P,Y)          the pressure-based solver's state (Section 3): bracketed Newton on
 //                    h(T; P, Y) = h* with the cubic and root choice inside every evaluation
 //                    and the real-fluid cp as the slope
@@ -35,7 +36,7 @@ namespace props {
 
 // ------------------------------------------------------------------ precision policies
 // Double precision: the table-driven exp (table in LDS), the lean log and the refined
-// reciprocal of fastmath.hpp, the device library's expm1 (a few ulp; outputs stay within
+// reciprocal and reciprocal square root of fastmath.hpp, the device library's expm1 (a few ulp; outputs stay within
 // 1e-15 relative of correctly rounded maths).
 struct P64 {
     using R = double;
@@ -677,7 +678,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
         if (!(Z == Z)) bad = true;
         v = Z * RT * fm::rcp(P);
     } else if (MODE == PROPS_RHOEY && !bad) {
-        // ---- (rho, e, Y): bracketed Newton on e(T) at fixed v
+        // ---- (rho, e, Y): bracketed Chebyshev (third-order Newton) iteration on e(T) at fixed v
         v = W * fm::rcp(in0);
         if (!(v > bm)) {
             bad = true;
