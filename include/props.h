@@ -84,10 +84,13 @@ int props_mech_create(const props_species_desc *sp, int ns, const double *kij,
 void props_mech_destroy(props_mech_t m);
 int props_mech_num_species(props_mech_t m);
 
-/* Newton options of the (rho, e, Y) and (h, P, Y) inversions: max_iter >= 1 (default 100)
- * and the relative step size that ends the iteration (default 1e-10): a Newton step at
- * most this small is the last one (convergence is quadratic); after a bisection step that
- * small, one more Newton step is taken. */
+/* Iteration options of the (rho, e, Y) and (h, P, Y) inversions: max_iter >= 1 (default
+ * 100) and the relative step size that ends the iteration (default 1e-10): a Newton-type
+ * step at most this small is the last one (convergence is cubic for (rho, e, Y), which
+ * takes Chebyshev's third-order step, and quadratic for (h, P, Y)); after a bisection step
+ * that small, one more step is taken.  (h, P, Y) also ends after three Newton steps of
+ * consistent quadratic contraction once the error they predict is below 1e-5 rtol T.
+ * max_iter and rtol outside [1, 10000] and (0, 1) return PROPS_EINVAL. */
 int props_mech_set_newton(props_mech_t m, int max_iter, double rtol);
 
 /* ------------------------------------------------------------------ property evaluation */
