@@ -125,8 +125,9 @@ typedef struct {
 /* Evaluate the Peng-Robinson property path on n independent cells.
  *   PROPS_PTY:   given P, T, Y: solve the cubic of Eq. (1) for Z, choose among physical
  *                roots (Z > B) by minimum Gibbs energy, then rho, h, e, cp, c (+ mu, lambda).
- *   PROPS_RHOEY: given rho, e, Y: find T with e(T; v = W/rho, Y) = e* by bracketed Newton
- *                iteration on [60, 5000] K, then P from Eq. (1) and every property.
+ *   PROPS_RHOEY: given rho, e, Y: find T with e(T; v = W/rho, Y) = e* by a bracketed
+ *                Newton-type (Chebyshev) iteration on [60, 5000] K, then P from Eq. (1) and
+ *                every property.
  *   PROPS_HPY:   given h, P, Y (the state of the pressure-based solver, Section 3): find T
  *                with h(T; P, Y) = h* by bracketed Newton iteration on [60, 5000] K, the
  *                cubic and root choice of PROPS_PTY inside every evaluation, the slope
