@@ -36,10 +36,10 @@ enum {
     PROPS_ENOMEM = -2,    /* device or host allocation failed */
     PROPS_EHIP = -3,      /* a HIP runtime call failed (message names it) */
     PROPS_ETOOBIG = -4,   /* request exceeds a fixed limit (species count, budget, cell
-                           * count: props_pr, props_diffusion and props_features_hpz take
-                           * n <= (2^31 - 1) * 256,
-                           * one lane per cell in blocks of 256; props_dnn and props_dnn_features
-                           * take n <= 2^31 - 1) */
+                           * count: props_pr and props_diffusion take
+                           * n <= (2^31 - 1) * 64, one lane per cell in blocks of 64;
+                           * props_features_hpz n <= (2^31 - 1) * 256, blocks of 256;
+                           * props_dnn and props_dnn_features n <= 2^31 - 1) */
     PROPS_ETIMEDOUT = -5, /* serve_wait ran out of time */
     PROPS_ENOTREADY = -6  /* object not in a usable state (e.g. network not trained) */
 };

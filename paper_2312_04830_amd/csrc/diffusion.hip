@@ -46,6 +46,9 @@ struct DiffArgs {
     int ns;
 };
 
+// one wavefront per block (as the property kernels; the table below is staged one entry per thread)
+constexpr int kDiffBlock = 64;
+
 template <int NS, int PREC>
 __global__ __launch_bounds__(256) void diffusion_kernel(const ThermoTab<NS> *__restrict__ tt,
                                                         const DiffTab<double, NS> *__restrict__ tdd,
@@ -139,9 +142,9 @@ int launch_ns(const props_mech_s *m, const DiffArgs &a, hipStream_t s)
     const auto *tt = reinterpret_cast<const ThermoTab<NS> *>(base);
     const auto *tdd = reinterpret_cast<const DiffTab<double, NS> *>(base + m->off_diffd);
     const auto *tdf = reinterpret_cast<const DiffTab<float, NS> *>(base + m->off_difff);
-    const int64_t blocks = (a.n + 255) / 256;
+    const int64_t blocks = (a.n + kDiffBlock - 1) / kDiffBlock;
     if (blocks > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_diffusion: n = %lld too large", (long long)a.n);
-    hipLaunchKernelGGL((diffusion_kernel<NS, PREC>), dim3((unsigned)blocks), dim3(256), 0, s, tt, tdd, tdf, a);
+    hipLaunchKernelGGL((diffusion_kernel<NS, PREC>), dim3((unsigned)blocks), dim3(kDiffBlock), 0, s, tt, tdd, tdf, a);
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
 }

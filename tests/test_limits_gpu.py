@@ -11,6 +11,7 @@ pytestmark = pytest.mark.gpu
 
 ETOOBIG = -4
 HUGE_GRID = 0x7FFFFFFF * 256 + 1      # one more cell than 2^31 - 1 blocks of 256 lanes
+HUGE_GRID_PR = 0x7FFFFFFF * 64 + 1    # the same for the blocks of 64 lanes of props_pr and props_diffusion
 HUGE_INT = 0x7FFFFFFF + 1             # beyond a 32-bit cell index
 
 
@@ -42,13 +43,13 @@ def test_pr_refuses_a_grid_beyond_the_launch_limit(props, mech, tiny, mode):
     pin = props._lib.PropsIn(P=p, T=p, rho=p, e=p, Y=p, h=p)
     pout = props._lib.PropsOut(T=p)
     rc = props.lib().props_pr(mech.handle, getattr(props, mode), props.FP64, ctypes.byref(pin), ctypes.byref(pout),
-                              HUGE_GRID, None, None)
+                              HUGE_GRID_PR, None, None)
     assert rc == ETOOBIG, props.lib().props_last_error()
 
 
 def test_diffusion_refuses_a_grid_beyond_the_launch_limit(props, mech, tiny):
     p = tiny.data_ptr()
-    rc = props.lib().props_diffusion(mech.handle, props.FP64, p, p, p, p, HUGE_GRID, None, None)
+    rc = props.lib().props_diffusion(mech.handle, props.FP64, p, p, p, p, HUGE_GRID_PR, None, None)
     assert rc == ETOOBIG, props.lib().props_last_error()
 
 
