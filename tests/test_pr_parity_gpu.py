@@ -153,6 +153,32 @@ def test_mixed_precision_error_report(props, orc, sp8, kij8):
         assert statsp[f][0] <= 1e-3, (f, statsp[f])
 
 
+@pytest.mark.parametrize("mode", ["PTY", "RHOEY", "HPY"])
+def test_mixed_precision_ragged_launch(props, orc, sp8, kij8, mode):
+    """Mixed precision (launched in blocks of 64 lanes) on cell counts that end inside a
+    block, and on one cell: every cell is written, each within the mixed-precision bar of the
+    FP64 oracle (outputs are pre-filled with a sentinel, status with 255)."""
+    P, T, Y = synth.flame_field(16, seed=12)
+    om = orc.Mech(sp8, kij8)
+    gm = props.Mechanism(sp8, kij8)
+    for n in (T.size - 37, 65, 1):
+        Pn, Tn, Yn = P[:n], T[:n], np.ascontiguousarray(Y[:, :n])
+        st = om.state_PT(Pn, Tn, Yn, transport=(mode == "PTY"))
+        if mode == "PTY":
+            ref, inputs = st, {"P": Pn, "T": Tn, "Y": Yn}
+        elif mode == "RHOEY":
+            ref = om.state_rhoe(st["rho"], st["e"], Yn)
+            inputs = {"rho": st["rho"], "e": st["e"], "Y": Yn, "T_guess": synth.temperature_guess(Tn)}
+        else:
+            ref = om.state_hP(st["h"], Pn, Yn)
+            inputs = {"h": st["h"], "P": Pn, "Y": Yn, "T_guess": synth.temperature_guess(Tn)}
+        g = run_gpu(props, gm, getattr(props, mode), props.MIXED, n, inputs)
+        assert np.all(g["status"] == 0), (n, np.unique(g["status"]))
+        stats = rel_err_stats(g, ref)
+        for f, (mx, _) in stats.items():
+            assert mx <= 1e-3, (mode, n, f, mx)
+
+
 # ------------------------------------------------------------------ edge cases
 
 def test_three_root_gibbs_selection(props, orc):
