@@ -99,6 +99,37 @@ def test_rhoey_fp64_flame_field(props, orc, sp8, kij8, guess):
     assert np.max(np.abs(g["T"] / T - 1)) < 1e-11
 
 
+@pytest.mark.parametrize("guess_rel", [0.3, None])
+def test_rhoey_fp64_wide_states_poor_guess(props, orc, sp8, kij8, guess_rel):
+    """(rho, e, Y) on states far from the flame field's: T ~ U[100, 4800] K (across the NASA
+    range switch and every sign change of the mixing sum), P ~ U[1, 30] MPa, random
+    8-species compositions, started from a poor guess (30 % spread, clipped into the bracket
+    by the kernel where it falls outside) or from the top of the bracket: the iteration's
+    bisection fallbacks and third-order steps meet the oracle's plain Newton at every cell.
+    The thermodynamic outputs are compared; transport is not: at such arbitrary compositions
+    and densities Chung's dense-fluid viscosity cancels (and turns negative for ~1 % of the
+    cells), so the two sides agree only to that cancellation's rounding, which the
+    thermodynamic condition number of the tolerance does not cover.  Transport parity is
+    tested on the flame field's compositions."""
+    rng = np.random.default_rng(77)
+    n = 2048
+    P = rng.uniform(1.0e6, 30.0e6, n)
+    T = rng.uniform(100.0, 4800.0, n)
+    Y = rng.uniform(0.0, 1.0, (8, n))
+    Y /= Y.sum(axis=0)
+    om = orc.Mech(sp8, kij8)
+    st = om.state_PT(P, T, Y, transport=False)
+    ref = om.state_rhoe(st["rho"], st["e"], Y)
+    Tg = None if guess_rel is None else synth.temperature_guess(T, seed=78, rel=guess_rel)
+    g = run_gpu(props, props.Mechanism(sp8, kij8), props.RHOEY, props.FP64, n,
+                {"rho": st["rho"], "e": st["e"], "Y": Y, "T_guess": Tg}, fields=FIELDS + ("iters",))
+    assert np.array_equal(g["status"], ref["status"]), np.unique(g["status"] - ref["status"])
+    worst = compare(g, ref, 1, FP64_RTOL, fields=[f for f in FIELDS if f not in ("mu", "lambda")])
+    _report(f"rhoey fp64 wide states guess={guess_rel}", worst)
+    assert max(worst.values()) <= 1.0, worst
+    assert g["iters"].max() <= 40, np.bincount(g["iters"].astype(np.int64))
+
+
 def test_rhoey_fp64_full_field_sampled(props, orc, sp8, kij8):
     """The 128^3 flame field in the benchmark's launch configuration; a seeded sample of
     cells is recomputed by the oracle one by one."""
