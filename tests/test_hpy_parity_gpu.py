@@ -274,6 +274,33 @@ def test_hpy_mixed_error_report(props, orc, sp8, kij8):
         assert stats[f][0] <= 1e-3, (f, stats[f])
 
 
+@pytest.mark.parametrize("guess_rel", [0.3, None])
+def test_hpy_fp64_wide_states_poor_guess(props, orc, sp8, kij8, guess_rel):
+    """(h, P, Y) on states far from the flame field's (T ~ U[100, 4800] K, P ~ U[1, 30] MPa,
+    random 8-species compositions) from a poor guess or from the bracket top: the Newton
+    iteration with its bisection fallbacks and its look-ahead stop (three steps of consistent
+    quadratic contraction) meets the oracle at every cell.  Thermodynamic outputs only: at
+    such compositions Chung's viscosity cancels (see the (rho, e, Y) wide-state test)."""
+    rng = np.random.default_rng(79)
+    n = 2048
+    P = rng.uniform(1.0e6, 30.0e6, n)
+    T = rng.uniform(100.0, 4800.0, n)
+    Y = rng.uniform(0.0, 1.0, (8, n))
+    Y /= Y.sum(axis=0)
+    om = orc.Mech(sp8, kij8)
+    h = om.state_PT(P, T, Y, transport=False)["h"]
+    ref = om.state_hP(h, P, Y)
+    Tg = None if guess_rel is None else synth.temperature_guess(T, seed=80, rel=guess_rel)
+    g = run_gpu(props, props.Mechanism(sp8, kij8), props.HPY, props.FP64, n,
+                {"h": h, "P": P, "Y": Y, "T_guess": Tg}, fields=FIELDS + ("iters",))
+    assert np.array_equal(g["status"], ref["status"]), np.unique(g["status"] - ref["status"])
+    worst = hp_compare(om, g, ref, P, Y, FP64_RTOL, fields=[f for f in FIELDS if f not in ("mu", "lambda")])
+    print(f"\n[hpy fp64 wide states guess={guess_rel}] worst err/tol: "
+          + ", ".join(f"{k}={v:.3g}" for k, v in worst.items()), flush=True)
+    assert max(worst.values()) <= 1.0, worst
+    assert g["iters"].max() <= 40, np.bincount(g["iters"].astype(np.int64))
+
+
 def test_hpy_newton_iteration_limit_and_empty_launch(props, orc, sp8, kij8):
     import torch
     P, T, Y = synth.flame_field(6, seed=3)
