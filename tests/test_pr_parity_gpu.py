@@ -130,6 +130,36 @@ def test_rhoey_fp64_wide_states_poor_guess(props, orc, sp8, kij8, guess_rel):
     assert g["iters"].max() <= 40, np.bincount(g["iters"].astype(np.int64))
 
 
+@pytest.mark.parametrize("mode", ["RHOEY", "HPY"])
+def test_mixed_precision_wide_states_poor_guess(props, orc, sp8, kij8, mode):
+    """The mixed-precision inversions on the wide states of the FP64 test above, from a poor
+    guess: every cell converges, thermodynamic outputs within the mixed-precision bar."""
+    rng = np.random.default_rng(77)
+    n = 2048
+    P = rng.uniform(1.0e6, 30.0e6, n)
+    T = rng.uniform(100.0, 4800.0, n)
+    Y = rng.uniform(0.0, 1.0, (8, n))
+    Y /= Y.sum(axis=0)
+    om = orc.Mech(sp8, kij8)
+    st = om.state_PT(P, T, Y, transport=False)
+    Tg = synth.temperature_guess(T, seed=78, rel=0.3)
+    if mode == "RHOEY":
+        ref = om.state_rhoe(st["rho"], st["e"], Y)
+        inputs = {"rho": st["rho"], "e": st["e"], "Y": Y, "T_guess": Tg}
+    else:
+        ref = om.state_hP(st["h"], P, Y)
+        inputs = {"h": st["h"], "P": P, "Y": Y, "T_guess": Tg}
+    g = run_gpu(props, props.Mechanism(sp8, kij8), getattr(props, mode), props.MIXED, n, inputs,
+                fields=FIELDS + ("iters",))
+    assert np.array_equal(g["status"], ref["status"]), np.unique(g["status"] - ref["status"])
+    stats = rel_err_stats(g, ref, fields=[f for f in FIELDS if f not in ("mu", "lambda")])
+    print(f"\n[mixed {mode.lower()} wide states] max/rms rel err: "
+          + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in stats.items()), flush=True)
+    for f, (mx, _) in stats.items():
+        assert mx <= 1e-3, (f, mx)
+    assert g["iters"].max() <= 40, np.bincount(g["iters"].astype(np.int64))
+
+
 def test_rhoey_fp64_full_field_sampled(props, orc, sp8, kij8):
     """The 128^3 flame field in the benchmark's launch configuration; a seeded sample of
     cells is recomputed by the oracle one by one."""
