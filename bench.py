@@ -138,7 +138,8 @@ def cpu_baseline(res, target_s=15.0):
     om.eval(oracle.RHOE, s1["rho"], s1["e"], Y1, nthreads=1)
     dt1 = time.perf_counter() - t0
     return {"value": idx.size / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
-            "sample": f"every {stride}th cell of the {res}^3 field ({idx.size} cells), FP64 (rho,e,Y) "
+            "sample": (f"every {stride}th cell" if stride > 1 else "every cell") +
+                      f" of the {res}^3 field ({idx.size} cells), FP64 (rho,e,Y) "
                       f"by bisection + Chung transport, {dt:.1f} s",
             "single_thread_value": i1.size / dt1, "single_thread_sample_cells": int(i1.size),
             "cpu_model": _cpu_model()}
@@ -740,7 +741,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"{args.res}^3 supercritical CH4/O2 Taylor-Green flame field, 8 species, "
-                               "(rho,e,Y)->T Newton + PR departures + Chung mu/lambda, FP64, T_guess",
+                               "(rho,e,Y)->T Newton-type (Chebyshev) + PR departures + Chung mu/lambda, FP64, T_guess",
                    "cells": n, "species": ns, "mode": "RHOEY", "precision": "FP64",
                    "kij": "dense synthetic U[0,0.1]"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
