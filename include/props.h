@@ -36,10 +36,10 @@ enum {
     PROPS_ENOMEM = -2,    /* device or host allocation failed */
     PROPS_EHIP = -3,      /* a HIP runtime call failed (message names it) */
     PROPS_ETOOBIG = -4,   /* request exceeds a fixed limit (species count, budget, cell
-                           * count: props_pr and props_diffusion take
-                           * n <= (2^31 - 1) * 64, one lane per cell in blocks of 64;
-                           * props_features_hpz n <= (2^31 - 1) * 256, blocks of 256;
-                           * props_dnn and props_dnn_features n <= 2^31 - 1) */
+                           * count: props_pr, props_diffusion and props_features_hpz take
+                           * n <= 2^32 - 256 = 4294967040, one lane per cell, because one
+                           * dispatch holds at most 2^32 - 1 work-items; props_dnn and
+                           * props_dnn_features n <= 2^31 - 1, a 32-bit cell index) */
     PROPS_ETIMEDOUT = -5, /* serve_wait ran out of time */
     PROPS_ENOTREADY = -6  /* object not in a usable state (e.g. network not trained) */
 };
@@ -185,7 +185,9 @@ void props_dnn_destroy(props_dnn_t net);
 int props_dnn_get_layer(props_dnn_t net, int l, float *W, float *b);
 int props_dnn_set_layer(props_dnn_t net, int l, const float *W, const float *b);
 
-/* Host scalers: in_lo/in_hi[10] raw input box (also the hull), out_lo/out_hi[6] box of
+/* Host scalers: in_lo/in_hi[10] raw input box (also the hull: a cell is inside when every
+ * feature lies in [lo, hi] to 1e-9 of the range, or, for a feature with lo = hi, within
+ * 1e-9 max(1, |lo|) of lo; such a feature scales to 0), out_lo/out_hi[6] box of
  * the transformed targets. */
 int props_dnn_get_scalers(props_dnn_t net, double *in_lo, double *in_hi, double *out_lo, double *out_hi);
 int props_dnn_set_scalers(props_dnn_t net, const double *in_lo, const double *in_hi,
@@ -214,8 +216,11 @@ int props_dnn_load(const char *path, props_dnn_t *out);
  * PROPS_ST_OUT_OF_HULL; if `fallback` is not NULL they are recomputed by
  * props_pr(PROPS_PTY, PROPS_MIXED) on the device and also get PROPS_ST_FALLBACK, without a
  * host synchronisation.  The network must share the mechanism's species order.
- * Asynchronous on hip_stream; may grow an internal index buffer (hipMalloc) when n
- * exceeds every previous call. */
+ * Asynchronous on hip_stream.  With a fallback the call
+ * keeps its list of flagged cells in a buffer of the handle, grown (hipMalloc, after
+ * synchronising hip_stream) when n exceeds every previous call: calls on one handle must
+ * therefore not overlap on different streams (serialise them, or use one handle per
+ * stream; the server keeps a list per slot). */
 int props_dnn(props_dnn_t net, props_mech_t fallback, const props_in *in, const props_out *out,
               int64_t n, uint8_t *status, void *hip_stream);
 
@@ -278,17 +283,21 @@ int props_dnn_grad(props_dnn_t net, const float *X, const float *Y, int64_t n, f
 
 /* ------------------------------------------------------------------ serving */
 /* A request loop for concurrent solver subdomains (paper, Section 4.4: property inference
- * served by a GPU beside a CPU solver).  Requests carry HOST arrays (pinned memory,
- * e.g. hipHostMalloc, makes the copies asynchronous).  The server owns a device arena of
- * `mem_budget` bytes cut into slots of `chunk_cells` cells; each request is split into
- * chunks that are admitted as slots free up, round-robin across the active requests
- * (a small request never waits for a large one to finish), copied in, evaluated and
- * copied out on a pool of streams so chunks of different requests overlap on the device.
- * Mechanism tables and network weights stay resident.  A cell's result does not depend
- * on which chunk, slot or stream carried it. */
+ * served by a GPU beside the solver).  Requests carry device arrays (PROPS_MEM_DEVICE, the
+ * default), evaluated in place, or host arrays (PROPS_MEM_HOST; pinned memory, e.g.
+ * hipHostMalloc, makes the copies asynchronous) staged through device slots.  The server
+ * owns a device arena of `mem_budget` bytes cut into slots of `chunk_cells` cells; each
+ * request is split into chunks that are admitted as slots free up, round-robin across the
+ * active requests (a small request never waits for a large one to finish), and evaluated
+ * (host requests: copied in, evaluated, copied out) on a pool of streams so chunks of
+ * different requests overlap on the device.  A slot holds a chunk's staging buffers and its
+ * fallback list, so the number of slots bounds the chunks in flight.  Mechanism tables and
+ * network weights stay resident.  A cell's result does not depend on which chunk, slot or
+ * stream carried it. */
 typedef struct props_server_s *props_server_t;
 
 enum { PROPS_ROUTE_PR_FP64 = 0, PROPS_ROUTE_PR_MIXED = 1, PROPS_ROUTE_DNN = 2 };
+enum { PROPS_MEM_DEVICE = 0, PROPS_MEM_HOST = 1 };
 enum { PROPS_EXEC_GPU = 0, PROPS_EXEC_MOCK = 1 };
 
 typedef struct {
@@ -306,9 +315,13 @@ typedef struct {
     int mode;                 /* PROPS_PTY, PROPS_RHOEY or PROPS_HPY (PROPS_ROUTE_DNN: PTY only) */
     int route;                /* PROPS_ROUTE_* */
     int64_t n;
-    props_in in;              /* HOST arrays (Y: [ns][n]) */
-    props_out out;            /* HOST arrays; NULL members are not returned */
-    uint8_t *status;          /* HOST, optional */
+    props_in in;              /* Y: [ns][n] */
+    props_out out;            /* NULL members are not returned.  PROPS_ROUTE_DNN returns rho,
+                                 h, cp, c, mu and lambda only (any other member: EINVAL);
+                                 psi, alpha, hRT and iters need PROPS_MEM_DEVICE */
+    uint8_t *status;          /* optional */
+    int memory;               /* PROPS_MEM_DEVICE: in, out and status are device arrays on
+                                 the server's device; PROPS_MEM_HOST: host arrays */
 } props_request;
 
 typedef struct {
@@ -327,12 +340,15 @@ typedef struct {
 
 /* mech is required (except by the mock executor); dnn may be NULL (then PROPS_ROUTE_DNN
  * is refused).  The server does not own mech or dnn, which must outlive it.  The mock
- * executor evaluates a fixed function of each cell's inputs on host threads, and fails a
- * chunk whose first input value is NaN (to exercise failure paths). */
+ * executor evaluates a fixed function of each cell's inputs on host threads (it takes
+ * PROPS_MEM_HOST requests only), and fails a chunk whose first input value is NaN (to
+ * exercise failure paths). */
 int serve_create(const props_serve_cfg *cfg, props_mech_t mech, props_dnn_t dnn,
                  props_server_t *out);
-/* Thread-safe and non-blocking.  The request's host arrays must stay valid until
- * serve_wait reports it done. */
+/* Thread-safe and non-blocking.  The request's arrays must stay valid (and, for device
+ * requests, unmodified by the caller) until serve_wait reports it done; a device request's
+ * input arrays must be ready when it is submitted (the server's streams do not wait on the
+ * caller's). */
 int serve_submit(props_server_t s, const props_request *req, uint64_t *ticket);
 /* Wait for a ticket (timeout_us < 0: forever).  PROPS_ETIMEDOUT if not done in time;
  * otherwise the ticket is retired and res (if not NULL) filled. */

@@ -74,9 +74,12 @@ class ServeCfg(ctypes.Structure):
                 ("mock_species", ctypes.c_int)]
 
 
+MEM_DEVICE, MEM_HOST = 0, 1
+
+
 class Request(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("route", ctypes.c_int), ("n", ctypes.c_int64),
-                ("inp", PropsIn), ("out", PropsOut), ("status", _P)]
+                ("inp", PropsIn), ("out", PropsOut), ("status", _P), ("memory", ctypes.c_int)]
 
 
 class Result(ctypes.Structure):
@@ -306,18 +309,21 @@ class Network:
         check(lib().props_dnn_get_log_outputs(self.handle, ctypes.byref(m)))
         return m.value
 
-    def __call__(self, inputs, outputs, n, fallback=None, status=None, stream=None):
-        """props_dnn: inputs P, T, Y [8, n]; outputs rho, h, cp, c, mu, lambda (float64 device
-        tensors); status uint8 [n]."""
+    def _dnn_args(self, inputs, outputs, n, status):
         import torch
-        n = int(n)
         ns = NIN - 2
         pin = PropsIn(**{k: _arg(inputs.get(k), ns * n if k == "Y" else n, torch.float64, k) for k in IN_FIELDS})
         pout = PropsOut(**{k: _arg(outputs.get(k), n, torch.uint8 if k == "iters" else torch.float64, k)
                            for k in OUT_FIELDS + ("iters",)})
+        return pin, pout, _arg(status, n, torch.uint8, "status")
+
+    def __call__(self, inputs, outputs, n, fallback=None, status=None, stream=None):
+        """props_dnn: inputs P, T, Y [8, n]; outputs rho, h, cp, c, mu, lambda (float64 device
+        tensors); status uint8 [n]."""
+        n = int(n)
+        pin, pout, st = self._dnn_args(inputs, outputs, n, status)
         check(lib().props_dnn(self.handle, fallback.handle if fallback is not None else None,
-                              ctypes.byref(pin), ctypes.byref(pout), n, _arg(status, n, torch.uint8, "status"),
-                              _stream(stream)))
+                              ctypes.byref(pin), ctypes.byref(pout), n, st, _stream(stream)))
 
     def features(self, X, Y, n, stream=None):
         """props_dnn_features: X [10, n] raw features, Y [6, n] outputs (float64 device tensors)."""
@@ -402,14 +408,30 @@ class Server:
         self._keep = {}
 
     def submit(self, mode, route, n, inputs, outputs, status=None):
-        """Non-blocking; host arrays must stay alive until wait() returns."""
+        """Non-blocking.  Arrays are either all device tensors (a device-resident request,
+        evaluated in place; the inputs must be ready, e.g. after a synchronize) or all numpy
+        host arrays (staged through the server's slots); they must stay alive until wait()
+        returns."""
+        import torch
         n = int(n)
-        req = Request(mode=int(mode), route=int(route), n=n,
-                      inp=PropsIn(**{k: _host_ptr(inputs.get(k), self.ns * n if k == "Y" else n, 8, k)
-                                     for k in IN_FIELDS}),
-                      out=PropsOut(**{k: _host_ptr(outputs.get(k), n, 1 if k == "iters" else 8, k)
-                                      for k in OUT_FIELDS + ("iters",)}),
-                      status=_host_ptr(status, n, 1, "status"))
+        arrays = [a for a in list(inputs.values()) + list(outputs.values()) + [status] if a is not None]
+        on_dev = [isinstance(a, torch.Tensor) and a.is_cuda for a in arrays]
+        if any(on_dev) and not all(on_dev):
+            raise ValueError("serve request: mix of device tensors and host arrays")
+        size = lambda k: self.ns * n if k in ("Y", "hRT") else n  # noqa: E731
+        if arrays and all(on_dev):
+            f8, u8 = torch.float64, torch.uint8
+            req = Request(mode=int(mode), route=int(route), n=n, memory=MEM_DEVICE,
+                          inp=PropsIn(**{k: _arg(inputs.get(k), size(k), f8, k) for k in IN_FIELDS}),
+                          out=PropsOut(**{k: _arg(outputs.get(k), size(k), u8 if k == "iters" else f8, k)
+                                          for k in OUT_FIELDS + ("iters",) + EXTRA_OUT_FIELDS}),
+                          status=_arg(status, n, u8, "status"))
+        else:
+            req = Request(mode=int(mode), route=int(route), n=n, memory=MEM_HOST,
+                          inp=PropsIn(**{k: _host_ptr(inputs.get(k), size(k), 8, k) for k in IN_FIELDS}),
+                          out=PropsOut(**{k: _host_ptr(outputs.get(k), size(k), 1 if k == "iters" else 8, k)
+                                          for k in OUT_FIELDS + ("iters",) + EXTRA_OUT_FIELDS}),
+                          status=_host_ptr(status, n, 1, "status"))
         t = ctypes.c_uint64()
         check(lib().serve_submit(self.handle, ctypes.byref(req), ctypes.byref(t)))
         self._keep[t.value] = (inputs, outputs, status)

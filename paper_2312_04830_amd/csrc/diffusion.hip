@@ -142,8 +142,9 @@ int launch_ns(const props_mech_s *m, const DiffArgs &a, hipStream_t s)
     const auto *tt = reinterpret_cast<const ThermoTab<NS> *>(base);
     const auto *tdd = reinterpret_cast<const DiffTab<double, NS> *>(base + m->off_diffd);
     const auto *tdf = reinterpret_cast<const DiffTab<float, NS> *>(base + m->off_difff);
+    // a dispatch holds at most 2^32 - 1 work-items: n <= 2^32 - 256 (a multiple of the block)
+    if (a.n > 0x100000000LL - 256) return fail(PROPS_ETOOBIG, "props_diffusion: n = %lld too large", (long long)a.n);
     const int64_t blocks = (a.n + kDiffBlock - 1) / kDiffBlock;
-    if (blocks > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_diffusion: n = %lld too large", (long long)a.n);
     hipLaunchKernelGGL((diffusion_kernel<NS, PREC>), dim3((unsigned)blocks), dim3(kDiffBlock), 0, s, tt, tdd, tdf, a);
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;

@@ -161,6 +161,7 @@ struct FwdArgs {
     uint64_t pa, pc;
     int64_t row0;        // first permuted row of this batch
     int64_t n;           // cells (rows) this launch covers
+    int64_t ldy;         // inference: element stride between the species rows of Y (>= n)
     const bf16_t *Wf;    // fused-layout weights of all layers
     const float *bias;   // FP32 master vector (biases read from their offsets)
     const double *in_lo, *in_inv;   // [10] input box
@@ -265,7 +266,7 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
                     raw[0] = a.P[cell];
                     raw[1] = a.T[cell];
 #pragma unroll
-                    for (int f = 0; f < NIN - 2; f++) raw[2 + f] = a.Y[(int64_t)f * a.n + cell];
+                    for (int f = 0; f < NIN - 2; f++) raw[2 + f] = a.Y[(int64_t)f * a.ldy + cell];
                 }
                 if (h == 0) {
 #pragma unroll
@@ -280,8 +281,12 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
                     double sy = 0.0;
 #pragma unroll
                     for (int f = 0; f < NIN; f++) {
-                        const double sc = (raw[f] - a.in_lo[f]) * a.in_inv[f];
-                        out |= !(sc >= -1e-9 && sc <= 1.0 + 1e-9);
+                        // a feature constant in the training data (in_inv = 0) scales to 0
+                        // for the network, but the box still holds only that one value
+                        const double d = raw[f] - a.in_lo[f];
+                        const double sc = d * a.in_inv[f];
+                        out |= (a.in_inv[f] != 0.0) ? !(sc >= -1e-9 && sc <= 1.0 + 1e-9)
+                                                    : !(fabs(d) <= 1e-9 * fmax(1.0, fabs(a.in_lo[f])));
                     }
 #pragma unroll
                     for (int f = 2; f < NIN; f++) {
@@ -1072,7 +1077,10 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
 
 static void epoch_perm(uint64_t seed, int epoch, int64_t n, uint64_t &pa, uint64_t &pc)
 {
-    uint64_t st = seed * 0x9E3779B97F4A7C15ull + (uint64_t)epoch * 0xD1B54A32D192ED03ull + 1;
+    // the stream starts from the hashed seed (so that neighbouring seeds do not give shifted
+    // copies of one stream) xor-ed with an odd multiple of the epoch
+    uint64_t st = seed;
+    st = splitmix64(st) ^ ((uint64_t)epoch * 0xD1B54A32D192ED03ull);
     // a: an odd multiplier coprime to n; c: any offset
     for (;;) {
         pa = (splitmix64(st) % (uint64_t)n) | 1ull;
@@ -1113,7 +1121,7 @@ __global__ __launch_bounds__(256) void hpz_features_kernel(HpzArgs a)
 }
 
 int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_out *out, int64_t n,
-             uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s)
+             int64_t ldy, uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s)
 {
     if (!in->P || !in->T || !in->Y) return fail(PROPS_EINVAL, "props_dnn: needs P, T and Y");
     if (d->logmask != kPTYLogMask)
@@ -1124,7 +1132,7 @@ int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_o
     if (fb && (!fb_idx || !fb_count)) return fail(PROPS_EINVAL, "props_dnn: fallback needs index scratch");
     int rc;
     FwdArgs a{};
-    a.P = in->P, a.T = in->T, a.Y = in->Y, a.n = n;
+    a.P = in->P, a.T = in->T, a.Y = in->Y, a.n = n, a.ldy = ldy;
     a.Wf = d->fused, a.bias = d->master;
     a.in_lo = d->scal, a.in_inv = d->scal + NIN;
     a.out_lo = d->scal + 2 * NIN, a.out_rng = d->scal + 2 * NIN + NOUT;
@@ -1141,7 +1149,7 @@ int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_o
         po.rho = out->rho, po.h = out->h, po.cp = out->cp, po.c = out->c, po.mu = out->mu, po.lambda = out->lambda;
         props_in pi{};
         pi.P = in->P, pi.T = in->T, pi.Y = in->Y;
-        rc = launch_pr_indirect(fb, PROPS_PTY, PROPS_MIXED, &pi, &po, n, fb_idx, fb_count, status,
+        rc = launch_pr_indirect(fb, PROPS_PTY, PROPS_MIXED, &pi, &po, n, ldy, fb_idx, fb_count, status,
                                 PROPS_ST_OUT_OF_HULL | PROPS_ST_FALLBACK, s);
         if (rc) return rc;
     }
@@ -1286,7 +1294,7 @@ int props_dnn(props_dnn_t d, props_mech_t fb, const props_in *in, const props_ou
         if ((rc = dalloc(&d->fb_idx, (size_t)n))) return rc;
         d->fb_cap = n;
     }
-    return dnn_eval(d, fb, in, out, n, status, d->fb_idx, d->fb_count, s);
+    return dnn_eval(d, fb, in, out, n, n, status, d->fb_idx, d->fb_count, s);
 }
 
 int props_dnn_features(props_dnn_t d, const double *X, double *Y, int64_t n, void *hip_stream)
@@ -1332,8 +1340,9 @@ int props_features_hpz(const int *atoms, const double *W, int ns, int fuel, int 
     a.inv_range = 1.0 / (beta_fuel - beta_ox);
     a.lambda = bc_lambda;
     a.h = h, a.P = P, a.Y = Y, a.X = X, a.n = n;
+    // a dispatch holds at most 2^32 - 1 work-items: n <= 2^32 - 256
+    if (n > 0x100000000LL - 256) return fail(PROPS_ETOOBIG, "props_features_hpz: n too large");
     const int64_t blocks = (n + 255) / 256;
-    if (blocks > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_features_hpz: n too large");
     hipLaunchKernelGGL(hpz_features_kernel, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)hip_stream, a);
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;

@@ -69,7 +69,8 @@ struct PRArgs {
     uint8_t *status, *iters;
     const int *idx;    // optional cell list: lane k evaluates cell idx[k] for k < *count
     const int *count;
-    int64_t n;         // cells in the arrays (stride of Y)
+    int64_t n;         // cells in the arrays
+    int64_t ldy;       // element stride between species rows of Y and hRT (>= n)
     int ns, maxit;
     double rtol;
     uint8_t st_or;     // bits OR-ed into every status byte written
@@ -508,9 +509,10 @@ constexpr int kOutTransport = 1, kOutSolver = 2;
 // inversions; the double-precision (rho, e, Y) kernel measured 1.6 % faster with 256.
 template <int MODE, int PREC>
 constexpr int kPRBlock = (PREC == PROPS_FP64 && MODE != PROPS_PTY) ? 256 : 64;
-// Largest cell count of a launch, the same for every mode: 2^31 - 1 blocks of the smallest
-// block size.
-constexpr int64_t kPRMaxCells = 0x7fffffffLL * 64;
+// Largest cell count of a launch, the same for every mode: a dispatch holds at most
+// 2^32 - 1 work-items (its grid size is a 32-bit count of work-items), and 2^32 - 256 is
+// the largest multiple of both block sizes below that.
+constexpr int64_t kPRMaxCells = 0x100000000LL - 256;
 template <int NS, int MODE, int PREC, int OUTS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PROPS_HPY ? PR_HPY_WAVES : PR_WAVES_PER_EU))) void pr_kernel(const ThermoTab<NS> *__restrict__ tt,
                                                  const MixTab<double, NS> *__restrict__ tmd,
@@ -537,10 +539,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
     if (a.idx) {
         if (k >= *a.count) return;
         k = a.idx[k];
+        if (k < 0 || k >= a.n) return;   // a list entry outside the arrays is never evaluated
     } else if (k >= a.n) {
         return;
     }
-    const int64_t n = a.n;
+    const int64_t n = a.ldy;   // species-row stride of Y and hRT
     // mixing build over the pairs i < j (see MixQuad::build) in single precision and in the
     // (P, T, Y) kernels (measured: (P, T, Y) with transport 3 % faster; the double-precision
     // (rho, e, Y) and (h, P, Y) kernels 12 % and 1.5 % slower, so they keep the full mat-vecs)
@@ -913,7 +916,7 @@ static int dispatch_ns(const props_mech_s *m, int mode, int prec, int outs, cons
 }
 
 static int launch_pr_args(const props_mech_s *m, int mode, int prec, const props_in *in,
-                          const props_out *out, int64_t n, uint8_t *status, const int *idx,
+                          const props_out *out, int64_t n, int64_t ldy, uint8_t *status, const int *idx,
                           const int *count, uint8_t st_or, hipStream_t stream)
 {
     PRArgs a{};
@@ -930,6 +933,7 @@ static int launch_pr_args(const props_mech_s *m, int mode, int prec, const props
     a.status = status;
     a.iters = (mode != PROPS_PTY) ? out->iters : nullptr;
     a.n = n;
+    a.ldy = ldy;
     a.ns = m->ns;
     a.maxit = m->maxit;
     a.rtol = m->rtol;
@@ -946,14 +950,20 @@ static int launch_pr_args(const props_mech_s *m, int mode, int prec, const props
 int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
               const props_out *out, int64_t n, uint8_t *status, hipStream_t stream)
 {
-    return launch_pr_args(m, mode, prec, in, out, n, status, nullptr, nullptr, 0, stream);
+    return launch_pr_args(m, mode, prec, in, out, n, n, status, nullptr, nullptr, 0, stream);
+}
+
+int launch_pr_strided(const props_mech_s *m, int mode, int prec, const props_in *in,
+                      const props_out *out, int64_t n, int64_t ldy, uint8_t *status, hipStream_t stream)
+{
+    return launch_pr_args(m, mode, prec, in, out, n, ldy, status, nullptr, nullptr, 0, stream);
 }
 
 int launch_pr_indirect(const props_mech_s *m, int mode, int prec, const props_in *in,
-                       const props_out *out, int64_t n, const int *idx, const int *count,
+                       const props_out *out, int64_t n, int64_t ldy, const int *idx, const int *count,
                        uint8_t *status, uint8_t st_or, hipStream_t stream)
 {
-    return launch_pr_args(m, mode, prec, in, out, n, status, idx, count, st_or, stream);
+    return launch_pr_args(m, mode, prec, in, out, n, ldy, status, idx, count, st_or, stream);
 }
 
 }  // namespace props

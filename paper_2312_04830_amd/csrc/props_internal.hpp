@@ -115,16 +115,22 @@ namespace props {
 // Launch the PR property kernel for a mechanism (defined in pr_kernel.hip).
 int launch_pr(const props_mech_s *m, int mode, int prec, const props_in *in,
               const props_out *out, int64_t n, uint8_t *status, hipStream_t stream);
+// The same with the species rows of Y (and of the hRT output) ldy >= n elements apart, so
+// that a range of cells of a larger array can be evaluated in place.
+int launch_pr_strided(const props_mech_s *m, int mode, int prec, const props_in *in,
+                      const props_out *out, int64_t n, int64_t ldy, uint8_t *status, hipStream_t stream);
 // The same over a device list of cells: lane k < *count evaluates cell idx[k] of arrays of
-// length n, OR-ing st_or into its status byte (grid sized for n).
+// length n (species rows ldy apart), OR-ing st_or into its status byte (grid sized for n);
+// entries outside [0, n) are skipped.
 int launch_pr_indirect(const props_mech_s *m, int mode, int prec, const props_in *in,
-                       const props_out *out, int64_t n, const int *idx, const int *count,
+                       const props_out *out, int64_t n, int64_t ldy, const int *idx, const int *count,
                        uint8_t *status, uint8_t st_or, hipStream_t stream);
-// The surrogate with caller-provided fallback scratch (idx: n ints, count: 1 int), so
-// that concurrent evaluations on different streams never share scratch (mlp.hip).
 // Mixture-averaged diffusion coefficients (diffusion.hip).
 int launch_diffusion(const props_mech_s *m, int prec, const double *P, const double *T,
                      const double *Y, double *D, int64_t n, uint8_t *status, hipStream_t stream);
+// The surrogate with caller-provided fallback scratch (idx: n ints, count: 1 int), so
+// that concurrent evaluations on different streams never share scratch (mlp.hip); the
+// species rows of in->Y are ldy >= n elements apart.
 int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_out *out, int64_t n,
-             uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s);
+             int64_t ldy, uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s);
 }  // namespace props

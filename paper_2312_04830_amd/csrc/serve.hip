@@ -106,11 +106,46 @@ void mode_inputs(const props_request &q, const double **a, const double **b)
     else *a = q.in.h, *b = q.in.P;
 }
 
+// Device-resident request: the chunk's kernels read and write the caller's arrays in place
+// (cells [off, off + m) of arrays of n cells, species rows n apart); the slot only lends its
+// fallback-list scratch.
+int dispatch_device(props_server_s *S, Chunk *ch, const Request &R, hipStream_t st)
+{
+    const Slot &sl = S->slots[ch->slot];
+    const props_request &q = R.r;
+    const int64_t m = ch->m, off = ch->off, n = q.n;
+    auto at = [off](const double *p) { return p ? p + off : nullptr; };
+    auto atw = [off](double *p) { return p ? p + off : nullptr; };
+    props_in in{};
+    in.P = at(q.in.P), in.T = at(q.in.T), in.rho = at(q.in.rho), in.e = at(q.in.e), in.h = at(q.in.h);
+    in.Y = q.in.Y + off;
+    in.T_guess = q.mode != PROPS_PTY ? at(q.in.T_guess) : nullptr;
+    props_out out{};
+    out.T = atw(q.out.T), out.P = atw(q.out.P), out.Z = atw(q.out.Z), out.rho = atw(q.out.rho);
+    out.h = atw(q.out.h), out.e = atw(q.out.e), out.cp = atw(q.out.cp), out.c = atw(q.out.c);
+    out.mu = atw(q.out.mu), out.lambda = atw(q.out.lambda);
+    out.psi = atw(q.out.psi), out.alpha = atw(q.out.alpha);
+    out.hRT = q.out.hRT ? q.out.hRT + off : nullptr;
+    out.iters = q.out.iters ? q.out.iters + off : nullptr;
+    uint8_t *status = q.status ? q.status + off : nullptr;
+    int rc;
+    if (q.route == PROPS_ROUTE_DNN)
+        rc = dnn_eval(S->dnn, S->mech, &in, &out, m, n, status, sl.fb_idx, sl.fb_count, st);
+    else
+        rc = launch_pr_strided(S->mech, q.mode, q.route == PROPS_ROUTE_PR_FP64 ? PROPS_FP64 : PROPS_MIXED, &in, &out,
+                               m, n, status, st);
+    if (rc) return rc;
+    PROPS_HIP_TRY(hipEventRecord(S->events[ch->slot], st));
+    return PROPS_OK;
+}
+
 int dispatch_gpu(props_server_s *S, Chunk *ch, const Request &R)
 {
     const Slot &sl = S->slots[ch->slot];
     hipStream_t st = S->streams[ch->slot % S->streams.size()];
     const props_request &q = R.r;
+    if (q.memory == PROPS_MEM_DEVICE) return dispatch_device(S, ch, R, st);
+    // host-staged request: copy the chunk in, evaluate in the slot, copy it out
     const int64_t m = ch->m, off = ch->off, n = q.n;
     const size_t b = (size_t)m * sizeof(double);
     const bool pty = q.mode == PROPS_PTY;
@@ -134,7 +169,7 @@ int dispatch_gpu(props_server_s *S, Chunk *ch, const Request &R)
         if (out_ptr(q.out, f)) *dst[f] = sl.out[f];
     int rc;
     if (q.route == PROPS_ROUTE_DNN)
-        rc = dnn_eval(S->dnn, S->mech, &in, &out, m, sl.status, sl.fb_idx, sl.fb_count, st);
+        rc = dnn_eval(S->dnn, S->mech, &in, &out, m, m, sl.status, sl.fb_idx, sl.fb_count, st);
     else
         rc = launch_pr(S->mech, q.mode, q.route == PROPS_ROUTE_PR_FP64 ? PROPS_FP64 : PROPS_MIXED, &in, &out, m,
                        sl.status, st);
@@ -383,8 +418,20 @@ int serve_submit(props_server_t S, const props_request *req, uint64_t *ticket)
         return fail(PROPS_EINVAL, "serve_submit: unknown mode %d", q.mode);
     if (q.route < PROPS_ROUTE_PR_FP64 || q.route > PROPS_ROUTE_DNN)
         return fail(PROPS_EINVAL, "serve_submit: unknown route %d", q.route);
+    if (q.memory != PROPS_MEM_DEVICE && q.memory != PROPS_MEM_HOST)
+        return fail(PROPS_EINVAL, "serve_submit: unknown memory kind %d", q.memory);
+    if (S->cfg.executor == PROPS_EXEC_MOCK && q.memory != PROPS_MEM_HOST)
+        return fail(PROPS_EINVAL, "serve_submit: the mock executor evaluates host arrays only");
     if (q.route == PROPS_ROUTE_DNN && (!S->dnn || q.mode != PROPS_PTY))
         return fail(PROPS_EINVAL, "serve_submit: the DNN route needs a network and (P, T, Y) inputs");
+    // the surrogate predicts rho, h, cp, c, mu and lambda only: any other requested output
+    // would come back unwritten
+    if (q.route == PROPS_ROUTE_DNN &&
+        (q.out.T || q.out.P || q.out.Z || q.out.e || q.out.psi || q.out.alpha || q.out.hRT || q.out.iters))
+        return fail(PROPS_EINVAL, "serve_submit: the DNN route returns only rho, h, cp, c, mu and lambda");
+    // host-staged requests carry the ten scalar outputs and the status only
+    if (q.memory == PROPS_MEM_HOST && (q.out.psi || q.out.alpha || q.out.hRT || q.out.iters))
+        return fail(PROPS_EINVAL, "serve_submit: psi, alpha, hRT and iters need device-resident requests");
     const double *a, *b;
     mode_inputs(q, &a, &b);
     if (!q.in.Y || !a || !b) return fail(PROPS_EINVAL, "serve_submit: missing input arrays");

@@ -18,13 +18,18 @@ int launch_pr(const props_mech_s *, int, int, const props_in *, const props_out 
 {
     return PROPS_EINVAL;
 }
-int launch_pr_indirect(const props_mech_s *, int, int, const props_in *, const props_out *, int64_t,
+int launch_pr_strided(const props_mech_s *, int, int, const props_in *, const props_out *, int64_t, int64_t,
+                      uint8_t *, hipStream_t)
+{
+    return PROPS_EINVAL;
+}
+int launch_pr_indirect(const props_mech_s *, int, int, const props_in *, const props_out *, int64_t, int64_t,
                        const int *, const int *, uint8_t *, uint8_t, hipStream_t)
 {
     return PROPS_EINVAL;
 }
-int dnn_eval(props_dnn_s *, props_mech_s *, const props_in *, const props_out *, int64_t, uint8_t *, int *,
-             int *, hipStream_t)
+int dnn_eval(props_dnn_s *, props_mech_s *, const props_in *, const props_out *, int64_t, int64_t, uint8_t *,
+             int *, int *, hipStream_t)
 {
     return PROPS_EINVAL;
 }
@@ -73,6 +78,7 @@ props_request as_request(Req &r)
                       &q.out.mu, &q.out.lambda};
     for (int f = 0; f < 10; f++) *o[f] = r.out[f].data();
     q.status = r.st.data();
+    q.memory = PROPS_MEM_HOST;
     return q;
 }
 

@@ -10,8 +10,9 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 ETOOBIG = -4
-HUGE_GRID = 0x7FFFFFFF * 256 + 1      # one more cell than 2^31 - 1 blocks of 256 lanes
-HUGE_GRID_PR = 0x7FFFFFFF * 64 + 1    # the same for the blocks of 64 lanes of props_pr and props_diffusion
+# one more cell than the largest launch: a dispatch holds at most 2^32 - 1 work-items, and
+# 2^32 - 256 is the largest multiple of the 64- and 256-lane blocks below that
+HUGE_GRID_PR = (1 << 32) - 256 + 1
 HUGE_INT = 0x7FFFFFFF + 1             # beyond a 32-bit cell index
 
 

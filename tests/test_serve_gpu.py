@@ -156,3 +156,126 @@ def test_server_hpy_equals_direct_calls(env):
         assert np.array_equal(st, sd.cpu().numpy())
         assert np.all(st == 0)
     s.close()
+
+
+# ------------------------------------------------------------------ device-resident requests
+
+def to_dev(d):
+    import torch
+    return {k: torch.from_numpy(np.ascontiguousarray(v)).to("cuda:0") for k, v in d.items()}
+
+
+def dev_outputs(n, keys, ns=8):
+    import torch
+    return {k: torch.full((ns, n) if k == "hRT" else (n,), float("nan"), dtype=torch.float64, device="cuda:0")
+            for k in keys}
+
+
+def test_device_requests_equal_direct_calls(env):
+    """Requests on device arrays are evaluated in place, chunk by chunk (the species rows of Y
+    and hRT keep the request's stride): bit for bit the direct call, for every route and for
+    the solver outputs of (h, P, Y)."""
+    import torch
+    P, mech, net = env
+    s = P.Server(mech, net, mem_budget=64 << 20, chunk_cells=1000, streams=3)
+    n = 4321                                    # five chunks, the last one ragged
+    ins = to_dev(req(n, 21, res=20))
+    torch.cuda.synchronize()
+    for route, prec in ((P.ROUTE_PR_FP64, P.FP64), (P.ROUTE_PR_MIXED, P.MIXED)):
+        o, sd = dev_outputs(n, KEYS10), torch.full((n,), 255, dtype=torch.uint8, device="cuda:0")
+        s.wait(s.submit(P.PTY, route, n, ins, o, sd))
+        od, sd2 = dev_outputs(n, KEYS10), torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        P.pr(mech, P.PTY, prec, ins, od, n, status=sd2)
+        torch.cuda.synchronize()
+        for k in KEYS10:
+            assert torch.equal(o[k].view(torch.int64), od[k].view(torch.int64)), (route, k)
+        assert torch.equal(sd, sd2)
+    # (h, P, Y) with psi, alpha, hRT and iters
+    h = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    P.pr(mech, P.PTY, P.FP64, ins, {"h": h}, n)
+    hin = {"h": h, "P": ins["P"], "Y": ins["Y"], "T_guess": ins["T"] * 1.004}
+    keys = KEYS10 + ("psi", "alpha", "hRT")
+    torch.cuda.synchronize()
+    o = dev_outputs(n, keys)
+    o["iters"] = torch.zeros(n, dtype=torch.uint8, device="cuda:0")
+    s.wait(s.submit(P.HPY, P.ROUTE_PR_FP64, n, hin, o))
+    od = dev_outputs(n, keys)
+    od["iters"] = torch.zeros(n, dtype=torch.uint8, device="cuda:0")
+    P.pr(mech, P.HPY, P.FP64, hin, od, n)
+    torch.cuda.synchronize()
+    for k in keys + ("iters",):
+        assert torch.equal(o[k], od[k]) if k == "iters" else torch.equal(o[k].view(torch.int64), od[k].view(torch.int64)), k
+    # the surrogate with its fallback (cells outside the box planted)
+    Tb = ins["T"].clone()
+    Tb[::7] = 3400.0
+    din = {"P": ins["P"], "T": Tb, "Y": ins["Y"]}
+    torch.cuda.synchronize()
+    o, sd = dev_outputs(n, KEYS6), torch.full((n,), 255, dtype=torch.uint8, device="cuda:0")
+    s.wait(s.submit(P.PTY, P.ROUTE_DNN, n, din, o, sd))
+    od, sd2 = dev_outputs(n, KEYS6), torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    net(din, od, n, fallback=mech, status=sd2)
+    torch.cuda.synchronize()
+    assert int(((sd2 & 128) != 0).sum()) >= n // 7
+    for k in KEYS6:
+        assert torch.equal(o[k].view(torch.int64), od[k].view(torch.int64)), k
+    assert torch.equal(sd, sd2)
+    s.close()
+
+
+def test_device_alone_equals_in_the_mix(env):
+    import torch
+    P, mech, net = env
+    s = P.Server(mech, net, mem_budget=64 << 20, chunk_cells=2048, streams=4)
+    base = to_dev(req(5000, 7, res=20))
+    torch.cuda.synchronize()
+    cases = [(P.ROUTE_PR_MIXED, KEYS10), (P.ROUTE_DNN, KEYS6), (P.ROUTE_PR_FP64, KEYS10)]
+
+    def submit(route, keys, ins):
+        n = ins["Y"].shape[1]
+        o, st = dev_outputs(n, keys), torch.zeros(n, dtype=torch.uint8, device="cuda:0")
+        return s.submit(P.PTY, route, n, ins, o, st), (o, st)
+
+    alone = []
+    for route, keys in cases:
+        t, r = submit(route, keys, base)
+        s.wait(t)
+        alone.append(r)
+    rng = np.random.default_rng(9)
+    pending, again = [], []
+    for j in range(30):
+        n = int(rng.integers(1, 5000))
+        ins = to_dev(req(n, 200 + j, res=18))
+        torch.cuda.synchronize()
+        pending.append(submit([P.ROUTE_PR_MIXED, P.ROUTE_DNN, P.ROUTE_PR_FP64][j % 3], KEYS6, ins)[0])
+        if j in (4, 17):
+            for route, keys in cases:
+                t, r = submit(route, keys, base)
+                pending.append(t)
+                again.append(r)
+    for t in pending:
+        s.wait(t)
+    assert len(again) == 6
+    for j, (o2, st2) in enumerate(again):
+        o1, st1 = alone[j % 3]
+        for k in o1:
+            assert torch.equal(o1[k].view(torch.int64), o2[k].view(torch.int64)), (j, k)
+        assert torch.equal(st1, st2)
+    assert s.stats()["failed"] == 0
+    s.close()
+
+
+def test_dnn_route_refuses_outputs_it_does_not_produce(env):
+    """The surrogate predicts rho, h, cp, c, mu and lambda only: a request for T, P, Z or e on
+    that route is refused (host and device requests), instead of returning stale memory."""
+    P, mech, net = env
+    s = P.Server(mech, net, mem_budget=64 << 20, chunk_cells=1024, streams=2)
+    ins = req(500, 31, res=12)
+    for extra in ("T", "P", "Z", "e"):
+        with pytest.raises(P.PropsError, match="EINVAL"):
+            s.submit(P.PTY, P.ROUTE_DNN, 500, ins, outputs(500, KEYS6 + (extra,)))
+        with pytest.raises(P.PropsError, match="EINVAL"):
+            s.submit(P.PTY, P.ROUTE_DNN, 500, to_dev(ins), dev_outputs(500, KEYS6 + (extra,)))
+    with pytest.raises(P.PropsError, match="EINVAL"):       # solver outputs need device requests
+        s.submit(P.HPY, P.ROUTE_PR_FP64, 500, ins, outputs(500, ("psi",)))
+    assert s.stats()["submitted"] == 0
+    s.close()
