@@ -224,6 +224,20 @@ int props_dnn_load(const char *path, props_dnn_t *out);
 int props_dnn(props_dnn_t net, props_mech_t fallback, const props_in *in, const props_out *out,
               int64_t n, uint8_t *status, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): props_dnn with the same arguments,
+ * outputs and status, whose fallback list (a count and up to n cell indices) lives in a
+ * static device array of the library instead of a buffer of the handle.  It calls no
+ * hipMalloc, hipFree or allocating library routine.  n <= PROPS_DNN_NOALLOC_MAX_CELLS
+ * (larger: PROPS_ETOOBIG, nothing launched).  The array takes 16 MiB + 256 B on each
+ * device the library runs on, held until the process ends; every call on a device shares
+ * it and it keeps the last call's contents (the call resets the count on hip_stream before
+ * use), so calls that overlap on one device, from any stream or thread, race.  Call with
+ * the device of the network and mechanism current; otherwise PROPS_EINVAL. */
+#define PROPS_DNN_NOALLOC_MAX_CELLS 4194304
+int props_dnn_noalloc(props_dnn_t net, props_mech_t fallback, const props_in *in, const props_out *out,
+                      int64_t n, uint8_t *status, void *hip_stream);
+
 /* Evaluate the surrogate on raw features: X is a device array [PROPS_DNN_IN][n] (feature-
  * major, double), Y a device array [PROPS_DNN_OUT][n] that receives the six outputs in the
  * network's target units (outputs trained on their logarithm, see

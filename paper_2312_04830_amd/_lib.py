@@ -63,6 +63,7 @@ class TrainReport(ctypes.Structure):
 
 DNN_LAYERS = ((256, 10), (256, 256), (256, 256), (256, 256), (6, 256))
 NIN, NOUT = 10, 6     # PROPS_DNN_IN, PROPS_DNN_OUT
+DNN_NOALLOC_MAX_CELLS = 4194304   # PROPS_DNN_NOALLOC_MAX_CELLS
 
 ROUTE_PR_FP64, ROUTE_PR_MIXED, ROUTE_DNN = 0, 1, 2
 EXEC_GPU, EXEC_MOCK = 0, 1
@@ -126,6 +127,8 @@ def lib():
         L.props_dnn_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(_P)]
         L.props_dnn.argtypes = [_P, _P, ctypes.POINTER(PropsIn), ctypes.POINTER(PropsOut),
                                 ctypes.c_int64, _P, _P]
+        L.props_dnn_noalloc.argtypes = [_P, _P, ctypes.POINTER(PropsIn), ctypes.POINTER(PropsOut),
+                                        ctypes.c_int64, _P, _P]
         L.props_dnn_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_float), _P]
         L.props_dnn_features.argtypes = [_P, _P, _P, ctypes.c_int64, _P]
         L.props_features_hpz.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -324,6 +327,15 @@ class Network:
         pin, pout, st = self._dnn_args(inputs, outputs, n, status)
         check(lib().props_dnn(self.handle, fallback.handle if fallback is not None else None,
                               ctypes.byref(pin), ctypes.byref(pout), n, st, _stream(stream)))
+
+    def noalloc(self, inputs, outputs, n, fallback=None, status=None, stream=None):
+        """props_dnn_noalloc: props_dnn with its fallback list in the library's static device
+        array (allocates nothing; n <= DNN_NOALLOC_MAX_CELLS; calls on one device must not
+        overlap)."""
+        n = int(n)
+        pin, pout, st = self._dnn_args(inputs, outputs, n, status)
+        check(lib().props_dnn_noalloc(self.handle, fallback.handle if fallback is not None else None,
+                                      ctypes.byref(pin), ctypes.byref(pout), n, st, _stream(stream)))
 
     def features(self, X, Y, n, stream=None):
         """props_dnn_features: X [10, n] raw features, Y [6, n] outputs (float64 device tensors)."""

@@ -1120,6 +1120,8 @@ __global__ __launch_bounds__(256) void hpz_features_kernel(HpzArgs a)
     for (int f = 3; f < NIN; f++) a.X[(int64_t)f * a.n + k] = 0.0;
 }
 
+int dnn_device(const props_dnn_s *d) { return d->device; }
+
 int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_out *out, int64_t n,
              int64_t ldy, uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s)
 {

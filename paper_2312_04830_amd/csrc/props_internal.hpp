@@ -133,4 +133,6 @@ int launch_diffusion(const props_mech_s *m, int prec, const double *P, const dou
 // species rows of in->Y are ldy >= n elements apart.
 int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_out *out, int64_t n,
              int64_t ldy, uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s);
+// Device a network handle was created on (mlp.hip).
+int dnn_device(const props_dnn_s *d);
 }  // namespace props
