@@ -157,8 +157,10 @@ def forward_bf16(params, xs):
 def backward_bf16(params, cache, y, t, n_total=None, magnitudes=False):
     """Gradients with the back-propagated signal rounded to bf16 where a BF16 GEMM
     consumes it; products exact, sums in float64.  With magnitudes=True also returns, per
-    gradient element, the sum of the magnitudes of its terms (|dz|^T |h| and sum |dz|):
-    the scale against which the rounding of a finite-precision sum is measured."""
+    layer, for each gradient element the sum of the magnitudes of its terms (|dz|^T |h| and
+    sum |dz|), the scale against which the rounding of a finite-precision sum is measured,
+    and the sum of the squares of its terms ((dz^2)^T h^2 and sum dz^2), the scale of a sum
+    of independent one-term perturbations: (S_W, S_b, Q_W, Q_b)."""
     n = y.shape[0] if n_total is None else n_total
     dz = bf16(np.sign(y - t) / (n * y.shape[1]))
     grads = [None] * len(params)
@@ -168,7 +170,8 @@ def backward_bf16(params, cache, y, t, n_total=None, magnitudes=False):
         W, _ = params[l]
         grads[l] = (dz.T @ h_prev, dz.sum(0))
         if magnitudes:
-            mags[l] = (np.abs(dz).T @ np.abs(h_prev), np.abs(dz).sum(0))
+            adz, ah = np.abs(dz), np.abs(h_prev)
+            mags[l] = (adz.T @ ah, adz.sum(0), (adz * adz).T @ (ah * ah), (adz * adz).sum(0))
         if l > 0:
             dh = dz @ bf16(W)
             z_prev = cache[2 * l - 1]

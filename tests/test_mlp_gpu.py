@@ -21,8 +21,8 @@ def props():
     return P
 
 
-# Mixed-precision bar of the PR fallback against the FP64 oracle.
-MIXED_BAR = 1e-4
+# Mixed-precision bar of the PR fallback against the FP64 oracle (measured: 2.1e-6 at most).
+MIXED_BAR = 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -70,13 +70,24 @@ def scaled_outputs(o, olo, ohi):
 # differ only where an FP32 accumulation order flips a bf16 rounding (measured: max 3.5e-5,
 # RMS 1.1e-6); the bars are about 10x that.
 FWD_MAX, FWD_RMS = 5e-4, 1e-5
-# Gradients, element by element: each gradient element is a sum of K = n terms accumulated in
-# FP32 on the matrix cores (and split over the batch); against the exact sum its rounding is
-# bounded by about K' u S with S the sum of the terms' magnitudes, u = 2^-24 and K' the depth
-# of the summation (<= 2^7 here: 16-term matrix-core steps, 32-row K steps, 128 splits,
-# summed in order); a bf16 flip of one term (2^-8 relative) adds 2^-8 S / n.  2^-16 S
-# covers both with room.
+# Gradients, element by element.  Each gradient element is a sum of n terms dz[r, j] h[r, i]
+# accumulated in FP32 on the matrix cores (and split over the batch); against the exact sum
+# its rounding is bounded by about K' u S, S the sum of the terms' magnitudes, u = 2^-24 and
+# K' the depth of the summation (<= 2^7 here: 16-term matrix-core steps, 32-row K steps,
+# 128 splits summed in order): 2^-16 S covers it with room.  Besides, both factors of a term
+# are bf16 values rounded from FP32 results (the back-propagated dz from FP32 sums, the
+# activation h from the FP32 pre-activation) that the oracle computes exactly, so either can
+# land on the other side of a bf16 rounding boundary: a flip of one bf16 step, at most 2^-7
+# relative, so a term moves by at most 2^-6 of itself.  Near the output flips are rare, but
+# a flip moves its whole row of the next dz by about 2^-12 relative, so further down they
+# multiply; bounding the flip probability by 1, with independent signs, the flips of a sum
+# have a standard deviation of at most 2^-6 sqrt(Q), Q = sum_r (dz[r, j] h[r, i])^2; the
+# bar takes six of them.
 GRAD_REL_S = 2.0 ** -16
+
+
+def grad_bar(S, Q):
+    return GRAD_REL_S * S + 6.0 * 2.0 ** -6 * np.sqrt(Q)
 
 
 def test_forward_matches_bf16_oracle_several_tiles_with_fallback(props, orc, sp8):
@@ -151,20 +162,29 @@ def test_gradient_matches_bf16_oracle_elementwise(props, orc, sp8, mask, n):
     y, cache = omlp.forward_bf16(params, xs)
     grads, mags = omlp.backward_bf16(params, cache, y, t, magnitudes=True)
     assert loss == pytest.approx(omlp.l1_loss(y, t), rel=1e-5)
-    off = 0
-    for l, ((dW, db), (sW, sb)) in enumerate(zip(grads, mags)):
+    off, worst = 0, []
+    for l, ((dW, db), (sW, sb, tW, tb)) in enumerate(zip(grads, mags)):
         o, i = dW.shape
         gw = g[off:off + o * i].reshape(o, i)
         off += o * i
         gb = g[off:off + o]
         off += o
-        rw = np.abs(gw - dW) / (GRAD_REL_S * sW + 1e-30)
-        rb = np.abs(gb - db) / (GRAD_REL_S * sb + 1e-30)
+        rw = np.abs(gw - dW) / (grad_bar(sW, tW) + 1e-30)
+        rb = np.abs(gb - db) / (grad_bar(sb, tb) + 1e-30)
+        print(f"    elements within 2^-16 S alone: W {float((np.abs(gw - dW) <= GRAD_REL_S * sW).mean()):.4f}, "
+              f"b {float((np.abs(gb - db) <= GRAD_REL_S * sb).mean()):.4f}")
         print(f"[mlp grad mask {mask:#x} n={n}] layer {l}: max |dW - dW_bf16| {np.abs(gw - dW).max():.2e} "
               f"(worst / bar {rw.max():.3f}), max |db - db_bf16| {np.abs(gb - db).max():.2e} (worst / bar {rb.max():.3f})",
               flush=True)
-        assert rw.max() <= 1.0 and rb.max() <= 1.0, (l, rw.max(), rb.max())
+        for idx in np.argsort(rw.ravel())[-4:]:
+            r, c = np.unravel_index(idx, rw.shape)
+            print(f"    W[{r},{c}]: gpu {gw[r, c]:.6e} oracle {dW[r, c]:.6e} S {sW[r, c]:.3e} ratio {rw[r, c]:.2f}")
+        j = int(np.argmax(rb))
+        print(f"    b[{j}]: gpu {gb[j]:.6e} oracle {db[j]:.6e} S {sb[j]:.3e}; rows with ratio > 1: "
+              f"{int((rw > 1).any(1).sum())}, columns: {int((rw > 1).any(0).sum())}", flush=True)
+        worst.append((l, float(rw.max()), float(rb.max())))
     assert off == g.size
+    assert all(a <= 1.0 and b <= 1.0 for _, a, b in worst), worst
 
 
 def _adam_interval(w0, g, delta, lr, eps=1e-8):
@@ -195,11 +215,12 @@ def test_first_training_step_matches_oracle_adam(props, orc, sp8):
     y, cache = omlp.forward_bf16(params, xs)
     grads, mags = omlp.backward_bf16(params, cache, y, t, magnitudes=True)
     rate = omlp.cosine_lr(lr, lr_min, 0, 4)
+    mags = [(grad_bar(sW, tW), grad_bar(sb, tb)) for sW, sb, tW, tb in mags]
     assert losses[0] == pytest.approx(omlp.l1_loss(y, t), rel=1e-5)
     for l, ((W, b), (gW, gb), (sW, sb)) in enumerate(zip(params, grads, mags)):
         Wg, bg = net.get_layer(l)
         for name, w0, gr, sm, wg in (("W", W, gW, sW, Wg), ("b", b, gb, sb, bg)):
-            lo, hi = _adam_interval(w0, gr, GRAD_REL_S * sm, rate)
+            lo, hi = _adam_interval(w0, gr, sm, rate)
             # FP32 rounding of the new master weight, and of the update itself (beta1, beta2
             # and the bias corrections are single-precision constants on the device)
             slack = 2.0 * np.spacing(np.maximum(np.abs(w0), np.abs(wg)).astype(np.float32)).astype(np.float64) \
