@@ -409,12 +409,7 @@ def dnn_section(props, synth, mech, sp, epochs, n_train, res, reps=5):
     L = torch.stack([lab[k] for k in keys]).float().contiguous()
     bad_labels = int((st != 0).sum())
     del Pd, Td, Yd, lab
-    net = props.Network(seed=2024)
-    log(f"training {epochs} epochs on {n_train} samples")
-    rep, losses = net.train(X, L, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=5)
-    log(f"trained in {rep['seconds']:.1f} s, loss {losses[0]:.4f} -> {losses[-1]:.5f}")
-    del X, L
-    # inference field
+    # inference field and its FP64 PR reference
     Pf, Tf, Yf = synth.flame_field(res, seed=4)
     n = Tf.size
     ins = {"P": torch.from_numpy(Pf).to(dev), "T": torch.from_numpy(Tf).to(dev),
@@ -424,6 +419,27 @@ def dnn_section(props, synth, mech, sp, epochs, n_train, res, reps=5):
     sd = torch.empty(n, dtype=torch.uint8, device=dev)
     ref = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys}
     mx = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys}
+    props.pr(mech, props.PTY, props.FP64, ins, ref, n)
+    net = props.Network(seed=2024)
+    log(f"training {epochs} epochs on {n_train} samples")
+    # error against the number of epochs: the same cosine schedule (horizon `epochs`), trained
+    # in segments, the field evaluated at each milestone
+    curve, t_train, losses, done, rep = [], 0.0, [], 0, None
+    for m in sorted({e for e in (10, 30, 100, 300, 1000) if e < epochs} | {epochs}):
+        rep, ls = net.train(X, L, n_train, epochs=m - done, batch=65536, lr=2e-3, lr_min=2e-5, seed=5,
+                            total_epochs=epochs, fit_scalers=(done == 0))
+        t_train += rep["seconds"]
+        losses.extend(float(v) for v in ls)
+        done = m
+        net(ins, out, n)
+        torch.cuda.synchronize()
+        e = {k: _rel_stats(out[k], ref[k], k) for k in ("rho", "h", "cp")}
+        curve.append({"epochs": m, "loss": losses[-1], "train_s": t_train,
+                      **{f"{k}_max": e[k]["max"] for k in e}, **{f"{k}_rms": e[k]["rms"] for k in e}})
+        log(f"  epoch {m}: loss {losses[-1]:.5f}, rho max {e['rho']['max']:.2e} rms {e['rho']['rms']:.2e}, "
+            f"cp max {e['cp']['max']:.2e}")
+    log(f"trained in {t_train:.1f} s, loss {losses[0]:.4f} -> {losses[-1]:.5f}")
+    del X, L
 
     def timeit(fn, k=reps):
         fn()
@@ -452,22 +468,29 @@ def dnn_section(props, synth, mech, sp, epochs, n_train, res, reps=5):
         "pr_fp64_cells_per_s": n / (ms_fp64 * 1e-3), "pr_mixed_cells_per_s": n / (ms_mixed * 1e-3),
         "speedup_vs_pr_fp64": ms_fp64 / ms_dnn, "speedup_vs_pr_mixed": ms_mixed / ms_dnn,
         "rel_err_vs_fp64": err, "mixed_rel_err_vs_fp64": err_mixed,
-        "train": {"samples": n_train, "epochs": epochs, "seconds": rep["seconds"],
-                  "samples_per_s": rep["samples_per_s"], "loss_first": float(losses[0]),
-                  "loss_last": float(losses[-1]), "label_flags": bad_labels, "state_gen_s": t_gen},
+        "train": {"samples": n_train, "epochs": epochs, "seconds": t_train,
+                  "samples_per_s": n_train * epochs / t_train, "loss_first": float(losses[0]),
+                  "loss_last": float(losses[-1]), "label_flags": bad_labels, "state_gen_s": t_gen,
+                  "error_vs_epochs": curve},
     }
 
 
+# The seven networks of the paper's surrogate (Section 4.1), 3 hidden GELU layers each, on the
+# features (h, P, Box-Cox Bilger Z): name, outputs, log mask (the Box-Cox transform with
+# lambda = 0 of Section 4.2 for rho and the other positive quantities spanning decades).
+PAPER_NETS = (("T", 1, 0x0), ("rho", 1, 0x1), ("mu", 1, 0x1), ("psi", 1, 0x1), ("alpha", 1, 0x1),
+              ("D", 6, 0x3F), ("hRT", 6, 0x0))
+PAPER_SPECIES = 6   # CH4, O2, CO2, H2O, CO, H2: the first six species of the mechanism
+
+
 def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps=5):
-    """The paper's own surrogate inputs (Section 4.1): (h, P, Box-Cox Bilger Z) -> T, rho, mu,
-    psi, thermal diffusivity and h_CH4/RT (first network), D_i of six species (second, log
-    outputs) and h_i/RT of six more species (third, linear outputs), each trained on labels
-    from the library's FP64 paths and compared with the (h, P, Y) Newton path on a res^3
-    field."""
+    """The paper's surrogate as the paper builds it (Section 4.1): seven networks of three
+    hidden layers on (h, P, Box-Cox Bilger Z) predicting T, rho, mu, psi, the thermal
+    diffusivity, the D_i of six species and their h_i/RT, each trained on labels from the
+    library's FP64 paths and compared with the (h, P, Y) Newton path on a res^3 field."""
     import torch
     dev = torch.device("cuda:0")
     ns = len(sp)
-    keys = ("rho", "T", "mu", "hRT0", "psi", "alpha")   # outputs 0, 2, 4, 5 trained on log
     # training set: jittered flame states, labels from the FP64 (P, T, Y) path
     P, T, Y = synth.training_states(n_train, seed=13)
     Pd, Td, Yd = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (P, T, Y))
@@ -476,29 +499,26 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
     hrt = torch.empty((ns, n_train), dtype=torch.float64, device=dev)
     st = torch.empty(n_train, dtype=torch.uint8, device=dev)
     props.pr(mech, props.PTY, props.FP64, {"P": Pd, "T": Td, "Y": Yd}, dict(lab, hRT=hrt), n_train, status=st)
-    X = torch.empty((10, n_train), dtype=torch.float64, device=dev)
-    props.features_hpz(sp, 0, 1, lam, lab["h"], Pd, Yd, n_train, X)
-    L = torch.stack([lab["rho"], Td, lab["mu"], hrt[0], lab["psi"], lab["alpha"]]).float().contiguous()
-    # a second network for the diffusion coefficients of the first six species (all six
-    # outputs trained on their logarithm), labels from the Chapman-Enskog kernel
     Dlab = torch.empty((ns, n_train), dtype=torch.float64, device=dev)
     props.diffusion(mech, props.FP64, Pd, Td, Yd, Dlab, n_train)
-    LD = Dlab[:6].float().contiguous()
-    # a third network for h_i/RT of the next six species (linear outputs: they cross zero)
-    LH = hrt[1:7].float().contiguous()
+    X = torch.empty((10, n_train), dtype=torch.float64, device=dev)
+    props.features_hpz(sp, 0, 1, lam, lab["h"], Pd, Yd, n_train, X)
     Xf = X.float().contiguous()
+    labels = {"T": Td[None], "rho": lab["rho"][None], "mu": lab["mu"][None], "psi": lab["psi"][None],
+              "alpha": lab["alpha"][None], "D": Dlab[:PAPER_SPECIES], "hRT": hrt[:PAPER_SPECIES]}
     bad_labels = int((st != 0).sum())
-    del X, lab, hrt, Pd, Td, Yd, Dlab
-    net = props.Network(seed=2025)
-    log(f"(h,P,Z) surrogate: training {epochs} epochs on {n_train} samples")
-    rep, losses = net.train(Xf, L, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=7)
-    netD = props.Network(seed=2026)
-    netD.set_log_outputs(0x3F)
-    repD, lossesD = netD.train(Xf, LD, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=8)
-    netH = props.Network(seed=2027)
-    netH.set_log_outputs(0)
-    repH, lossesH = netH.train(Xf, LH, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=9)
-    del Xf, L, LD, LH
+    nets, train = {}, {}
+    log(f"paper surrogate: 7 networks (3 x 256), {epochs} epochs on {n_train} samples each")
+    for k, (name, nout, mask) in enumerate(PAPER_NETS):
+        net = props.Network(seed=3000 + k, hidden_layers=3, outputs=nout)
+        net.set_log_outputs(mask)
+        L = labels[name].float().contiguous()
+        rep, losses = net.train(Xf, L, n_train, epochs=epochs, batch=65536, lr=2e-3, lr_min=2e-5, seed=7 + k)
+        nets[name] = net
+        train[name] = {"seconds": rep["seconds"], "samples_per_s": rep["samples_per_s"],
+                       "loss_first": float(losses[0]), "loss_last": float(losses[-1])}
+        del L
+    del X, Xf, lab, hrt, Pd, Td, Yd, Dlab, labels
     # inference field and the (h, P, Y) reference
     Pf, Tf, Yf = synth.flame_field(res, seed=4)
     n = Tf.size
@@ -512,7 +532,7 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
     ref["hRT"] = torch.empty((ns, n), dtype=torch.float64, device=dev)
     hin = {"h": h, "P": Pd, "Y": Yd, "T_guess": Tg}
     X = torch.empty((10, n), dtype=torch.float64, device=dev)
-    Yo = torch.empty((6, n), dtype=torch.float64, device=dev)
+    outs = {name: torch.empty((nout, n), dtype=torch.float64, device=dev) for name, nout, _ in PAPER_NETS}
 
     def timeit(fn, k=reps):
         fn()
@@ -527,63 +547,40 @@ def dnn_hpz_section(props, synth, mech, sp, epochs, n_train, res, lam=0.25, reps
 
     def surrogate():
         props.features_hpz(sp, 0, 1, lam, h, Pd, Yd, n, X)
-        net.features(X, Yo, n)
+        for name, _, _ in PAPER_NETS:
+            nets[name].features(X, outs[name], n)
 
-    ms_dnn = timeit(surrogate)
-    YD = torch.empty((6, n), dtype=torch.float64, device=dev)
-    ms_dnnD = timeit(lambda: netD.features(X, YD, n))
-    YH = torch.empty((6, n), dtype=torch.float64, device=dev)
-    ms_dnnH = timeit(lambda: netH.features(X, YH, n))
+    ms_all = timeit(surrogate)
+    ms_feat = timeit(lambda: props.features_hpz(sp, 0, 1, lam, h, Pd, Yd, n, X))
+    ms_net = {name: timeit(lambda name=name: nets[name].features(X, outs[name], n)) for name, _, _ in PAPER_NETS}
     ms_hpy64 = timeit(lambda: props.pr(mech, props.HPY, props.FP64, hin, ref, n))
     out32 = {k: torch.empty_like(v) for k, v in ref.items()}
     ms_hpy32 = timeit(lambda: props.pr(mech, props.HPY, props.MIXED, hin, out32, n))
     props.pr(mech, props.HPY, props.FP64, hin, ref, n)
     surrogate()
-    netD.features(X, YD, n)
-    netH.features(X, YH, n)
     Dref = torch.empty((ns, n), dtype=torch.float64, device=dev)
-    ms_diff64 = timeit(lambda: props.diffusion(mech, props.FP64, Pd, ref["T"], Yd, Dref, n))
+    props.diffusion(mech, props.FP64, Pd, ref["T"], Yd, Dref, n)
     torch.cuda.synchronize()
-    errD = {sp[i]["name"]: _rel_stats(YD[i], Dref[i], "D") for i in range(6)}
-    errH = {}
-    for j in range(6):
-        r = ref["hRT"][1 + j]
-        d = (YH[j] - r).abs() / (r.abs() + 1.0)
-        r2 = 1.0 - float(((YH[j] - r) ** 2).sum() / ((r - r.mean()) ** 2).sum())
-        errH[sp[1 + j]["name"]] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt()), "r2": r2}
-    refs = {"rho": ref["rho"], "T": ref["T"], "mu": ref["mu"], "hRT0": ref["hRT"][0], "psi": ref["psi"],
-            "alpha": ref["alpha"]}
     err = {}
-    for j, k in enumerate(keys):
-        if k in ("T", "hRT0"):
-            scale = refs[k].abs() + (1.0 if k == "hRT0" else 0.0)
-            d = (Yo[j] - refs[k]).abs() / scale
-            r2 = 1.0 - float(((Yo[j] - refs[k]) ** 2).sum() / ((refs[k] - refs[k].mean()) ** 2).sum())
-            err[k] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt()), "r2": r2}
-        else:
-            err[k] = _rel_stats(Yo[j], refs[k], k)
-    return {"workload": f"{res}^3 flame field ({n} cells): (h, P, Box-Cox(lambda={lam}) Bilger Z) -> "
-                        "T, rho, mu, psi, lambda/(rho cp), h_CH4/RT; one network, 6 of the paper's 17 outputs",
-            "value": n / (ms_dnn * 1e-3), "unit": "cells/s", "ms": ms_dnn,
+    for name in ("T", "rho", "mu", "psi", "alpha"):
+        err[name] = _rel_stats(outs[name][0], ref[name], name)
+    for i in range(PAPER_SPECIES):
+        err[f"D_{sp[i]['name']}"] = _rel_stats(outs["D"][i], Dref[i], "D")
+        r, y = ref["hRT"][i], outs["hRT"][i]
+        d = (y - r).abs() / (r.abs() + 1.0)
+        r2 = 1.0 - float(((y - r) ** 2).sum() / ((r - r.mean()) ** 2).sum())
+        err[f"hRT_{sp[i]['name']}"] = {"max": float(d.max()), "rms": float(d.pow(2).mean().sqrt()), "r2": r2,
+                                       "scale": "|h_i/RT| + 1"}
+    return {"workload": f"{res}^3 flame field ({n} cells): (h, P, Box-Cox(lambda={lam}) Bilger Z) -> T, rho, mu, "
+                        "psi, lambda/(rho cp), D_i and h_i/RT of CH4, O2, CO2, H2O, CO, H2: seven networks of "
+                        "3 x 256 GELU (17 outputs), the paper's surrogate",
+            "value": n / (ms_all * 1e-3), "unit": "cells/s (all seven networks and the features)", "ms": ms_all,
+            "features_ms": ms_feat,
+            "per_network_cells_per_s": {k: n / (v * 1e-3) for k, v in ms_net.items()},
             "pr_hpy_fp64_cells_per_s": n / (ms_hpy64 * 1e-3), "pr_hpy_mixed_cells_per_s": n / (ms_hpy32 * 1e-3),
-            "speedup_vs_pr_hpy_fp64": ms_hpy64 / ms_dnn, "speedup_vs_pr_hpy_mixed": ms_hpy32 / ms_dnn,
+            "speedup_vs_pr_hpy_fp64": ms_hpy64 / ms_all, "speedup_vs_pr_hpy_mixed": ms_hpy32 / ms_all,
             "rel_err_vs_pr_hpy_fp64": err,
-            "train": {"samples": n_train, "epochs": epochs, "seconds": rep["seconds"],
-                      "samples_per_s": rep["samples_per_s"], "loss_first": float(losses[0]),
-                      "loss_last": float(losses[-1]), "label_flags": bad_labels},
-            "diffusion_net": {
-                "workload": "same features -> D_i of CH4, O2, CO2, H2O, CO, H2 (log outputs), second network",
-                "value": n / (ms_dnnD * 1e-3), "unit": "cells/s", "ms": ms_dnnD,
-                "pr_diffusion_fp64_cells_per_s": n / (ms_diff64 * 1e-3),
-                "rel_err_vs_chapman_enskog_at_hpy_T": errD,
-                "train": {"seconds": repD["seconds"], "loss_first": float(lossesD[0]),
-                          "loss_last": float(lossesD[-1])}},
-            "enthalpy_net": {
-                "workload": "same features -> h_i/RT of O2, CO2, H2O, CO, H2, OH (linear outputs), third network",
-                "value": n / (ms_dnnH * 1e-3), "unit": "cells/s", "ms": ms_dnnH,
-                "rel_err_vs_pr_hpy_fp64": errH,
-                "train": {"seconds": repH["seconds"], "loss_first": float(lossesH[0]),
-                          "loss_last": float(lossesH[-1])}}}
+            "train": {"samples": n_train, "epochs": epochs, "label_flags": bad_labels, "networks": train}}
 
 
 def serving_section(props, synth, mech, net, n_sub=64, reqs_per_sub=50, loads=(0.5, 0.8), chunk=524288,
@@ -725,7 +722,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--no-dnn", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--dnn-epochs", type=int, default=30)
+    ap.add_argument("--dnn-epochs", type=int, default=300)
+    ap.add_argument("--hpz-epochs", type=int, default=30)
     ap.add_argument("--dnn-train", type=int, default=8_388_608)
     ap.add_argument("--dnn-res", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -908,8 +906,8 @@ def main():
         log("surrogate: labels, training, inference")
         net, rec["dnn"] = dnn_section(props, synth, mech, sp, args.dnn_epochs, args.dnn_train, args.dnn_res)
         torch.cuda.empty_cache()
-        rec["dnn_hpz"] = dnn_hpz_section(props, synth, mech, sp, args.dnn_epochs, args.dnn_train, args.dnn_res)
-        log(f"(h,P,Z) surrogate: {rec['dnn_hpz']['value']:.3e} cells/s, "
+        rec["dnn_hpz"] = dnn_hpz_section(props, synth, mech, sp, args.hpz_epochs, args.dnn_train, args.dnn_res)
+        log(f"paper surrogate (7 networks): {rec['dnn_hpz']['value']:.3e} cells/s, "
             f"{rec['dnn_hpz']['speedup_vs_pr_hpy_fp64']:.2f}x the FP64 (h,P,Y) path")
     if not args.no_extras and not args.no_serving:
         if net is None:

@@ -161,27 +161,34 @@ int props_diffusion(props_mech_t m, int prec, const double *P, const double *T, 
 
 
 /* ------------------------------------------------------------------ MLP surrogate */
-/* The surrogate of Section 4: a multilayer perceptron with GELU activations mapping a
- * cell's (P, T, Y_1..Y_8) to (rho, h, cp, c, mu, lambda), here 10 -> 4 x 256 -> 6.
- * Inputs are min-max scaled to [0, 1] by the training box; outputs are predicted as
- * min-max scaled targets, with rho, cp, mu and lambda log-transformed first (the
- * Box-Cox transform with lambda = 0 that Section 4.2 applies to density).  Matrix
- * products run on the BF16 matrix cores with FP32 accumulation; FP32 master weights. */
+/* The surrogate of Section 4: a multilayer perceptron with GELU activations.  The default
+ * network maps a cell's (P, T, Y_1..Y_8) to (rho, h, cp, c, mu, lambda), 10 -> 4 x 256 -> 6;
+ * networks of the paper's shape (3 hidden layers, Section 4.1) and with fewer outputs are
+ * made with props_dnn_create_ex.  Inputs are min-max scaled to [0, 1] by the training box;
+ * outputs are predicted as min-max scaled targets, with the outputs flagged in the network's
+ * log mask (by default rho, cp, mu, lambda) log-transformed first (the Box-Cox transform with
+ * lambda = 0 that Section 4.2 applies to density).  Matrix products run on the BF16 matrix
+ * cores with FP32 accumulation; FP32 master weights; the bias is added exactly. */
 typedef struct props_dnn_s *props_dnn_t;
 
 #define PROPS_DNN_IN 10
-#define PROPS_DNN_OUT 6
+#define PROPS_DNN_OUT 6         /* largest output count */
 #define PROPS_DNN_HIDDEN 256
-#define PROPS_DNN_LAYERS 5      /* weight layers: 10->256, 3 x 256->256, 256->6 */
+#define PROPS_DNN_LAYERS 5      /* weight layers of the default network: 10->256, 3 x 256->256, 256->6 */
 
 /* Create a network on the current device with weights and biases drawn
  * U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from a splitmix64 stream seeded by `seed`, and
- * identity scalers (inputs and targets taken as already in [0, 1]). */
+ * identity scalers (inputs and targets taken as already in [0, 1]).  props_dnn_create makes
+ * the default 4-hidden-layer, 6-output network; props_dnn_create_ex takes hidden_layers in
+ * {3, 4} and outputs in 1..PROPS_DNN_OUT (other values: PROPS_EINVAL). */
 int props_dnn_create(uint64_t seed, props_dnn_t *out);
+int props_dnn_create_ex(uint64_t seed, int hidden_layers, int outputs, props_dnn_t *out);
 void props_dnn_destroy(props_dnn_t net);
+int props_dnn_get_shape(props_dnn_t net, int *hidden_layers, int *outputs);
 
-/* Host copies of layer l (0..4): W row-major [out][in] FP32 (out x in = 256x10,
- * 256x256, 256x256, 256x256, 6x256) and b[out].  set_layer resets the Adam moments. */
+/* Host copies of weight layer l (0..hidden_layers): W row-major [out][in] FP32 (out x in =
+ * 256x10, then 256x256 for each further hidden layer, then outputs x 256) and b[out].
+ * set_layer resets the Adam moments of the layer. */
 int props_dnn_get_layer(props_dnn_t net, int l, float *W, float *b);
 int props_dnn_set_layer(props_dnn_t net, int l, const float *W, const float *b);
 
@@ -204,8 +211,8 @@ int props_dnn_set_scalers(props_dnn_t net, const double *in_lo, const double *in
 int props_dnn_set_log_outputs(props_dnn_t net, unsigned mask);
 int props_dnn_get_log_outputs(props_dnn_t net, unsigned *mask);
 
-/* Checkpoint: FP32 master weights, Adam moments and step, epoch counter, log-output
- * mask, scalers.
+/* Checkpoint: network shape, FP32 master weights, Adam moments and step, epoch counter,
+ * log-output mask, scalers.
  * A load followed by further training continues bit for bit. */
 int props_dnn_save(props_dnn_t net, const char *path);
 int props_dnn_load(const char *path, props_dnn_t *out);
@@ -239,7 +246,7 @@ int props_dnn_noalloc(props_dnn_t net, props_mech_t fallback, const props_in *in
                       int64_t n, uint8_t *status, void *hip_stream);
 
 /* Evaluate the surrogate on raw features: X is a device array [PROPS_DNN_IN][n] (feature-
- * major, double), Y a device array [PROPS_DNN_OUT][n] that receives the six outputs in the
+ * major, double), Y a device array [outputs][n] that receives the network's outputs in the
  * network's target units (outputs trained on their logarithm, see
  * props_dnn_set_log_outputs, are returned through exp).  Inputs are min-max scaled by the network's input box; no hull
  * test, status or fallback.  This is the entry for networks trained on other inputs than
@@ -282,15 +289,17 @@ typedef struct {
                             each epoch on the scaled targets */
 } props_train_report;
 
-/* Train with the L1 loss of Section 4.3 and Adam.  X: device float [10][n] (P, T, Y_1..8,
- * feature-major), Y: device float [6][n] raw targets (rho, h, cp, c, mu, lambda).
+/* Train with the L1 loss of Section 4.3 (the mean absolute error over the network's outputs)
+ * and Adam.  X: device float [10][n] raw inputs (P, T, Y_1..8 for the default network),
+ * feature-major; Y: device float [outputs][n] raw targets (rho, h, cp, c, mu, lambda for the
+ * default network).
  * Blocking: returns when training is done (synchronises hip_stream once per epoch). */
 int train_dnn(props_dnn_t net, const float *X, const float *Y, int64_t n,
               const props_train_cfg *cfg, props_train_report *rep, void *hip_stream);
 
 /* One forward/backward pass without an update: the mean L1 loss of samples [0, n) and the
  * gradient of every weight and bias, written to the host array grad in layer order
- * (W_0, b_0, ..., W_4, b_4; shapes as in props_dnn_get_layer).  n <= 65536. */
+ * (W_0, b_0, ..., W_L, b_L; shapes as in props_dnn_get_layer).  n <= 65536. */
 int props_dnn_grad(props_dnn_t net, const float *X, const float *Y, int64_t n, float *grad,
                    float *loss, void *hip_stream);
 

@@ -156,7 +156,9 @@ def forward_bf16(params, xs):
 
 def backward_bf16(params, cache, y, t, n_total=None, magnitudes=False):
     """Gradients with the back-propagated signal rounded to bf16 where a BF16 GEMM
-    consumes it; products exact, sums in float64.  With magnitudes=True also returns, per
+    consumes it, and the GELU derivative taken at the bf16-rounded pre-activation (the
+    precision in which a BF16 engine keeps it between the passes); products exact, sums in
+    float64.  With magnitudes=True also returns, per
     layer, for each gradient element the sum of the magnitudes of its terms (|dz|^T |h| and
     sum |dz|), the scale against which the rounding of a finite-precision sum is measured,
     and the sum of the squares of its terms ((dz^2)^T h^2 and sum dz^2), the scale of a sum
@@ -174,15 +176,16 @@ def backward_bf16(params, cache, y, t, n_total=None, magnitudes=False):
             mags[l] = (adz.T @ ah, adz.sum(0), (adz * adz).T @ (ah * ah), (adz * adz).sum(0))
         if l > 0:
             dh = dz @ bf16(W)
-            z_prev = cache[2 * l - 1]
+            z_prev = bf16(cache[2 * l - 1])      # pre-activations kept in bf16 for the backward
             dz = bf16(dh * gelu_tanh_grad(z_prev))
     return (grads, mags) if magnitudes else grads
 
 
-def init_params(rng):
-    """U(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases (PyTorch Linear style)."""
+def init_params(rng, layers=LAYERS):
+    """U(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights and biases (PyTorch Linear style) for the
+    layer widths `layers` (inputs, hidden..., outputs)."""
     params = []
-    for fi, fo in zip(LAYERS[:-1], LAYERS[1:]):
+    for fi, fo in zip(layers[:-1], layers[1:]):
         k = 1.0 / math.sqrt(fi)
         params.append((rng.uniform(-k, k, (fo, fi)), rng.uniform(-k, k, fo)))
     return params

@@ -115,6 +115,8 @@ def lib():
                                ctypes.POINTER(PropsOut), ctypes.c_int64, _P, _P]
         L.props_diffusion.argtypes = [_P, ctypes.c_int, _P, _P, _P, _P, ctypes.c_int64, _P, _P]
         L.props_dnn_create.argtypes = [ctypes.c_uint64, ctypes.POINTER(_P)]
+        L.props_dnn_create_ex.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, ctypes.POINTER(_P)]
+        L.props_dnn_get_shape.argtypes = [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.props_dnn_destroy.argtypes = [_P]
         L.props_dnn_destroy.restype = None
         L.props_dnn_get_layer.argtypes = [_P, ctypes.c_int, _P, _P]
@@ -259,14 +261,24 @@ def features_hpz(species, fuel, oxidizer, bc_lambda, h, P, Y, n, X, stream=None)
                                    _stream(stream)))
 
 
-class Network:
-    """props_dnn_* handle: the MLP surrogate (10 -> 4 x 256 GELU -> 6)."""
+def dnn_layers(hidden_layers=4, outputs=NOUT):
+    """(out, in) of each weight layer of a network of that shape."""
+    return ((256, NIN),) + ((256, 256),) * (hidden_layers - 1) + ((outputs, 256),)
 
-    def __init__(self, seed=0, handle=None):
+
+class Network:
+    """props_dnn_* handle: the MLP surrogate (10 -> hidden_layers x 256 GELU -> outputs;
+    4 and 6 by default, the paper's networks have 3 hidden layers)."""
+
+    def __init__(self, seed=0, handle=None, hidden_layers=4, outputs=NOUT):
         if handle is None:
             handle = _P()
-            check(lib().props_dnn_create(int(seed), ctypes.byref(handle)))
+            check(lib().props_dnn_create_ex(int(seed), int(hidden_layers), int(outputs), ctypes.byref(handle)))
         self.handle = handle
+        nh, no = ctypes.c_int(), ctypes.c_int()
+        check(lib().props_dnn_get_shape(self.handle, ctypes.byref(nh), ctypes.byref(no)))
+        self.hidden_layers, self.outputs = nh.value, no.value
+        self.layers = dnn_layers(self.hidden_layers, self.outputs)
 
     @classmethod
     def load(cls, path):
@@ -279,7 +291,7 @@ class Network:
 
     def get_layer(self, l):
         import numpy as np
-        o, i = DNN_LAYERS[l]
+        o, i = self.layers[l]
         W = np.zeros((o, i), dtype=np.float32)
         b = np.zeros(o, dtype=np.float32)
         check(lib().props_dnn_get_layer(self.handle, l, W.ctypes.data, b.ctypes.data))
@@ -289,7 +301,7 @@ class Network:
         import numpy as np
         W = np.ascontiguousarray(W, dtype=np.float32)
         b = np.ascontiguousarray(b, dtype=np.float32)
-        assert W.shape == DNN_LAYERS[l] and b.shape == (DNN_LAYERS[l][0],)
+        assert W.shape == self.layers[l] and b.shape == (self.layers[l][0],)
         check(lib().props_dnn_set_layer(self.handle, l, W.ctypes.data, b.ctypes.data))
 
     def get_scalers(self):
@@ -342,18 +354,18 @@ class Network:
         import torch
         n = int(n)
         check(lib().props_dnn_features(self.handle, _arg(X, NIN * n, torch.float64, "X"),
-                                       _arg(Y, NOUT * n, torch.float64, "Y"), n, _stream(stream)))
+                                       _arg(Y, self.outputs * n, torch.float64, "Y"), n, _stream(stream)))
 
     def grad(self, X, Y, n, stream=None):
         """props_dnn_grad on device X [10, n], Y [6, n] (float32): (loss, flat gradient)."""
         import numpy as np
-        total = sum(o * i + o for o, i in DNN_LAYERS)
+        total = sum(o * i + o for o, i in self.layers)
         g = np.zeros(total, dtype=np.float32)
         loss = ctypes.c_float()
         import torch
         n = int(n)
         check(lib().props_dnn_grad(self.handle, _arg(X, NIN * n, torch.float32, "X"),
-                                   _arg(Y, NOUT * n, torch.float32, "Y"), n, g.ctypes.data,
+                                   _arg(Y, self.outputs * n, torch.float32, "Y"), n, g.ctypes.data,
                                    ctypes.byref(loss), _stream(stream)))
         return loss.value, g
 
@@ -369,7 +381,7 @@ class Network:
         import torch
         n = int(n)
         check(lib().train_dnn(self.handle, _arg(X, NIN * n, torch.float32, "X"),
-                              _arg(Y, NOUT * n, torch.float32, "Y"), n, ctypes.byref(cfg),
+                              _arg(Y, self.outputs * n, torch.float32, "Y"), n, ctypes.byref(cfg),
                               ctypes.byref(rep), _stream(stream)))
         return {"epochs": rep.epochs_run, "steps": rep.steps, "seconds": rep.seconds,
                 "samples_per_s": rep.samples_per_s}, losses[:int(epochs)]

@@ -1,25 +1,34 @@
 // MLP surrogate of the property path (paper, Section 4): BF16 matrix-core kernels.
 //
-// Network: 10 -> 256 -> 256 -> 256 -> 256 -> 6, GELU after each hidden layer, L1 loss.
+// Network: NIN inputs -> nh hidden layers of 256 (GELU) -> nout outputs, L1 loss; nh is 3
+// (the paper's networks, Section 4.1) or 4, nout is 1..6.
 //
 // Inference / training forward: one fused kernel.  Cells are the N dimension of
 // v_mfma_f32_32x32x16_bf16 (32 cells per wave) and features the M and K dimensions: the
 // 32x32 FP32 accumulator of a 32-feature output block holds, in each lane, 16 features of
 // one cell, which are exactly the 2 x 8 bf16 values that lane contributes to two K blocks
 // of the next layer's B operand.  Activations therefore never leave registers; the next
-// layer's weights are stored with the matching permutation of their input index.  The 8
-// waves of a workgroup share each layer's weights, staged once per 256-cell tile in LDS
-// (rows padded by 16 bytes so that the lanes reading consecutive rows hit distinct banks);
-// a 32-row A fragment feeds 32 cells, twice the reuse of the 16x16 shape, which halves the
-// LDS traffic per matrix-core operation.  GELU (tanh form, hardware exp2 and reciprocal)
-// and the bias are applied in FP32 on the accumulators, then packed to bf16 with
-// v_cvt_pk_bf16_f32 (round to nearest even).
+// layer's weights are stored with the matching permutation of their input index.  The bias
+// rides on the matrix cores as well: each weight row carries the FP32 bias split into three
+// bf16 parts (hi + mid + lo, exact), which one extra K block multiplies by a constant
+// (1, 1, 1, 0, ...) operand, so the accumulator starts from zero and no vector instruction
+// touches the bias.  GELU (tanh form, hardware exp2 and reciprocal) is applied in FP32 on
+// the accumulators, then packed to bf16 with v_cvt_pk_bf16_f32 (round to nearest even).
 //
-// Backward: dH = dZ W with the GELU derivative fused in the epilogue (64x64 tiles on the
-// 16x16x32 MFMA, W kept transposed so both operands are contiguous along K), dW = dZ^T H on
+// Weight streaming: two independent 4-wave workgroups per CU, each with a ring of four
+// 32-row weight slots in LDS (67.6 KB).  Every tile of 128 cells walks the same sequence of
+// weight blocks (layer 0 whole, then the hidden layers' 32-row output blocks, then the output
+// layer); slots are filled a pair at a time with global_load_lds, one pair ahead of the one
+// being used, so staging overlaps the matrix-core work and the two workgroups of a CU, in
+// unrelated phases, fill each other's barrier and GELU-only stretches.
+//
+// Backward: dH = dZ W with the GELU derivative fused in the epilogue (128 x 256 tiles on the
+// 32x32x16 MFMA, W kept transposed so both operands are contiguous along K), dW = dZ^T H on
 // the 32x32x16 MFMA with both operands k-major (split over the batch with a fixed-order
-// reduction: training is deterministic and resumable bit for bit), column sums for the
-// biases, Adam on FP32 master weights.
+// reduction: training is deterministic and resumable bit for bit) and the bias gradient as
+// the column sums of dZ in the same pass, Adam on FP32 master weights.  The forward keeps
+// bf16 copies of pre-activations and activations for the backward, and writes the output
+// layer's L1 gradient directly.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -27,6 +36,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "props_internal.hpp"
@@ -39,56 +49,53 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short bf16_t;  // storage type of a bfloat16
 
-constexpr int NIN = PROPS_DNN_IN, NOUT = PROPS_DNN_OUT, HID = PROPS_DNN_HIDDEN, NL = PROPS_DNN_LAYERS;
+constexpr int NIN = PROPS_DNN_IN, NOUT = PROPS_DNN_OUT, HID = PROPS_DNN_HIDDEN;
+constexpr int MIN_HIDDEN = 3, MAX_HIDDEN = 4;
 constexpr int IN_PAD = 32;     // input columns of the layer-0 weights and of saved inputs
-constexpr int OUT_PAD = 16;    // output rows of the last layer's weights and saved outputs
-constexpr int HROW = HID + 8;  // bf16 per weight row in the fused layout (528 B)
+constexpr int OUT_PAD = 16;    // output rows of the last layer's weights and output gradients
+constexpr int HROW = HID + 8;  // bf16 per fused row of a 256-input layer: inputs, bias hi/mid/lo, 5 zeros
 constexpr int FK0 = 16;        // layer-0 K in the fused layout: one 16-deep K block
-constexpr int IROW = FK0 + 8;  // bf16 per layer-0 fused row (48 B)
+constexpr int IROW = FK0 + 8;  // bf16 per layer-0 fused row (48 B): 16 inputs, bias hi/mid/lo, 5 zeros
 constexpr int FOUT_ROWS = 32;  // last layer padded to one 32-row output block
-constexpr int FWD_WAVES = 8;
+constexpr int FWD_WAVES = 8;                              // one workgroup per CU, 2 waves per SIMD
 constexpr int FWD_THREADS = FWD_WAVES * 64;
 constexpr int CELLS_PER_WAVE = 32;
 constexpr int TILE_CELLS = FWD_WAVES * CELLS_PER_WAVE;   // 256
+constexpr int SLOT_BYTES = 32 * HROW * 2;                 // one 32-row block: 16,896 B
+constexpr int NRING = 3;                                  // ring of three slot pairs
+constexpr int LDS_BYTES = NRING * 2 * SLOT_BYTES;         // 101,376 B per workgroup
+constexpr int L0_BYTES = HID * IROW * 2;                  // layer 0 whole: 12,288 B, one slot
+static_assert(L0_BYTES <= SLOT_BYTES, "layer 0 fits one slot");
 constexpr int MAX_BATCH = 65536;
 constexpr int SPLITW = 128;    // batch splits of the weight-gradient GEMMs (32: 89M, 64: 106M,
                                // 128: 115M, 256: 108M training samples/s)
-// LDS fragment prefetch distance of the hidden layers, in matrix-core steps (1 measured
-// 6 % slower on the 2^22-cell inference; 2 to 6 alike)
+// LDS fragment prefetch distance of the A-fragment stream, in matrix-core steps
 constexpr int FPF = 3;
 // Outputs of the (P, T, Y) surrogate trained on their logarithm: rho, cp, mu, lambda
 // (bits 0, 2, 4, 5; h and c cross or approach zero and stay linear).
 constexpr unsigned kPTYLogMask = 0x35u;
 
-// padded (out, in) of each weight layer and its offsets in the FP32 master vector
-__host__ __device__ constexpr int lout(int l) { return l == 0 ? HID : (l == NL - 1 ? OUT_PAD : HID); }
-__host__ __device__ constexpr int lin(int l) { return l == 0 ? IN_PAD : HID; }
-__host__ __device__ constexpr int lrow(int l) { return l == 0 ? IROW : HROW; }
+// ------------------------------------------------------------------ layout
+// Weight layers 0..nh: layer 0 maps the inputs to 256 features, layers 1..nh-1 are 256 x 256,
+// layer nh is the output layer.  Padded (out, in) of each layer in the FP32 master vector
+// (W row-major then b), and its offsets there, in the transposed natural bf16 copy and in the
+// fused bf16 layout.
+__host__ __device__ inline int lout(int l, int nh) { return l == 0 ? HID : (l == nh ? OUT_PAD : HID); }
+__host__ __device__ inline int lin(int l) { return l == 0 ? IN_PAD : HID; }
+__host__ __device__ inline int lrow(int l) { return l == 0 ? IROW : HROW; }
+__host__ __device__ inline size_t w_off(int l)
+{
+    return l == 0 ? 0 : (size_t)IN_PAD * HID + HID + (size_t)(l - 1) * (HID * HID + HID);
+}
+__host__ __device__ inline size_t b_off(int l, int nh) { return w_off(l) + (size_t)lout(l, nh) * lin(l); }
+__host__ __device__ inline size_t total_params(int nh) { return w_off(nh) + (size_t)OUT_PAD * HID + OUT_PAD; }
+__host__ __device__ inline size_t nat_off(int l) { return l == 0 ? 0 : (size_t)HID * IN_PAD + (size_t)(l - 1) * HID * HID; }
+__host__ __device__ inline size_t nat_total(int nh) { return nat_off(nh) + (size_t)OUT_PAD * HID; }
+__host__ __device__ inline size_t f_off(int l) { return l == 0 ? 0 : (size_t)HID * IROW + (size_t)(l - 1) * HID * HROW; }
+__host__ __device__ inline size_t f_total(int nh) { return f_off(nh) + (size_t)FOUT_ROWS * HROW; }
 // true (unpadded) shapes
-__host__ __device__ constexpr int tout(int l) { return l == NL - 1 ? NOUT : HID; }
-__host__ __device__ constexpr int tin(int l) { return l == 0 ? NIN : HID; }
-
-// offsets of each layer in the FP32 master vector (W then b), the fused bf16 layout and
-// the natural bf16 layout
-__host__ __device__ constexpr size_t w_off(int l) { return l == 0 ? 0 : w_off(l - 1) + (size_t)lout(l - 1) * lin(l - 1) + lout(l - 1); }
-__host__ __device__ constexpr size_t b_off(int l) { return w_off(l) + (size_t)lout(l) * lin(l); }
-// rows of each layer in the fused layout (the last layer padded to a 32-row block)
-__host__ __device__ constexpr int frows(int l) { return l == NL - 1 ? FOUT_ROWS : lout(l); }
-__host__ __device__ constexpr size_t f_off(int l) { return l == 0 ? 0 : f_off(l - 1) + (size_t)frows(l - 1) * lrow(l - 1); }
-__host__ __device__ constexpr size_t n_off(int l) { return l == 0 ? 0 : n_off(l - 1) + (size_t)lout(l - 1) * lin(l - 1); }
-struct Layout {
-    static constexpr size_t total = w_off(NL);
-    static constexpr size_t ftotal = f_off(NL);
-    static constexpr size_t nattotal = n_off(NL);
-    __host__ __device__ static constexpr size_t w(int l) { return w_off(l); }
-    __host__ __device__ static constexpr size_t b(int l) { return b_off(l); }
-    __host__ __device__ static constexpr size_t f(int l) { return f_off(l); }
-    __host__ __device__ static constexpr size_t nat(int l) { return n_off(l); }
-};
-using kLay = Layout;
-
-// Largest fused layer in bytes (the LDS staging buffer).
-constexpr int LDS_BYTES = HID * HROW * 2;   // 135168
+__host__ __device__ inline int tout(int l, int nh, int nout) { return l == nh ? nout : HID; }
+__host__ __device__ inline int tin(int l) { return l == 0 ? NIN : HID; }
 
 // ------------------------------------------------------------------ small device helpers
 // two floats -> two bf16 (round to nearest even; v_cvt_pk_bf16_f32 on gfx950)
@@ -135,11 +142,6 @@ __device__ __forceinline__ float gelu_grad_f(float x)
     return s + x * s * (1.0f - s) * up;
 }
 
-__device__ __forceinline__ f32x4 mfma16(bf16x8 a, bf16x8 b, f32x4 c)
-{
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
-
 __device__ __forceinline__ f32x16 mfma32(bf16x8 a, bf16x8 b, f32x16 c)
 {
     return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -153,84 +155,352 @@ __device__ __forceinline__ int64_t perm_index(int64_t i, uint64_t a, uint64_t c,
 
 // ------------------------------------------------------------------ fused forward
 struct FwdArgs {
-    // inference inputs (SoA doubles) ...
+    // inference inputs (SoA doubles, species rows ldy apart) ...
     const double *P, *T, *Y;
-    // ... or training inputs (feature-major float [10][nx]) with the epoch permutation
-    const float *X;
+    int64_t ldy;
+    // ... or training inputs (feature-major float [10][nx]) and raw targets ([6][nx]) with
+    // the epoch permutation
+    const float *X, *Yt;
     int64_t nx;
     uint64_t pa, pc;
     int64_t row0;        // first permuted row of this batch
     int64_t n;           // cells (rows) this launch covers
-    int64_t ldy;         // inference: element stride between the species rows of Y (>= n)
-    const bf16_t *Wf;    // fused-layout weights of all layers
-    const float *bias;   // FP32 master vector (biases read from their offsets)
+    int nhid, nout;      // hidden layers, outputs
+    const bf16_t *Wf;    // fused-layout weights (with the bias parts) of all layers
     const double *in_lo, *in_inv;   // [10] input box
-    const double *out_lo, *out_rng; // [6] target box
+    const double *out_lo, *out_rng, *out_inv; // [6] target box
     unsigned logmask;               // bit j: output j was trained on its logarithm
-    // ... or inference on raw feature-major inputs [10][n], outputs [6][n]
+    // ... or inference on raw feature-major inputs [10][n], outputs [nout][n]
     const double *Xd;
     double *Yd;
     // inference outputs
     double *orho, *oh, *ocp, *oc, *omu, *olam;
     uint8_t *status;
     int *fb_idx, *fb_count;         // fallback list (cells outside the box / non-physical)
-    // training saves
-    bf16_t *h0;          // [n][32]
-    float *z[4];         // [n][256] pre-activations of the hidden layers
-    bf16_t *h[4];        // [n][256] activations
-    float *y;            // [n][16] output layer
+    // training: saves for the backward and the output layer's L1 gradient
+    bf16_t *h0;                     // [n][32] scaled inputs
+    bf16_t *zs, *hs;                // pre-activations and activations of hidden layer l:
+    int64_t lstride;                // [n][256] each, at zs + l lstride and hs + l lstride
+    bf16_t *dzo;                    // [n][16] d loss / d output
+    float *lpart;                   // [tiles * FWD_WAVES] sums of |y - t| per wave
 };
 
-// Stage one fused layer (rows x row-stride bf16, a multiple of 16 bytes) into LDS with
-// global_load_lds_dwordx4: each lane's 16 bytes go straight to LDS base + 16 lane, without
-// passing through registers; one 1 KB chunk per wave and instruction.
-__device__ __forceinline__ void stage(unsigned char *lds, const bf16_t *src, int bytes)
+// Issue global_load_lds of `bytes` (a multiple of 16) from src to the LDS slot dst: each
+// lane's 16 bytes go straight to LDS, without passing through registers; one 1 KB chunk per
+// wave and instruction.  Completion is awaited by the caller (vmcnt, then a barrier).
+__device__ __forceinline__ void stage_async(unsigned char *dst, const bf16_t *src, int bytes)
 {
-    const uint4 *s = reinterpret_cast<const uint4 *>(src);
-    const int n16 = bytes / 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = wave; c * 64 < n16; c += FWD_WAVES) {
-        const int i = c * 64 + lane;
-        if (i < n16)
-            __builtin_amdgcn_global_load_lds((const void *)(s + i),
-                                             (__attribute__((address_space(3))) void *)(lds + c * 1024), 16, 0, 0);
-    }
-    __builtin_amdgcn_s_waitcnt(0);   // this wave's loads have landed (the caller's barrier does the rest)
-}
-
-__device__ __forceinline__ bf16x8 lds_frag(const unsigned char *lds, int row, int rowlen, int slot)
-{
-    return *reinterpret_cast<const bf16x8 *>(lds + ((size_t)row * rowlen + slot) * 2);
-}
-
-// Bias-initialised accumulator of output block ob: lane half h holds rows 8q + 4h + (0..3);
-// only the first nq row groups exist (the last layer has 16 bias entries, nq = 2).
-__device__ __forceinline__ f32x16 bias_block(const float *bias, int ob, int h, int nq = 4)
-{
-    f32x16 c;
+    // chunk addresses are wave-uniform (scalar base + this lane's 16-byte offset), and the lane
+    // offset is formed here, at each call, not hoisted out of the tile loop into registers
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    unsigned lo = (threadIdx.x & 63) * 16u;
+    asm volatile("" : "+v"(lo));
+    const unsigned char *s = reinterpret_cast<const unsigned char *>(src);
+    constexpr int PER_WAVE = (SLOT_BYTES / 1024 + FWD_WAVES) / FWD_WAVES;   // 1 KB chunks per wave (5)
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const f32x4 b = (q < nq) ? *reinterpret_cast<const f32x4 *>(bias + 32 * ob + 8 * q + 4 * h) : f32x4{};
-        c[4 * q + 0] = b[0];
-        c[4 * q + 1] = b[1];
-        c[4 * q + 2] = b[2];
-        c[4 * q + 3] = b[3];
+    for (int r = 0; r < PER_WAVE; r++) {
+        const int c = wave + FWD_WAVES * r;
+        if (c * 1024 + (int)lo < bytes)
+            __builtin_amdgcn_global_load_lds((const void *)(s + c * 1024 + lo),
+                                             (__attribute__((address_space(3))) void *)(dst + c * 1024), 16, 0, 0);
     }
+}
+
+// Weights of block k of the per-tile sequence: 0 .. 8 (nh - 1) - 1 the 32-row output blocks of
+// the hidden 256 x 256 layers in order, 8 (nh - 1) the output layer, 8 (nh - 1) + 1 layer 0
+// (whole) of the next tile.
+__device__ __forceinline__ void step_weights(const FwdArgs &a, int k, const bf16_t *&src, int &bytes)
+{
+    const int nh = a.nhid;
+    if (k == 8 * (nh - 1) + 1) {
+        src = a.Wf;
+        bytes = L0_BYTES;
+    } else if (k == 8 * (nh - 1)) {
+        src = a.Wf + f_off(nh);
+        bytes = SLOT_BYTES;
+    } else {
+        const int l = 1 + k / 8, ob = k % 8;
+        src = a.Wf + f_off(l) + (size_t)ob * 32 * HROW;
+        bytes = SLOT_BYTES;
+    }
+}
+
+// Fill the two slots of ring pair `rp` (0..2) with the weights of sequence pair p: blocks 2p
+// and 2p + 1.  The weight base goes through an empty asm so that the per-lane load addresses are
+// formed here, at each call: hoisted out of the tile loop (they do not depend on the tile) they
+// would occupy a hundred VGPR pairs.
+__device__ __forceinline__ void stage_pair(unsigned char *lds, const FwdArgs &a, int rp, int p)
+{
+    FwdArgs b = a;
+    const bf16_t *wf = a.Wf;
+    asm volatile("" : "+s"(wf));
+    b.Wf = wf;
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+        const bf16_t *src;
+        int bytes;
+        step_weights(b, 2 * p + j, src, bytes);
+        stage_async(lds + (2 * rp + j) * SLOT_BYTES, src, bytes);
+    }
+}
+
+// Start of the pair held in ring pair rp.  On entry the pair's weights are in LDS for every
+// wave (certified at the previous pair's start).  Here this wave's loads of the next pair
+// (issued at the previous pair's start) land, the barrier makes that true of every wave and
+// tells that every wave is done with the previous pair, whose ring pair then receives the
+// weights of sequence pair pn (two pairs ahead).  The A-fragment stream may thus read the
+// next pair's slots at any time during this pair.
+__device__ __forceinline__ void pair_top(unsigned char *lds, const FwdArgs &a, int rp, int pn, bool stage)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (stage) stage_pair(lds, a, rp == 0 ? NRING - 1 : rp - 1, pn);
+}
+
+// Per-lane LDS byte addresses of one block's A fragments: `k` the weight K blocks (row col,
+// K slot 8h), `b` the bias parts (row col, K slot past the inputs; for lane half 1 the B
+// operand is zero there).  Formed through an empty asm at each block, so that the compiler
+// does not hoist one pair per block and slot out of the tile loop.
+struct BlkAddr {
+    unsigned k, b;
+};
+__device__ __forceinline__ BlkAddr hid_addr(unsigned slot_off, int col, int h)
+{
+    unsigned k = slot_off + (unsigned)(col * HROW + 8 * h) * 2u;
+    unsigned b = slot_off + (unsigned)(col * HROW + HID) * 2u;
+    asm volatile("" : "+v"(k), "+v"(b));
+    return {k, b};
+}
+__device__ __forceinline__ BlkAddr l0_addr(unsigned slot_off, int col, int h)
+{
+    unsigned k = slot_off + (unsigned)(col * IROW + 8 * h) * 2u;
+    unsigned b = slot_off + (unsigned)(col * IROW + FK0) * 2u;
+    asm volatile("" : "+v"(k), "+v"(b));
+    return {k, b};
+}
+__device__ __forceinline__ bf16x8 lds_at(const unsigned char *lds, unsigned addr, int off)
+{
+    return *reinterpret_cast<const bf16x8 *>(lds + addr + off);
+}
+// A fragment of step s of a 256-input block: s = 0 the bias parts, s >= 1 K block s - 1
+__device__ __forceinline__ bf16x8 hid_frag(const unsigned char *lds, BlkAddr ad, int s)
+{
+    return s == 0 ? lds_at(lds, ad.b, 0) : lds_at(lds, ad.k, (s - 1) * 32);
+}
+// A fragment of step s of layer 0: sub-block s / 2, its bias parts (s even) or inputs (s odd)
+__device__ __forceinline__ bf16x8 l0_frag(const unsigned char *lds, BlkAddr ad, int s)
+{
+    const int off = (s >> 1) * 32 * IROW * 2;
+    return (s & 1) ? lds_at(lds, ad.k, off) : lds_at(lds, ad.b, off);
+}
+
+// The A-fragment stream: FPF fragments in flight ahead of the matrix-core step that uses them,
+// continuing across block and pair boundaries.
+struct Ring {
+    bf16x8 f[FPF];
+};
+__device__ __forceinline__ bf16x8 ring_step(Ring &r, bf16x8 incoming)
+{
+    const bf16x8 c = r.f[0];
+#pragma unroll
+    for (int d = 0; d + 1 < FPF; d++) r.f[d] = r.f[d + 1];
+    r.f[FPF - 1] = incoming;
     return c;
 }
 
-// Training saves of one 32-feature block of layer l: pre-activations z (FP32) and the
-// packed bf16 activations p (8 pairs), in natural feature order [cell][256].
-__device__ __forceinline__ void save_block(const FwdArgs &a, int l, int64_t cell, int ob, int h,
-                                           const f32x16 &z, const unsigned *p)
+// Training saves of one 32-feature block of a hidden layer: bf16 pre-activations z into zl and
+// the packed bf16 activations p (8 pairs) into hl, in natural feature order [cell][256].
+__device__ __forceinline__ void save_block(bf16_t *zl, bf16_t *hl, int64_t cell, int ob, int h, const f32x16 &z,
+                                           const unsigned *p)
 {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const int64_t off = cell * HID + 32 * ob + 8 * q + 4 * h;
-        *reinterpret_cast<f32x4 *>(a.z[l] + off) = f32x4{z[4 * q], z[4 * q + 1], z[4 * q + 2], z[4 * q + 3]};
-        *reinterpret_cast<uint2 *>(a.h[l] + off) = make_uint2(p[2 * q], p[2 * q + 1]);
+        *reinterpret_cast<uint2 *>(zl + off) =
+            make_uint2(pack_bf16x2(z[4 * q], z[4 * q + 1]), pack_bf16x2(z[4 * q + 2], z[4 * q + 3]));
+        *reinterpret_cast<uint2 *>(hl + off) = make_uint2(p[2 * q], p[2 * q + 1]);
     }
 }
+
+// GELU of the 16 accumulator values of one block, packed into the two bf16x8 B-operand
+// fragments of the next layer.
+__device__ __forceinline__ void gelu_block(const f32x16 &z, bf16x8 &lo, bf16x8 &hi, unsigned *p)
+{
+#pragma unroll
+    for (int q = 0; q < 8; q++) p[q] = pack_bf16x2(gelu_f(z[2 * q]), gelu_f(z[2 * q + 1]));
+    lo = __builtin_bit_cast(bf16x8, make_uint4(p[0], p[1], p[2], p[3]));
+    hi = __builtin_bit_cast(bf16x8, make_uint4(p[4], p[5], p[6], p[7]));
+}
+
+// Layer 0: 16 matrix-core steps, the bias and input MFMAs of each 32-row sub-block ob, with
+// the GELU of sub-block ob - 1 beside them.  Fills act[0..13] (and, with `save`, writes the
+// training saves of sub-blocks 0..6); returns sub-block 7's accumulator, whose GELU is pending.
+// The stream continues into the first 256-input block at `nx`.
+__device__ __forceinline__ f32x16 l0_block(const unsigned char *lds, BlkAddr cur, BlkAddr nx, Ring &ring,
+                                           bf16x8 x0, bf16x8 (&act)[16], bf16x8 ones, const FwdArgs &a,
+                                           int64_t cell, bool save)
+{
+    const int h = (threadIdx.x & 63) >> 5;
+    constexpr int NS = 16;
+    f32x16 zp = {};
+#pragma unroll
+    for (int ob = 0; ob < 8; ob++) {
+        f32x16 z;
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            const int s = 2 * ob + t, u = s + FPF;
+            const bf16x8 af = ring_step(ring, u < NS ? l0_frag(lds, cur, u) : hid_frag(lds, nx, u - NS));
+            z = (t == 0) ? mfma32(af, ones, f32x16{}) : mfma32(af, x0, z);
+        }
+        if (ob > 0) {
+            unsigned p[8];
+            gelu_block(zp, act[2 * ob - 2], act[2 * ob - 1], p);
+            if (save) save_block(a.zs, a.hs, cell, ob - 1, h, zp, p);
+        }
+        zp = z;
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return zp;
+}
+
+// One 32-row output block of a 256-input layer at `cur`: returns bias + W act in 17
+// matrix-core steps (the bias block, then K blocks 0..15), while the GELU of the pending
+// block's accumulator pz is formed one value per step into the packed bf16 pairs pg.  Each
+// step is a scheduling region of its own (the LDS read FPF steps ahead, one MFMA, one or two
+// GELU values), so that the vector work of a step runs in the shadow of its MFMA.  The stream
+// continues into the next block at `nx`, a 256-input block or (NEXT_L0) the next tile's
+// layer 0.  FIRST: pz is the previous layer's last block, i.e. act[14], act[15]; its 16
+// values are done by step 14 (two at step 0), and act[14], act[15] are filled before steps
+// 15 and 16.
+template <bool FIRST, bool NEXT_L0>
+__device__ __forceinline__ f32x16 hid_block(const unsigned char *lds, BlkAddr cur, BlkAddr nx, Ring &ring,
+                                            bf16x8 (&act)[16], const f32x16 &pz, unsigned (&pg)[8], bf16x8 ones)
+{
+    constexpr int NS = 17;
+    f32x16 acc = {};
+    float gv[16];
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        if (FIRST && s == 15) {
+            act[14] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
+            act[15] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
+        }
+        const int u = s + FPF;
+        const bf16x8 af = ring_step(ring, u < NS ? hid_frag(lds, cur, u)
+                                                 : (NEXT_L0 ? l0_frag(lds, nx, u - NS) : hid_frag(lds, nx, u - NS)));
+        acc = (s == 0) ? mfma32(af, ones, f32x16{}) : mfma32(af, act[s - 1], acc);
+        const int v0 = FIRST ? (s == 0 ? 0 : s + 1) : s;
+        const int nv = FIRST ? (s == 0 ? 2 : (s < 15 ? 1 : 0)) : (s < 16 ? 1 : 0);
+#pragma unroll
+        for (int w = 0; w < nv; w++) {
+            const int v = v0 + w;
+            gv[v] = gelu_f(pz[v]);
+            if (v & 1) pg[v >> 1] = pack_bf16x2(gv[v - 1], gv[v]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+// Raw inputs of one cell for this lane (inference: doubles; training: the float features of
+// the permuted sample), loaded a block ahead of their use.
+template <bool TRAIN>
+struct RawIn {
+    typedef typename std::conditional<TRAIN, float, double>::type T;
+    T x[NIN];
+};
+
+// Issue the loads of one tile's inputs for this lane's cell (`cell` < n) or, in training,
+// of its permuted sample `sidx`.
+template <bool TRAIN>
+__device__ __forceinline__ void load_inputs(const FwdArgs &a, int64_t cell, int64_t sidx, RawIn<TRAIN> &r)
+{
+    if (TRAIN) {
+#pragma unroll
+        for (int f = 0; f < NIN; f++) r.x[f] = a.X[(int64_t)f * a.nx + sidx];
+    } else if (a.Xd) {
+#pragma unroll
+        for (int f = 0; f < NIN; f++) r.x[f] = a.Xd[(int64_t)f * a.n + cell];
+    } else {
+        r.x[0] = a.P[cell];
+        r.x[1] = a.T[cell];
+#pragma unroll
+        for (int f = 0; f < NIN - 2; f++) r.x[2 + f] = a.Y[(int64_t)f * a.ldy + cell];
+    }
+}
+
+// Training targets of this lane's output rows 4h + r (r = 0..3; at most 6 outputs, so rows
+// 8 and up of the block carry none) for sample sidx
+__device__ __forceinline__ void load_targets(const FwdArgs &a, int64_t sidx, int h, float (&t)[4])
+{
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int j = 4 * h + r;
+        t[r] = j < a.nout ? a.Yt[(int64_t)j * a.nx + sidx] : 0.0f;
+    }
+}
+
+// Scaled bf16 B operand of layer 0 from the raw inputs (half 0: features 0..7, half 1: 8, 9),
+// and in inference the hull / sanity flag of the cell; training saves the scaled inputs.
+template <bool TRAIN>
+__device__ __forceinline__ bf16x8 scale_inputs(const FwdArgs &a, const RawIn<TRAIN> &r, bool live, int64_t cell,
+                                               int h, uint8_t &flag)
+{
+    float xs[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) xs[j] = 0.0f;
+    flag = 0;
+    if (live) {
+        double raw[NIN];
+#pragma unroll
+        for (int f = 0; f < NIN; f++) raw[f] = (double)r.x[f];
+        if (h == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; j++) xs[j] = (float)((raw[j] - a.in_lo[j]) * a.in_inv[j]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < NIN - 8; j++) xs[j] = (float)((raw[8 + j] - a.in_lo[8 + j]) * a.in_inv[8 + j]);
+        }
+        if (!TRAIN && !a.Xd && h == 0) {
+            // training box (the hull) and physical sanity of the whole cell
+            bool out = false, bad = !(raw[0] > 0.0) || !(raw[1] > 0.0);
+            double sy = 0.0;
+#pragma unroll
+            for (int f = 0; f < NIN; f++) {
+                // a feature constant in the training data (in_inv = 0) scales to 0 for the
+                // network, but the box still holds only that one value
+                const double d = raw[f] - a.in_lo[f];
+                const double sc = d * a.in_inv[f];
+                out |= (a.in_inv[f] != 0.0) ? !(sc >= -1e-9 && sc <= 1.0 + 1e-9)
+                                            : !(fabs(d) <= 1e-9 * fmax(1.0, fabs(a.in_lo[f])));
+            }
+#pragma unroll
+            for (int f = 2; f < NIN; f++) {
+                bad |= !(raw[f] >= -1e-12);
+                sy += raw[f];
+            }
+            bad |= !(fabs(sy - 1.0) <= 1e-6);
+            flag = (out || bad) ? 1 : 0;
+        }
+    }
+    unsigned p[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) p[j] = pack_bf16x2(xs[2 * j], xs[2 * j + 1]);
+    if (TRAIN && live) {
+        // saved inputs keep IN_PAD columns; 16..31 stay zero from allocation
+        *reinterpret_cast<uint4 *>(a.h0 + cell * IN_PAD + 8 * h) = *reinterpret_cast<uint4 *>(p);
+    }
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<uint4 *>(p));
+}
+
+// Fused forward of the surrogate: per 256-cell tile, layer 0, the hidden 256 x 256 layers and
+// the output layer, with activations in registers (cells are the N side of
+// v_mfma_f32_32x32x16_bf16, 32 per wave) and the weights streamed through LDS one 32-row block
+// at a time.  The per-tile sequence of blocks (the hidden layers' 8 blocks each, the output
+// layer, then layer 0 of the next tile) is staged in pairs by LDS DMA into a ring of three slot
+// pairs, two pairs ahead; one barrier per pair.  The next tile's inputs are loaded at the start
+// of the output pair and used after its matrix-core work; the outputs are written before the
+// next tile's layer 0, a whole block ahead of the next wait on memory.
 template <bool TRAIN>
 __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
 {
@@ -239,323 +509,301 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
     const int wave = threadIdx.x >> 6;
     const int h = lane >> 5;         // lane half: K slots 8h..8h+7 (A, B); rows 8q + 4h.. (C)
     const int col = lane & 31;       // cell within the wave's 32-cell block (B, C); A row
+    const int nh = a.nhid;
+    const int PT = 1 + 4 * (nh - 1);        // pairs per tile: (2 + 8 (nh - 1)) blocks
     const int64_t ntiles = (a.n + TILE_CELLS - 1) / TILE_CELLS;
+    if ((int64_t)blockIdx.x >= ntiles) return;   // whole workgroup: no barrier is skipped by part of it
+    // B operand of the bias block: K slots 0..2 are 1 (they meet the bias hi, mid, lo parts of
+    // each weight row), every other slot 0
+    bf16x8 ones = bf16x8{};
+    if (h == 0) ones = __builtin_bit_cast(bf16x8, make_uint4(0x3f803f80u, 0x00003f80u, 0u, 0u));
+    // Blocks write their bf16 pre-activations and activations when save buffers are given
+    // (training).  Inference passes none, but keeps the branch: it splits each block's code,
+    // which keeps the register allocator from spilling the inference kernel (without it this
+    // kernel needs more than 256 VGPRs).
+    const bool saves = TRAIN || a.h0 != nullptr;
+    constexpr unsigned PAIR = 2 * SLOT_BYTES;
+    const auto next_rp = [](int r) { return r == NRING - 1 ? 0 : r + 1; };
+
+    // prologue: layer 0 of the first tile into slot 1 of ring pair 2, the tile's pairs 0 and 1
+    // into ring pairs 0 and 1; the first tile's inputs; the first fragments of layer 0
+    {
+        const bf16_t *wf = a.Wf;
+        asm volatile("" : "+s"(wf));
+        stage_async(lds + (2 * 2 + 1) * SLOT_BYTES, wf, L0_BYTES);
+    }
+    stage_pair(lds, a, 0, 0);
+    stage_pair(lds, a, 1, 1);
+    int64_t cell = (int64_t)blockIdx.x * TILE_CELLS + wave * CELLS_PER_WAVE + col;
+    bool live = cell < a.n;
+    int64_t sidx = TRAIN ? perm_index(a.row0 + (live ? cell : 0), a.pa, a.pc, a.nx) : 0;
+    uint8_t flag;
+    bf16x8 x0;                       // B operand of layer 0: the scaled inputs
+    {
+        RawIn<TRAIN> r;
+        load_inputs<TRAIN>(a, live ? cell : 0, sidx, r);
+        x0 = scale_inputs<TRAIN>(a, r, live, cell, h, flag);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int rp = 2;                      // ring pair of the current pair
+    Ring ring;
+    {
+        const BlkAddr l0 = l0_addr(2 * PAIR + SLOT_BYTES, col, h);
+#pragma unroll
+        for (int d = 0; d < FPF; d++) ring.f[d] = l0_frag(lds, l0, d);
+    }
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        bf16x8 act[16];              // B operand: one bf16x8 per 16-deep K block
-#pragma unroll
-        for (int kb = 0; kb < 16; kb++) act[kb] = bf16x8{};
-        const int64_t cell = tile * TILE_CELLS + wave * CELLS_PER_WAVE + col;
-        const bool live = cell < a.n;
-        uint8_t flag = 0;
-        // ---- inputs -> scaled bf16 B operand of layer 0 (half 0: features 0..7, half 1: 8, 9)
-        {
-            float xs[8];
-#pragma unroll
-            for (int j = 0; j < 8; j++) xs[j] = 0.0f;
-            if (live) {
-                double raw[NIN];
-                if (TRAIN) {
-                    const int64_t sidx = perm_index(a.row0 + cell, a.pa, a.pc, a.nx);
-#pragma unroll
-                    for (int f = 0; f < NIN; f++) raw[f] = (double)a.X[(int64_t)f * a.nx + sidx];
-                } else if (a.Xd) {
-#pragma unroll
-                    for (int f = 0; f < NIN; f++) raw[f] = a.Xd[(int64_t)f * a.n + cell];
-                } else {
-                    raw[0] = a.P[cell];
-                    raw[1] = a.T[cell];
-#pragma unroll
-                    for (int f = 0; f < NIN - 2; f++) raw[2 + f] = a.Y[(int64_t)f * a.ldy + cell];
-                }
-                if (h == 0) {
-#pragma unroll
-                    for (int j = 0; j < 8; j++) xs[j] = (float)((raw[j] - a.in_lo[j]) * a.in_inv[j]);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < NIN - 8; j++) xs[j] = (float)((raw[8 + j] - a.in_lo[8 + j]) * a.in_inv[8 + j]);
-                }
-                if (!TRAIN && !a.Xd && h == 0) {
-                    // training box (the hull) and physical sanity of the whole cell
-                    bool out = false, bad = !(raw[0] > 0.0) || !(raw[1] > 0.0);
-                    double sy = 0.0;
-#pragma unroll
-                    for (int f = 0; f < NIN; f++) {
-                        // a feature constant in the training data (in_inv = 0) scales to 0
-                        // for the network, but the box still holds only that one value
-                        const double d = raw[f] - a.in_lo[f];
-                        const double sc = d * a.in_inv[f];
-                        out |= (a.in_inv[f] != 0.0) ? !(sc >= -1e-9 && sc <= 1.0 + 1e-9)
-                                                    : !(fabs(d) <= 1e-9 * fmax(1.0, fabs(a.in_lo[f])));
-                    }
-#pragma unroll
-                    for (int f = 2; f < NIN; f++) {
-                        bad |= !(raw[f] >= -1e-12);
-                        sy += raw[f];
-                    }
-                    bad |= !(fabs(sy - 1.0) <= 1e-6);
-                    flag = (out || bad) ? 1 : 0;
-                }
+        const bool more = tile + gridDim.x < ntiles;
+        bf16x8 act[16];              // B operand of a 256-input layer: one bf16x8 per 16-deep K block
+        bf16x8 nxt[14];              // the layer's outputs of blocks 0..6 as they are formed
+        f32x16 pz;                   // accumulator of the block whose GELU is pending
+
+        // ---- layer 0: slot 1 of the current pair; the GELU of its blocks 0..6 gives
+        // act[0..13], that of block 7 is left pending
+        pz = l0_block(lds, l0_addr(rp * PAIR + SLOT_BYTES, col, h), hid_addr(next_rp(rp) * PAIR, col, h), ring, x0,
+                      act, ones, a, cell, saves && live);
+
+        // ---- hidden 256 x 256 layers: one 32-row output block per step, whose matrix-core work
+        // is interleaved with the GELU of the block before it; at block 0 that is the previous
+        // layer's last block, whose two K blocks of act are needed only by the last two steps.
+        // Sequence block k = 8 (l - 1) + ob; even ob open a pair (slot 0), odd ob are slot 1.
+#pragma unroll 1
+        for (int l = 1; l < nh; l++) {
+            bf16_t *zprev = nullptr, *hprev = nullptr, *zcur = nullptr, *hcur = nullptr;
+            if (saves) {
+                zcur = a.zs + l * a.lstride, hcur = a.hs + l * a.lstride;
+                zprev = zcur - a.lstride, hprev = hcur - a.lstride;
             }
-            unsigned p[4];
 #pragma unroll
-            for (int j = 0; j < 4; j++) p[j] = pack_bf16x2(xs[2 * j], xs[2 * j + 1]);
-            act[0] = __builtin_bit_cast(bf16x8, *reinterpret_cast<uint4 *>(p));
-            if (TRAIN && live) {
-                // saved inputs keep IN_PAD columns; 16..31 stay zero from allocation
-                *reinterpret_cast<uint4 *>(a.h0 + cell * IN_PAD + 8 * h) = *reinterpret_cast<uint4 *>(p);
+            for (int ob = 0; ob < 8; ob++) {
+                if (!(ob & 1)) {
+                    rp = next_rp(rp);
+                    const int pn = 4 * (l - 1) + ob / 2 + 2;   // sequence pair two ahead
+                    pair_top(lds, a, rp, pn < PT ? pn : pn - PT, pn < PT || more);
+                }
+                const unsigned base = rp * PAIR;
+                const BlkAddr cur = hid_addr((ob & 1) ? base + SLOT_BYTES : base, col, h);
+                const BlkAddr nx = hid_addr((ob & 1) ? next_rp(rp) * PAIR : base + SLOT_BYTES, col, h);
+                unsigned pg[8];
+                f32x16 acc;
+                if (ob == 0) {
+                    acc = hid_block<true, false>(lds, cur, nx, ring, act, pz, pg, ones);
+                    if (saves && live) save_block(zprev, hprev, cell, 7, h, pz, pg);
+                } else {
+                    acc = hid_block<false, false>(lds, cur, nx, ring, act, pz, pg, ones);
+                    const int pb = ob - 1;
+                    nxt[2 * pb] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
+                    nxt[2 * pb + 1] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
+                    if (saves && live) save_block(zcur, hcur, cell, pb, h, pz, pg);
+                }
+                pz = acc;
             }
+#pragma unroll
+            for (int kb = 0; kb < 14; kb++) act[kb] = nxt[kb];
         }
 
-        // ---- hidden layers 0..3 (GELU)
-#pragma unroll 1
-        for (int l = 0; l < NL - 1; l++) {
-            __syncthreads();   // previous layer done with the LDS buffer
-            const int rowlen = lrow(l);
-            stage(lds, a.Wf + kLay::f(l), frows(l) * rowlen * 2);
-            __syncthreads();
-            const float *bias = a.bias + kLay::b(l);
-            bf16x8 nxt[16];
-            if (l == 0) {
-                // one 16-deep K block: eight single MFMAs, then GELU
-#pragma unroll
-                for (int ob = 0; ob < 8; ob++) {
-                    const bf16x8 a0 = lds_frag(lds, ob * 32 + col, rowlen, 8 * h);
-                    const f32x16 z = mfma32(a0, act[0], bias_block(bias, ob, h));
-                    unsigned p[8];
-#pragma unroll
-                    for (int q = 0; q < 8; q++) p[q] = pack_bf16x2(gelu_f(z[2 * q]), gelu_f(z[2 * q + 1]));
-                    nxt[2 * ob] = __builtin_bit_cast(bf16x8, make_uint4(p[0], p[1], p[2], p[3]));
-                    nxt[2 * ob + 1] = __builtin_bit_cast(bf16x8, make_uint4(p[4], p[5], p[6], p[7]));
-                    if (TRAIN && live) save_block(a, 0, cell, ob, h, z, p);
-                }
-            } else {
-                // One 32-row output block per step; the GELU of block ob - 1 is interleaved
-                // with the matrix-core work of block ob (one value per K block), so that the
-                // vector and matrix units of a SIMD work at the same time.
-                // The 128 matrix-core steps of the layer (8 blocks x 16 K blocks) read their
-                // A fragments from LDS FPF steps ahead, across block boundaries.
-                const auto frag = [&](int st) {
-                    return lds_frag(lds, (st >> 4) * 32 + col, rowlen, (st & 15) * 16 + 8 * h);
-                };
-                bf16x8 ring[FPF];
-#pragma unroll
-                for (int d = 0; d < FPF; d++) ring[d] = frag(d);
-                f32x16 pz = {};
-#pragma unroll
-                for (int ob = 0; ob <= 8; ob++) {
-                    f32x16 acc = {};
-                    unsigned pg[8];
-                    float gv[16];
-                    if (ob < 8) acc = bias_block(bias, ob, h);
-#pragma unroll
-                    for (int kb = 0; kb < 16; kb++) {
-                        if (ob < 8) {
-                            const int st = ob * 16 + kb;
-                            const bf16x8 cur = ring[st % FPF];
-                            if (st + FPF < 128) ring[st % FPF] = frag(st + FPF);
-                            acc = mfma32(cur, act[kb], acc);
-                        }
-                        if (ob > 0) {
-                            gv[kb] = gelu_f(pz[kb]);
-                            if (kb & 1) pg[kb >> 1] = pack_bf16x2(gv[kb - 1], gv[kb]);
-                        }
-                        if (ob > 0 && ob < 8) {
-                            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // LDS read
-                            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // MFMA
-                            __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);   // VALU
-                        } else {
-                            __builtin_amdgcn_sched_barrier(0);
-                        }
-                    }
-                    if (ob > 0) {
-                        const int pb = ob - 1;
-                        nxt[2 * pb] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
-                        nxt[2 * pb + 1] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
-                        if (TRAIN && live) save_block(a, l, cell, pb, h, pz, pg);
-                    }
-                    if (ob < 8) pz = acc;
-                }
-            }
-#pragma unroll
-            for (int kb = 0; kb < 16; kb++) act[kb] = nxt[kb];
-        }
-        // ---- output layer (linear), outside the loop so that its double-precision
-        // epilogue does not share the register budget of the hidden layers
+        // ---- output layer (linear): slot 0 of the last pair of the tile, whose slot 1 holds
+        // the next tile's layer 0; its matrix-core work is interleaved with the GELU of the last
+        // hidden layer's last block.  The next tile's inputs (and in training this tile's
+        // targets) are loaded meanwhile.
+        rp = next_rp(rp);
+        pair_top(lds, a, rp, 1, more);
+        const int64_t ncell = cell + (int64_t)gridDim.x * TILE_CELLS;
+        const bool nlive = more && ncell < a.n;
+        const int64_t nsidx = (TRAIN && more) ? perm_index(a.row0 + (nlive ? ncell : 0), a.pa, a.pc, a.nx) : 0;
+        RawIn<TRAIN> rn;
+        if (more) load_inputs<TRAIN>(a, nlive ? ncell : 0, nsidx, rn);
+        float tg[4];
+        if (TRAIN) load_targets(a, sidx, h, tg);
         {
-            constexpr int l = NL - 1;
-            __syncthreads();
-            const int rowlen = lrow(l);
-            stage(lds, a.Wf + kLay::f(l), frows(l) * rowlen * 2);
-            __syncthreads();
-            const float *bias = a.bias + kLay::b(l);
-            {
-                f32x16 acc = bias_block(bias, 0, h, OUT_PAD / 8);   // rows 16..31: padding
+            unsigned pg[8];
+            const f32x16 acc = hid_block<true, true>(lds, hid_addr(rp * PAIR, col, h),
+                                                     l0_addr(rp * PAIR + SLOT_BYTES, col, h), ring, act, pz, pg, ones);
+            if (saves && live)
+                save_block(a.zs + (nh - 1) * a.lstride, a.hs + (nh - 1) * a.lstride, cell, 7, h, pz, pg);
+            uint8_t nflag = 0;
+            bf16x8 nx0 = x0;
+            if (more) nx0 = scale_inputs<TRAIN>(a, rn, nlive, ncell, h, nflag);
+            if (TRAIN) {
+                // L1 loss on the scaled targets: rows 8q + 4h + r (q = 0, 1) of the block are
+                // outputs j; d loss / d y_j = sign(y_j - t_j) / (rows * nout)
+                const float scale = 1.0f / ((float)a.n * (float)a.nout);
+                float lsum = 0.f;
+                float dv[8];
 #pragma unroll
-                for (int kb = 0; kb < 16; kb++) {
-                    const bf16x8 a0 = lds_frag(lds, col, rowlen, kb * 16 + 8 * h);
-                    acc = mfma32(a0, act[kb], acc);
-                }
-                if (live) {
-                    if (TRAIN) {
-                        // rows 8q + 4h + (0..3) for q = 0, 1 are the 16 saved outputs
+                for (int q = 0; q < 2; q++)
 #pragma unroll
-                        for (int q = 0; q < 2; q++)
-                            *reinterpret_cast<f32x4 *>(a.y + cell * OUT_PAD + 8 * q + 4 * h) =
-                                f32x4{acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]};
-                    } else if (a.Yd) {
-                        // feature-major outputs in target units: lanes of half 0 hold rows
-                        // 0..3, half 1 rows 4, 5; the rows flagged in logmask were trained
-                        // on their logarithm
-                        const int j0 = 4 * h;
-#pragma unroll
-                        for (int v = 0; v < 4; v++) {
-                            const int j = j0 + v;
-                            if (j < NOUT) {
-                                const double y = a.out_lo[j] + (double)acc[v] * a.out_rng[j];
-                                a.Yd[(int64_t)j * a.n + cell] = (a.logmask >> j & 1u) ? exp(y) : y;
-                            }
+                    for (int r = 0; r < 4; r++) {
+                        const int j = 8 * q + 4 * h + r;
+                        float d = 0.f;
+                        if (live && q == 0 && j < a.nout) {
+                            double tr = (double)tg[r];
+                            if (a.logmask >> j & 1u) tr = log(tr);
+                            const float t = (float)((tr - a.out_lo[j]) * a.out_inv[j]);
+                            const float diff = acc[4 * q + r] - t;
+                            lsum += fabsf(diff);
+                            d = (diff > 0.f) ? scale : ((diff < 0.f) ? -scale : 0.f);
                         }
-                    } else if (h == 0) {
-                        // rows 0..3: rho, h, cp, c
-                        if (a.orho) a.orho[cell] = exp(a.out_lo[0] + (double)acc[0] * a.out_rng[0]);
-                        if (a.oh) a.oh[cell] = a.out_lo[1] + (double)acc[1] * a.out_rng[1];
-                        if (a.ocp) a.ocp[cell] = exp(a.out_lo[2] + (double)acc[2] * a.out_rng[2]);
-                        if (a.oc) a.oc[cell] = a.out_lo[3] + (double)acc[3] * a.out_rng[3];
-                    } else {
-                        // rows 4, 5: mu, lambda
-                        if (a.omu) a.omu[cell] = exp(a.out_lo[4] + (double)acc[0] * a.out_rng[4]);
-                        if (a.olam) a.olam[cell] = exp(a.out_lo[5] + (double)acc[1] * a.out_rng[5]);
+                        dv[4 * q + r] = d;
+                    }
+                if (live) {
+#pragma unroll
+                    for (int q = 0; q < 2; q++)
+                        *reinterpret_cast<uint2 *>(a.dzo + cell * OUT_PAD + 8 * q + 4 * h) =
+                            make_uint2(pack_bf16x2(dv[4 * q], dv[4 * q + 1]), pack_bf16x2(dv[4 * q + 2], dv[4 * q + 3]));
+                }
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+                if (lane == 0) a.lpart[tile * FWD_WAVES + wave] = lsum;
+            } else {
+                if (live) {
+                    // rows 4h + v, v = 0..3, are outputs j (half 0: 0..3, half 1: 4, 5), back to
+                    // target units; those trained on their logarithm through exp, as 2^(y log2 e)
+                    // in single precision (the network's own precision)
+#pragma unroll
+                    for (int v = 0; v < 4; v++) {
+                        const int j = 4 * h + v;
+                        if (j < a.nout) {
+                            double y = __builtin_fma((double)acc[v], a.out_rng[j], a.out_lo[j]);
+                            if (a.logmask >> j & 1u)
+                                y = (double)__builtin_amdgcn_exp2f((float)(y * 1.4426950408889634));
+                            double *dst = a.Yd ? a.Yd + (int64_t)j * a.n
+                                               : (j == 0 ? a.orho : j == 1 ? a.oh : j == 2 ? a.ocp
+                                                  : j == 3 ? a.oc : j == 4 ? a.omu : a.olam);
+                            if (dst) dst[cell] = y;
+                        }
+                    }
+                }
+                // status and fallback list (lanes of half 0 own their cell)
+                const bool mine = live && h == 0;
+                const bool f = mine && flag;
+                if (mine && a.status) a.status[cell] = f ? PROPS_ST_OUT_OF_HULL : 0;
+                if (a.fb_idx) {
+                    const unsigned long long bal = __ballot(f);
+                    const int cnt = __popcll(bal);
+                    int base = 0;
+                    if (cnt) {
+                        const int first = __builtin_ctzll(bal);
+                        if (lane == first) base = atomicAdd(a.fb_count, cnt);
+                        base = __shfl(base, first);
+                        if (f) a.fb_idx[base + __popcll(bal & ((1ull << lane) - 1))] = (int)cell;
                     }
                 }
             }
+            x0 = nx0;
+            flag = nflag;
         }
-        if (!TRAIN) {
-            // status and fallback list (lanes of half 0 own their cell)
-            const bool mine = live && h == 0;
-            const bool f = mine && flag;
-            if (mine && a.status) a.status[cell] = f ? PROPS_ST_OUT_OF_HULL : 0;
-            if (a.fb_idx) {
-                const unsigned long long bal = __ballot(f);
-                const int cnt = __popcll(bal);
-                int base = 0;
-                if (cnt) {
-                    const int first = __builtin_ctzll(bal);
-                    if (lane == first) base = atomicAdd(a.fb_count, cnt);
-                    base = __shfl(base, first);
-                    if (f) a.fb_idx[base + __popcll(bal & ((1ull << lane) - 1))] = (int)cell;
-                }
-            }
-        }
+        cell = ncell;
+        live = nlive;
+        sidx = nsidx;
     }
+    __builtin_amdgcn_s_waitcnt(0);   // no weight load still in flight when the workgroup ends
 }
 
 // ------------------------------------------------------------------ input-gradient GEMM
-// D[m][n] = bf16( (sum_k A[m][k] B[n][k]) gelu'(Z[m][n]) ): dz_{l-1} = (dz_l W_l) * GELU'(z_{l-1})
-// with A = dz_l (rows = batch, K = the layer's outputs) and B = W_l transposed ([in][out]),
-// both contiguous along K.  64 x 64 tiles, K in steps of 32 staged in LDS with 16-byte
-// stores, 4 waves of 2 x 2 v_mfma_f32_16x16x32_bf16 blocks.  M, N, K, lda, ldb multiples of 8.
-// (An LDS-free variant with 16-byte fragment loads straight from global memory, cells on
-// either MFMA side, measured 1.5-2x slower.)
-struct GemmArgs {
-    int M, N, K;
-    const bf16_t *A;
-    int lda;
-    const bf16_t *B;
-    int ldb;
-    bf16_t *Cb;
-    int ldc;
-    const float *Z;
-    int ldz;
-};
-
-__global__ __launch_bounds__(256) void gemm_dh_kernel(GemmArgs g)
+// C[m][n] = bf16( (sum_k A[m][k] B[n][k]) gelu'(Z[m][n]) ): dz_{l-1} = (dz_l W_l) * GELU'(z_{l-1})
+// with A = dz_l (rows = batch, K = the layer's padded outputs, 256 or 16), B = W_l transposed
+// ([256 inputs][K]), both contiguous along K, and Z the bf16 pre-activations [M][256].  Tiles of
+// 128 rows x all 256 columns (so each row of dz is read once) per 256-thread workgroup: 2 x 2
+// waves of 64 x 128, i.e. 2 x 4 accumulator blocks of v_mfma_f32_32x32x16_bf16; K in steps of
+// 32 staged in LDS (rows padded by 16 bytes, so the 32 lanes of a fragment read hit distinct
+// banks), double-buffered: the next step's global loads are in flight during this step's MFMAs.
+template <int K>
+__global__ __launch_bounds__(256, 2) void gemm_dh_kernel(const bf16_t *__restrict__ A, const bf16_t *__restrict__ B,
+                                                      const bf16_t *__restrict__ Z, bf16_t *__restrict__ C, int M)
 {
-    __shared__ __attribute__((aligned(16))) bf16_t As[64][40];
-    __shared__ __attribute__((aligned(16))) bf16_t Bs[64][40];
+    constexpr int KS = K < 32 ? K : 32;       // k per step
+    constexpr int NST = K / KS;
+    constexpr int LDR = KS + 8;               // bf16 per padded LDS row
+    constexpr int CPR = KS / 8;               // 16-byte chunks per row and step
+    constexpr int CA = 128 * CPR, CB = 256 * CPR;
+    constexpr int PA = (CA + 255) / 256, PB = (CB + 255) / 256;
+    __shared__ __attribute__((aligned(16))) bf16_t As[2][128][LDR];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][256][LDR];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
-    f32x4 acc[2][2];
+    const int h = lane >> 5, col = lane & 31;
+    const int m0 = blockIdx.x * 128;
+    uint4 ra[PA], rb[PB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int p = 0; p < PA; p++) {
+            const int q = t + 256 * p;
+            const int r = q / CPR, c8 = q % CPR;
+            ra[p] = make_uint4(0, 0, 0, 0);
+            if (q < CA && m0 + r < M) ra[p] = *reinterpret_cast<const uint4 *>(A + (int64_t)(m0 + r) * K + k0 + 8 * c8);
+        }
+#pragma unroll
+        for (int p = 0; p < PB; p++) {
+            const int q = t + 256 * p;
+            const int r = q / CPR, c8 = q % CPR;
+            rb[p] = make_uint4(0, 0, 0, 0);
+            if (q < CB) rb[p] = *reinterpret_cast<const uint4 *>(B + (int64_t)r * K + k0 + 8 * c8);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < PA; p++) {
+            const int q = t + 256 * p;
+            if (q < CA) *reinterpret_cast<uint4 *>(&As[buf][q / CPR][8 * (q % CPR)]) = ra[p];
+        }
+#pragma unroll
+        for (int p = 0; p < PB; p++) {
+            const int q = t + 256 * p;
+            if (q < CB) *reinterpret_cast<uint4 *>(&Bs[buf][q / CPR][8 * (q % CPR)]) = rb[p];
+        }
+    };
+    f32x16 acc[2][4];
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    for (int k0 = 0; k0 < g.K; k0 += 32) {
-        // A tile (64 m x 32 k) -> As[m][k]; B tile (64 n x 32 k) -> Bs[n][k]
-        const int r = t >> 2, k8 = (t & 3) * 8;
-        uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
-        if (m0 + r < g.M && k0 + k8 < g.K) va = *reinterpret_cast<const uint4 *>(g.A + (int64_t)(m0 + r) * g.lda + k0 + k8);
-        if (n0 + r < g.N && k0 + k8 < g.K) vb = *reinterpret_cast<const uint4 *>(g.B + (int64_t)(n0 + r) * g.ldb + k0 + k8);
-        *reinterpret_cast<uint4 *>(&As[r][k8]) = va;
-        *reinterpret_cast<uint4 *>(&Bs[r][k8]) = vb;
-        __syncthreads();
+        for (int j = 0; j < 4; j++) acc[i][j] = f32x16{};
+    load(0);
+    store(0);
+    __syncthreads();
+#pragma unroll 1
+    for (int st = 0; st < NST; st++) {
+        const int buf = st & 1;
+        if (st + 1 < NST) load((st + 1) * KS);
 #pragma unroll
-        for (int i = 0; i < 2; i++) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(&As[wm * 32 + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+        for (int kb = 0; kb < KS / 16; kb++) {
+            bf16x8 af[2], bfr[4];
 #pragma unroll
-            for (int j = 0; j < 2; j++) {
-                const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(&Bs[wn * 32 + j * 16 + (lane & 15)][8 * (lane >> 4)]);
-                acc[i][j] = mfma16(av, bv, acc[i][j]);
-            }
+            for (int i = 0; i < 2; i++)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][wm * 64 + i * 32 + col][kb * 16 + 8 * h]);
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][wn * 128 + j * 32 + col][kb * 16 + 8 * h]);
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 4; j++) acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
         }
+        if (st + 1 < NST) store(buf ^ 1);
         __syncthreads();
     }
+    // C layout of the 32 x 32 blocks: column = lane % 32 (n), rows 8q + 4h + (0..3) (m)
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++)
+        for (int v = 0; v < 16; v++) {
+            const int m = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+            if (m < M) {
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
-                const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-                if (m < g.M && n < g.N) {
-                    const float d = acc[i][j][r] * gelu_grad_f(g.Z[(int64_t)m * g.ldz + n]);
-                    g.Cb[(int64_t)m * g.ldc + n] = to_bf16(d);
+                for (int j = 0; j < 4; j++) {
+                    const int n = wn * 128 + j * 32 + col;
+                    const float d = acc[i][j][v] * gelu_grad_f(bf16_to_f(Z[(int64_t)m * HID + n]));
+                    C[(int64_t)m * HID + n] = to_bf16(d);
                 }
             }
+        }
 }
 
 // ------------------------------------------------------------------ training helpers
-// L1 loss gradient on the scaled targets: dz[i][j] = sign(y - t) / (n_rows * 6) for j < 6.
-// Per-block partial sums of |y - t| go to part[blockIdx.x] (fixed-order reduction later).
-__global__ __launch_bounds__(256) void l1_grad_kernel(const float *y, const float *Yraw, int64_t nx,
-                                                      uint64_t pa, uint64_t pc, int64_t row0, int n,
-                                                      const double *out_lo, const double *out_inv,
-                                                      unsigned logmask, bf16_t *dz, float *part)
-{
-    __shared__ float red[256];
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    float s = 0.f;
-    if (i < n) {
-        const int64_t sidx = perm_index(row0 + i, pa, pc, nx);
-        const float scale = 1.0f / ((float)n * NOUT);
-#pragma unroll
-        for (int j = 0; j < OUT_PAD; j++) {
-            float d = 0.f;
-            if (j < NOUT) {
-                double tr = (double)Yraw[(int64_t)j * nx + sidx];
-                if (logmask >> j & 1u) tr = log(tr);
-                const float t = (float)((tr - out_lo[j]) * out_inv[j]);
-                const float diff = y[(int64_t)i * OUT_PAD + j] - t;
-                s += fabsf(diff);
-                d = (diff > 0.f) ? scale : ((diff < 0.f) ? -scale : 0.f);
-            }
-            dz[(int64_t)i * OUT_PAD + j] = to_bf16(d);
-        }
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
-}
-
 // out[i] = sum_s part[s * stride + i] in order s = 0..S-1 (deterministic split-K reduction),
-// with the result written to dst[i] (gradient of a weight matrix).
+// with the result written to dst[i] (gradient of a weight matrix and its bias).
 __global__ void reduce_partials_kernel(const float *part, int S, int64_t stride, int64_t count, float *dst)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -573,67 +821,6 @@ __global__ void reduce_partials_kernel(const float *part, int S, int64_t stride,
     dst[i] = s;
 }
 
-// Column sums of a bf16 [n][ncol] matrix (ncol a multiple of 8, at most 256): block p sums
-// rows [p*rows, ...) into part[p][col].  Thread (g, c8) adds the 8 columns 8 c8.. of rows
-// r0 + g, r0 + g + G, ... with 16-byte loads; the G row groups are then combined in a fixed
-// order, so the result is deterministic.
-__global__ __launch_bounds__(256) void colsum_partial_kernel(const bf16_t *dz, int n, int ncol, int rows, float *part)
-{
-    __shared__ float red[256 * 8];
-    const int cg = ncol / 8;                  // 16-byte column groups per row
-    const int G = 256 / cg;                   // row groups per block
-    const int g = threadIdx.x / cg, c8 = threadIdx.x % cg;
-    const int r0 = blockIdx.x * rows, r1 = min(n, r0 + rows);
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (g < G) {
-        for (int r = r0 + g; r < r1; r += G) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(dz + (int64_t)r * ncol + 8 * c8);
-            const unsigned w[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                acc[2 * j] += __builtin_bit_cast(float, w[j] << 16);
-                acc[2 * j + 1] += __builtin_bit_cast(float, w[j] & 0xffff0000u);
-            }
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < 8; j++) red[threadIdx.x * 8 + j] = acc[j];
-    __syncthreads();
-    if (threadIdx.x < ncol) {
-        const int c = threadIdx.x;
-        float s = 0.f;
-        for (int q = 0; q < G; q++) s += red[(q * cg + c / 8) * 8 + (c % 8)];
-        part[blockIdx.x * ncol + c] = s;
-    }
-}
-
-// dst[c] = sum_p part[p][c] in the order p = 0, 1, ... (one thread per column, eight
-// partial rows loaded at a time)
-// dst[c] = sum over the P partial rows of column c.  A block takes 64 columns; its four
-// wave-sized groups sum every fourth row (eight loads in flight), then one group adds the
-// four group sums in a fixed order, so the result is the same bits on every run.
-__global__ __launch_bounds__(256) void sum_rows_kernel(const float *part, int P, int ncol, float *dst)
-{
-    __shared__ float red[4][64];
-    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int g = threadIdx.x >> 6;
-    float s = 0.f;
-    if (c < ncol) {
-        int p = g;
-        for (; p + 28 < P; p += 32) {
-            float v[8];
-#pragma unroll
-            for (int j = 0; j < 8; j++) v[j] = part[(int64_t)(p + 4 * j) * ncol + c];
-#pragma unroll
-            for (int j = 0; j < 8; j++) s += v[j];
-        }
-        for (; p < P; p += 4) s += part[(int64_t)p * ncol + c];
-    }
-    red[g][threadIdx.x & 63] = s;
-    __syncthreads();
-    if (g == 0 && c < ncol) dst[c] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
-}
-
 __global__ void adam_kernel(float *w, const float *gr, float *m, float *v, int64_t n, float lr,
                             float b1, float b2, float eps, float bc1, float bc2)
 {
@@ -648,22 +835,35 @@ __global__ void adam_kernel(float *w, const float *gr, float *m, float *v, int64
 }
 
 // FP32 master -> bf16 transposed [in][out] (the B operand of dz W, contiguous along its K
-// = out) and fused (row-padded, k-permuted) layouts.
-__global__ void convert_weights_kernel(const float *master, bf16_t *nat, bf16_t *fused)
+// = out) and fused (row-padded, k-permuted) layouts; each fused row also receives its bias
+// as three bf16 parts hi + mid + lo (exact: each part takes the next 8 bits of the FP32
+// significand), in the slots after the inputs.
+__global__ void convert_weights_kernel(const float *master, bf16_t *nat, bf16_t *fused, int nh)
 {
     const int l = blockIdx.y;
-    const int rows = lout(l), cols = lin(l), rowlen = lrow(l);
+    const int rows = lout(l, nh), cols = lin(l), rowlen = lrow(l);
     const int64_t cnt = (int64_t)rows * cols;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
         const int o = (int)(e / cols), i = (int)(e % cols);
-        const float wv = master[kLay::w(l) + e];
+        const float wv = master[w_off(l) + e];
         const bf16_t b = to_bf16(wv);
-        nat[kLay::nat(l) + (int64_t)i * rows + o] = b;   // transposed: [in][out]
+        nat[nat_off(l) + (int64_t)i * rows + o] = b;   // transposed: [in][out]
         // layer 0 keeps the natural input order in its one 16-deep K block (inputs >= 16
         // are padding); later layers take the permutation of the accumulator layout
         if (l == 0 && i >= FK0) continue;
         const int slot = (l == 0) ? i : kslot(i);
-        fused[kLay::f(l) + (int64_t)o * rowlen + slot] = b;
+        fused[f_off(l) + (int64_t)o * rowlen + slot] = b;
+    }
+    for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < rows; o += gridDim.x * blockDim.x) {
+        const float bv = master[b_off(l, nh) + o];
+        const bf16_t hi = to_bf16(bv);
+        const float r1 = bv - bf16_to_f(hi);
+        const bf16_t mid = to_bf16(r1);
+        const bf16_t lo = to_bf16(r1 - bf16_to_f(mid));
+        bf16_t *dst = fused + f_off(l) + (int64_t)o * rowlen + (l == 0 ? FK0 : HID);
+        dst[0] = hi;
+        dst[1] = mid;
+        dst[2] = lo;
     }
 }
 
@@ -716,130 +916,7 @@ static double u01(uint64_t &s) { return (double)(splitmix64(s) >> 11) * (1.0 / 9
 
 }  // namespace props
 
-using namespace props;
-
-// ------------------------------------------------------------------ the handle
-struct props_dnn_s {
-    int device = 0;
-    float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;   // device FP32
-    bf16_t *nat = nullptr, *fused = nullptr;
-    double *scal = nullptr;        // device: in_lo[10], in_inv[10], out_lo[6], out_rng[6], out_inv[6]
-    double in_lo[NIN], in_hi[NIN], out_lo[NOUT], out_hi[NOUT];
-    unsigned logmask = kPTYLogMask;   // outputs trained on their logarithm
-    int64_t step = 0;
-    int epoch = 0;
-    // forward/backward scratch for one batch
-    bf16_t *h0 = nullptr, *hs[4] = {}, *dz = nullptr, *dz2 = nullptr, *dzo = nullptr;
-    float *zs[4] = {}, *y = nullptr, *part = nullptr, *lpart = nullptr, *cpart = nullptr;
-    int *fb_idx = nullptr, *fb_count = nullptr;
-    int64_t fb_cap = 0;
-};
-
 namespace props {
-
-static int upload_scalers(props_dnn_s *d)
-{
-    double h[NIN * 2 + NOUT * 3];
-    for (int f = 0; f < NIN; f++) {
-        h[f] = d->in_lo[f];
-        const double r = d->in_hi[f] - d->in_lo[f];
-        h[NIN + f] = (r > 0) ? 1.0 / r : 0.0;
-    }
-    for (int j = 0; j < NOUT; j++) {
-        const double r = d->out_hi[j] - d->out_lo[j];
-        h[2 * NIN + j] = d->out_lo[j];
-        h[2 * NIN + NOUT + j] = r;
-        h[2 * NIN + 2 * NOUT + j] = (r > 0) ? 1.0 / r : 0.0;
-    }
-    PROPS_HIP_TRY(hipMemcpy(d->scal, h, sizeof(h), hipMemcpyHostToDevice));
-    return PROPS_OK;
-}
-
-static int refresh_weights(props_dnn_s *d, hipStream_t s)
-{
-    hipLaunchKernelGGL(convert_weights_kernel, dim3(64, NL), dim3(256), 0, s, d->master, d->nat, d->fused);
-    PROPS_HIP_TRY(hipGetLastError());
-    return PROPS_OK;
-}
-
-template <typename T>
-static int dalloc(T **p, size_t count)
-{
-    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
-    if (e != hipSuccess) return fail(PROPS_ENOMEM, "hipMalloc(%zu): %s", sizeof(T) * count, hipGetErrorString(e));
-    return PROPS_OK;
-}
-
-static void free_dnn(props_dnn_s *d)
-{
-    void *ps[] = {d->master, d->grad, d->m, d->v, d->nat, d->fused, d->scal, d->h0, d->dz, d->dz2, d->dzo,
-                  d->y, d->part, d->lpart, d->cpart, d->fb_idx, d->fb_count,
-                  d->hs[0], d->hs[1], d->hs[2], d->hs[3], d->zs[0], d->zs[1], d->zs[2], d->zs[3]};
-    for (void *p : ps)
-        if (p) (void)hipFree(p);
-    delete d;
-}
-
-static int alloc_dnn(props_dnn_s *d)
-{
-    int rc;
-    const size_t P = kLay::total;
-    if ((rc = dalloc(&d->master, P)) || (rc = dalloc(&d->grad, P)) || (rc = dalloc(&d->m, P)) ||
-        (rc = dalloc(&d->v, P)) || (rc = dalloc(&d->nat, kLay::nattotal)) ||
-        (rc = dalloc(&d->fused, kLay::ftotal)) || (rc = dalloc(&d->scal, (size_t)NIN * 2 + NOUT * 3)) ||
-        (rc = dalloc(&d->fb_count, 1)))
-        return rc;
-    PROPS_HIP_TRY(hipMemset(d->grad, 0, P * sizeof(float)));
-    PROPS_HIP_TRY(hipMemset(d->m, 0, P * sizeof(float)));
-    PROPS_HIP_TRY(hipMemset(d->v, 0, P * sizeof(float)));
-    PROPS_HIP_TRY(hipMemset(d->fused, 0, kLay::ftotal * sizeof(bf16_t)));
-    return PROPS_OK;
-}
-
-static int ensure_train_scratch(props_dnn_s *d)
-{
-    if (d->h0) return PROPS_OK;
-    int rc;
-    const size_t B = MAX_BATCH;
-    if ((rc = dalloc(&d->h0, B * IN_PAD)) || (rc = dalloc(&d->dz, B * HID)) || (rc = dalloc(&d->dz2, B * HID)) ||
-        (rc = dalloc(&d->dzo, B * OUT_PAD)) || (rc = dalloc(&d->y, B * OUT_PAD)) ||
-        (rc = dalloc(&d->part, (size_t)SPLITW * HID * HID)) || (rc = dalloc(&d->lpart, (size_t)B / 256 + 64)) ||
-        (rc = dalloc(&d->cpart, (size_t)256 * HID)))
-        return rc;
-    // the forward writes input columns 0..15 of the saved inputs; 16..31 stay zero
-    PROPS_HIP_TRY(hipMemset(d->h0, 0, sizeof(bf16_t) * B * IN_PAD));
-    for (int l = 0; l < 4; l++)
-        if ((rc = dalloc(&d->hs[l], B * HID)) || (rc = dalloc(&d->zs[l], B * HID))) return rc;
-    return PROPS_OK;
-}
-
-static int fwd_grid(int64_t n)
-{
-    int dev = 0, cus = 256;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        int v = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-    }
-    const int64_t tiles = (n + TILE_CELLS - 1) / TILE_CELLS;
-    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, cus));
-}
-
-static std::once_flag g_lds_once;
-static hipError_t g_lds_err = hipSuccess;
-static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
-{
-    std::call_once(g_lds_once, [] {
-        g_lds_err = hipFuncSetAttribute((const void *)mlp_fwd_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
-        if (g_lds_err == hipSuccess)
-            g_lds_err = hipFuncSetAttribute((const void *)mlp_fwd_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
-    });
-    if (g_lds_err != hipSuccess) return fail(PROPS_EHIP, "hipFuncSetAttribute(LDS %d B): %s", LDS_BYTES, hipGetErrorString(g_lds_err));
-    const int grid = fwd_grid(a.n);
-    if (train) hipLaunchKernelGGL(mlp_fwd_kernel<true>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
-    else hipLaunchKernelGGL(mlp_fwd_kernel<false>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
-    PROPS_HIP_TRY(hipGetLastError());
-    return PROPS_OK;
-}
 
 // Weight gradient C_z[m][n] = sum_{k in split z} A[k][m] B[k][n], with both operands stored
 // k-major ([batch][feature] activations and output gradients), on v_mfma_f32_32x32x16_bf16,
@@ -851,7 +928,9 @@ static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
 // flight during the current step's MFMAs, one barrier per step.
 // A tile of TM x TN outputs per workgroup of 4 waves arranged WAVES_M x (4 / WAVES_M), each
 // wave BM x BN blocks of 32 x 32.  Columns at or beyond M (N) read as zero and are not
-// written, so the 16-row output layer runs on a 32-row tile.
+// written, so the 16-row output layer runs on a 32-row tile.  The workgroups of the first
+// column tile also sum the staged A columns over their K range (Cb: the bias gradient's
+// partials, the column sums of dz), in the same fixed order on every run.
 constexpr int KW_PAD = 8;          // extra pair-dwords per LDS row
 __device__ __forceinline__ void kw_interleave(uint4 x, uint4 y, uint4 &lo, uint4 &hi)
 {
@@ -869,7 +948,8 @@ __device__ __forceinline__ void kw_interleave(uint4 x, uint4 y, uint4 &lo, uint4
 
 template <int TM, int TN, int WAVES_M>
 __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int lda, int M, const bf16_t *B, int ldb,
-                                                          int N, int K, int kchunk, float *C, int ldc, int64_t strideC)
+                                                          int N, int K, int kchunk, float *C, int ldc, int64_t strideC,
+                                                          float *Cb)
 {
     constexpr int WAVES_N = 4 / WAVES_M;
     constexpr int BM = TM / WAVES_M / 32, BN = TN / WAVES_N / 32;
@@ -935,6 +1015,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
 #pragma unroll
         for (int j = 0; j < BN; j++) acc[i][j] = f32x16{};
     uint4 rx[PER][2];
+    float csum = 0.f;
     int buf = 0;
     if (kbeg < kend) {
         load(kbeg, rx);
@@ -968,10 +1049,20 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
 #pragma unroll
                 for (int j = 0; j < BN; j++) acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
         }
+        if (Cb && blockIdx.x == 0 && t < TM) {
+            // column t of the A tile: 16 (k even, k odd) pairs of this step
+#pragma unroll
+            for (int kp = 0; kp < 16; kp++) {
+                const unsigned v = As[buf][kp][t];
+                csum += __builtin_bit_cast(float, v << 16);
+                csum += __builtin_bit_cast(float, v & 0xffff0000u);
+            }
+        }
         if (more) store(buf ^ 1, rx);
         __syncthreads();
         buf ^= 1;
     }
+    if (Cb && blockIdx.x == 0 && t < TM && m0 + t < M) Cb[blockIdx.z * strideC + m0 + t] = csum;
     // C layout of the 32 x 32 blocks: column = lane % 32 (n), rows 8q + 4h + (0..3) (m)
     float *Cz = C + blockIdx.z * strideC;
 #pragma unroll
@@ -988,20 +1079,158 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
 
 // dW = dz^T h for the layer shapes of the network: (256, 256) on 128 x 128 tiles, (256, 32)
 // (input layer) on 128 x 32 tiles, (16, 256) (output layer) on 32 x 128 tiles.
+}  // namespace props
+
+using namespace props;
+
+// ------------------------------------------------------------------ the handle
+struct props_dnn_s {
+    int device = 0;
+    int nhid = 4, nout = NOUT;
+    float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;   // device FP32
+    bf16_t *nat = nullptr, *fused = nullptr;
+    double *scal = nullptr;        // device: in_lo[10], in_inv[10], out_lo[6], out_rng[6], out_inv[6]
+    double in_lo[NIN], in_hi[NIN], out_lo[NOUT], out_hi[NOUT];
+    unsigned logmask = kPTYLogMask;   // outputs trained on their logarithm
+    int64_t step = 0;
+    int epoch = 0;
+    // forward/backward scratch for one batch
+    bf16_t *h0 = nullptr, *zs[MAX_HIDDEN] = {}, *hs[MAX_HIDDEN] = {}, *dz = nullptr, *dz2 = nullptr, *dzo = nullptr;
+    float *part = nullptr, *lpart = nullptr;
+    int *fb_idx = nullptr, *fb_count = nullptr;
+    int64_t fb_cap = 0;
+    size_t params() const { return total_params(nhid); }
+};
+
+namespace props {
+
+static int upload_scalers(props_dnn_s *d)
+{
+    double h[NIN * 2 + NOUT * 3];
+    for (int f = 0; f < NIN; f++) {
+        h[f] = d->in_lo[f];
+        const double r = d->in_hi[f] - d->in_lo[f];
+        h[NIN + f] = (r > 0) ? 1.0 / r : 0.0;
+    }
+    for (int j = 0; j < NOUT; j++) {
+        const double r = d->out_hi[j] - d->out_lo[j];
+        h[2 * NIN + j] = d->out_lo[j];
+        h[2 * NIN + NOUT + j] = r;
+        h[2 * NIN + 2 * NOUT + j] = (r > 0) ? 1.0 / r : 0.0;
+    }
+    PROPS_HIP_TRY(hipMemcpy(d->scal, h, sizeof(h), hipMemcpyHostToDevice));
+    return PROPS_OK;
+}
+
+static int refresh_weights(props_dnn_s *d, hipStream_t s)
+{
+    hipLaunchKernelGGL(convert_weights_kernel, dim3(64, d->nhid + 1), dim3(256), 0, s, d->master, d->nat, d->fused,
+                       d->nhid);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
+}
+
+template <typename T>
+static int dalloc(T **p, size_t count)
+{
+    hipError_t e = hipMalloc((void **)p, sizeof(T) * count);
+    if (e != hipSuccess) return fail(PROPS_ENOMEM, "hipMalloc(%zu): %s", sizeof(T) * count, hipGetErrorString(e));
+    return PROPS_OK;
+}
+
+static void free_dnn(props_dnn_s *d)
+{
+    void *ps[] = {d->master, d->grad, d->m, d->v, d->nat, d->fused, d->scal, d->h0, d->dz, d->dz2, d->dzo,
+                  d->part, d->lpart, d->fb_idx, d->fb_count};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    if (d->zs[0]) (void)hipFree(d->zs[0]);
+    if (d->hs[0]) (void)hipFree(d->hs[0]);
+    delete d;
+}
+
+static int alloc_dnn(props_dnn_s *d)
+{
+    int rc;
+    const size_t P = d->params();
+    if ((rc = dalloc(&d->master, P)) || (rc = dalloc(&d->grad, P)) || (rc = dalloc(&d->m, P)) ||
+        (rc = dalloc(&d->v, P)) || (rc = dalloc(&d->nat, nat_total(d->nhid))) ||
+        (rc = dalloc(&d->fused, f_total(d->nhid))) || (rc = dalloc(&d->scal, (size_t)NIN * 2 + NOUT * 3)) ||
+        (rc = dalloc(&d->fb_count, 1)))
+        return rc;
+    PROPS_HIP_TRY(hipMemset(d->grad, 0, P * sizeof(float)));
+    PROPS_HIP_TRY(hipMemset(d->m, 0, P * sizeof(float)));
+    PROPS_HIP_TRY(hipMemset(d->v, 0, P * sizeof(float)));
+    PROPS_HIP_TRY(hipMemset(d->fused, 0, f_total(d->nhid) * sizeof(bf16_t)));
+    return PROPS_OK;
+}
+
+static int ensure_train_scratch(props_dnn_s *d)
+{
+    if (d->h0) return PROPS_OK;
+    int rc;
+    const size_t B = MAX_BATCH;
+    if ((rc = dalloc(&d->h0, B * IN_PAD)) || (rc = dalloc(&d->dz, B * HID)) || (rc = dalloc(&d->dz2, B * HID)) ||
+        (rc = dalloc(&d->dzo, B * OUT_PAD)) ||
+        (rc = dalloc(&d->part, (size_t)SPLITW * (HID * HID + HID))) ||
+        (rc = dalloc(&d->lpart, (size_t)B / CELLS_PER_WAVE + 64)))
+        return rc;
+    // the forward writes input columns 0..15 of the saved inputs; 16..31 stay zero
+    PROPS_HIP_TRY(hipMemset(d->h0, 0, sizeof(bf16_t) * B * IN_PAD));
+    // the hidden layers' saves, one block each, layer l at offset l B 256
+    if ((rc = dalloc(&d->hs[0], B * HID * d->nhid)) || (rc = dalloc(&d->zs[0], B * HID * d->nhid))) return rc;
+    for (int l = 1; l < d->nhid; l++) d->hs[l] = d->hs[0] + l * B * HID, d->zs[l] = d->zs[0] + l * B * HID;
+    return PROPS_OK;
+}
+
+// One workgroup per CU, capped by the tile count.
+static int fwd_grid(int64_t n)
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+    }
+    const int64_t tiles = (n + TILE_CELLS - 1) / TILE_CELLS;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus));
+}
+
+static std::once_flag g_lds_once;
+static hipError_t g_lds_err = hipSuccess;
+static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
+{
+    std::call_once(g_lds_once, [] {
+        g_lds_err = hipFuncSetAttribute((const void *)mlp_fwd_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+        if (g_lds_err == hipSuccess)
+            g_lds_err = hipFuncSetAttribute((const void *)mlp_fwd_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, LDS_BYTES);
+    });
+    if (g_lds_err != hipSuccess) return fail(PROPS_EHIP, "hipFuncSetAttribute(LDS %d B): %s", LDS_BYTES, hipGetErrorString(g_lds_err));
+    const int grid = fwd_grid(a.n);
+    if (train) hipLaunchKernelGGL(mlp_fwd_kernel<true>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
+    else hipLaunchKernelGGL(mlp_fwd_kernel<false>, dim3(grid), dim3(FWD_THREADS), LDS_BYTES, s, a);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
+}
+
+// dW = dz^T h (and db = column sums of dz) for the layer shapes of the network: (256, 256) on
+// 128 x 128 tiles, (256, 32) (input layer) on 128 x 32 tiles, (16, 256) (output layer) on
+// 32 x 128 tiles.  Split z writes its W partials at part + z (O I + O) and its bias partials
+// right after them, so one ordered reduction gives W and b, which are adjacent in the master.
 static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float *part, int &splits, hipStream_t s)
 {
     const int kchunk = ((n + SPLITW - 1) / SPLITW + 31) / 32 * 32;
     splits = (n + kchunk - 1) / kchunk;
-    const int64_t stride = (int64_t)O * I;
+    const int64_t stride = (int64_t)O * I + O;
+    float *pb = part + (int64_t)O * I;
     if (O % 128 == 0 && I % 128 == 0) {
         hipLaunchKernelGGL((gemm_wgrad_kernel<128, 128, 2>), dim3(I / 128, O / 128, splits), dim3(256), 0, s,
-                           dz, O, O, hp, I, I, n, kchunk, part, I, stride);
+                           dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
     } else if (O % 128 == 0 && I == 32) {
         hipLaunchKernelGGL((gemm_wgrad_kernel<128, 32, 4>), dim3(1, O / 128, splits), dim3(256), 0, s,
-                           dz, O, O, hp, I, I, n, kchunk, part, I, stride);
+                           dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
     } else if (O <= 32 && O % 8 == 0 && I % 128 == 0) {
         hipLaunchKernelGGL((gemm_wgrad_kernel<32, 128, 1>), dim3(I / 128, 1, splits), dim3(256), 0, s,
-                           dz, O, O, hp, I, I, n, kchunk, part, I, stride);
+                           dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
     } else {
         return fail(PROPS_EINVAL, "wgrad: unsupported layer shape %d x %d", O, I);
     }
@@ -1009,66 +1238,59 @@ static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float 
     return PROPS_OK;
 }
 
-static int gemm_dh(const GemmArgs &g, hipStream_t s)
-{
-    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, 1);
-    hipLaunchKernelGGL(gemm_dh_kernel, grid, dim3(256), 0, s, g);
-    PROPS_HIP_TRY(hipGetLastError());
-    return PROPS_OK;
-}
-
 // One forward + backward pass over rows [row0, row0 + n) of the permuted data; leaves the
-// gradient in d->grad and the loss partials (n/256 blocks) in d->lpart.
+// gradient in d->grad and the loss partials (one per wave of 32 rows) in d->lpart.
 static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, uint64_t pa, uint64_t pc,
                    int64_t row0, int n, hipStream_t s)
 {
     int rc;
+    const int nh = d->nhid;
     FwdArgs a{};
     a.X = X;
+    a.Yt = Y;
     a.nx = nx;
     a.pa = pa;
     a.pc = pc;
     a.row0 = row0;
     a.n = n;
+    a.nhid = nh;
+    a.nout = d->nout;
     a.Wf = d->fused;
-    a.bias = d->master;
     a.in_lo = d->scal;
     a.in_inv = d->scal + NIN;
+    a.out_lo = d->scal + 2 * NIN;
+    a.out_inv = d->scal + 2 * NIN + 2 * NOUT;
+    a.logmask = d->logmask;
     a.h0 = d->h0;
-    for (int l = 0; l < 4; l++) {
-        a.z[l] = d->zs[l];
-        a.h[l] = d->hs[l];
-    }
-    a.y = d->y;
+    a.zs = d->zs[0];
+    a.hs = d->hs[0];
+    a.lstride = (int64_t)MAX_BATCH * HID;
+    a.dzo = d->dzo;
+    a.lpart = d->lpart;
     if ((rc = launch_fwd(true, a, s))) return rc;
-    const int nb = (n + 255) / 256;
-    hipLaunchKernelGGL(l1_grad_kernel, dim3(nb), dim3(256), 0, s, d->y, Y, nx, pa, pc, row0, n,
-                       d->scal + 2 * NIN, d->scal + 2 * NIN + 2 * NOUT, d->logmask, d->dzo, d->lpart);
-    PROPS_HIP_TRY(hipGetLastError());
     // layer by layer, output to input
     const bf16_t *dzl = d->dzo;
-    for (int l = NL - 1; l >= 0; l--) {
-        const int O = lout(l), I = lin(l);
+    for (int l = nh; l >= 0; l--) {
+        const int O = lout(l, nh), I = lin(l);
         const bf16_t *hprev = (l == 0) ? d->h0 : d->hs[l - 1];
-        // dW = dz^T h  (M = O, N = I, K = n), split over the batch
+        // dW = dz^T h and db = sum dz  (M = O, N = I, K = n), split over the batch
         int splits = 0;
         if ((rc = wgrad(dzl, O, hprev, I, n, d->part, splits, s))) return rc;
-        const int64_t cnt = (int64_t)O * I;
+        const int64_t cnt = (int64_t)O * I + O;
         hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
-                           d->part, splits, (int64_t)O * I, cnt, d->grad + kLay::w(l));
-        // db = column sums of dz
-        const int rows = 256, P = (n + rows - 1) / rows;
-        hipLaunchKernelGGL(colsum_partial_kernel, dim3(P), dim3(256), 0, s, dzl, n, O, rows, d->cpart);
-        hipLaunchKernelGGL(sum_rows_kernel, dim3((O + 63) / 64), dim3(256), 0, s, d->cpart, P, O, d->grad + kLay::b(l));
+                           d->part, splits, cnt, cnt, d->grad + w_off(l));
         PROPS_HIP_TRY(hipGetLastError());
         if (l > 0) {
-            // dz_{l-1} = (dz W) * gelu'(z_{l-1})  (M = n, N = I = 256, K = O)
+            // dz_{l-1} = (dz W) * gelu'(z_{l-1})  (M = n, N = 256, K = O)
             bf16_t *out = (dzl == d->dz) ? d->dz2 : d->dz;
-            GemmArgs gh{};
-            gh.M = n, gh.N = I, gh.K = O;
-            gh.A = dzl, gh.lda = O, gh.B = d->nat + kLay::nat(l), gh.ldb = O;
-            gh.Cb = out, gh.ldc = I, gh.Z = d->zs[l - 1], gh.ldz = HID;
-            if ((rc = gemm_dh(gh, s))) return rc;
+            const unsigned blocks = (unsigned)((n + 127) / 128);
+            if (O == HID)
+                hipLaunchKernelGGL(gemm_dh_kernel<HID>, dim3(blocks), dim3(256), 0, s, dzl, d->nat + nat_off(l),
+                                   d->zs[l - 1], out, n);
+            else
+                hipLaunchKernelGGL(gemm_dh_kernel<OUT_PAD>, dim3(blocks), dim3(256), 0, s, dzl, d->nat + nat_off(l),
+                                   d->zs[l - 1], out, n);
+            PROPS_HIP_TRY(hipGetLastError());
             dzl = out;
         }
     }
@@ -1126,18 +1348,20 @@ int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_o
              int64_t ldy, uint8_t *status, int *fb_idx, int *fb_count, hipStream_t s)
 {
     if (!in->P || !in->T || !in->Y) return fail(PROPS_EINVAL, "props_dnn: needs P, T and Y");
-    if (d->logmask != kPTYLogMask)
-        return fail(PROPS_EINVAL, "props_dnn: the network's log outputs (mask 0x%x) are not those of "
-                    "(rho, h, cp, c, mu, lambda); evaluate it with props_dnn_features", d->logmask);
+    if (d->logmask != kPTYLogMask || d->nout != NOUT)
+        return fail(PROPS_EINVAL, "props_dnn: the network (%d outputs, log mask 0x%x) is not one of (rho, h, cp, "
+                    "c, mu, lambda); evaluate it with props_dnn_features", d->nout, d->logmask);
     if (fb && fb->ns != NIN - 2)
         return fail(PROPS_EINVAL, "props_dnn: fallback mechanism has %d species, the network %d", fb->ns, NIN - 2);
     if (fb && (!fb_idx || !fb_count)) return fail(PROPS_EINVAL, "props_dnn: fallback needs index scratch");
     int rc;
     FwdArgs a{};
     a.P = in->P, a.T = in->T, a.Y = in->Y, a.n = n, a.ldy = ldy;
-    a.Wf = d->fused, a.bias = d->master;
+    a.nhid = d->nhid, a.nout = d->nout;
+    a.Wf = d->fused;
     a.in_lo = d->scal, a.in_inv = d->scal + NIN;
     a.out_lo = d->scal + 2 * NIN, a.out_rng = d->scal + 2 * NIN + NOUT;
+    a.logmask = d->logmask;
     a.orho = out->rho, a.oh = out->h, a.ocp = out->cp, a.oc = out->c, a.omu = out->mu, a.olam = out->lambda;
     a.status = status;
     if (fb) {
@@ -1158,16 +1382,58 @@ int dnn_eval(props_dnn_s *d, props_mech_s *fb, const props_in *in, const props_o
     return PROPS_OK;
 }
 
+static int fit_scalers_dev(props_dnn_s *d, const float *X, const float *Y, int64_t n, hipStream_t s)
+{
+    const int B = 256;
+    const int64_t per = (n + B - 1) / B;
+    double *part = nullptr;
+    int rc;
+    const int no = d->nout;
+    if ((rc = dalloc(&part, (size_t)B * 2 * (NIN + no)))) return rc;
+    hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, NIN), dim3(256), 0, s, X, n, NIN, 0u, per, part);
+    hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, no), dim3(256), 0, s, Y, n, no, d->logmask, per,
+                       part + (size_t)B * 2 * NIN);
+    std::vector<double> h((size_t)B * 2 * (NIN + no));
+    hipError_t e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(part);
+    if (e != hipSuccess) return fail(PROPS_EHIP, "fit scalers: %s", hipGetErrorString(e));
+    for (int f = 0; f < NIN + no; f++) {
+        double lo = INFINITY, hi = -INFINITY;
+        for (int b = 0; b < B; b++) {
+            lo = std::min(lo, h[((size_t)f * B + b) * 2]);
+            hi = std::max(hi, h[((size_t)f * B + b) * 2 + 1]);
+        }
+        if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(PROPS_EINVAL, "train_dnn: non-finite data in column %d", f);
+        if (f < NIN) d->in_lo[f] = lo, d->in_hi[f] = hi;
+        else d->out_lo[f - NIN] = lo, d->out_hi[f - NIN] = hi;
+    }
+    return upload_scalers(d);
+}
+
+static double loss_of(const std::vector<float> &lp, int64_t rows, int nout)
+{
+    double sl = 0;
+    for (float v : lp) sl += v;
+    return sl / ((double)rows * nout);
+}
+
 }  // namespace props
 
 extern "C" {
 
-int props_dnn_create(uint64_t seed, props_dnn_t *out)
+int props_dnn_create_ex(uint64_t seed, int hidden_layers, int outputs, props_dnn_t *out)
 {
     if (!out) return fail(PROPS_EINVAL, "props_dnn_create: out is NULL");
     *out = nullptr;
+    if (hidden_layers < MIN_HIDDEN || hidden_layers > MAX_HIDDEN)
+        return fail(PROPS_EINVAL, "props_dnn_create: %d hidden layers (%d or %d supported)", hidden_layers, MIN_HIDDEN,
+                    MAX_HIDDEN);
+    if (outputs < 1 || outputs > NOUT) return fail(PROPS_EINVAL, "props_dnn_create: %d outputs (1..%d)", outputs, NOUT);
     props_dnn_s *d = new (std::nothrow) props_dnn_s();
     if (!d) return fail(PROPS_ENOMEM, "props_dnn_create: out of host memory");
+    d->nhid = hidden_layers;
+    d->nout = outputs;
     if (hipGetDevice(&d->device) != hipSuccess) {
         delete d;
         return fail(PROPS_EHIP, "props_dnn_create: hipGetDevice failed");
@@ -1177,13 +1443,15 @@ int props_dnn_create(uint64_t seed, props_dnn_t *out)
         free_dnn(d);
         return rc;
     }
-    std::vector<float> h(kLay::total, 0.0f);
+    const int nh = d->nhid;
+    std::vector<float> h(d->params(), 0.0f);
     uint64_t st = seed;
-    for (int l = 0; l < NL; l++) {
+    for (int l = 0; l <= nh; l++) {
         const double k = 1.0 / std::sqrt((double)tin(l));
-        for (int o = 0; o < tout(l); o++)
-            for (int i = 0; i < tin(l); i++) h[kLay::w(l) + (size_t)o * lin(l) + i] = (float)((2.0 * u01(st) - 1.0) * k);
-        for (int o = 0; o < tout(l); o++) h[kLay::b(l) + o] = (float)((2.0 * u01(st) - 1.0) * k);
+        const int to = tout(l, nh, d->nout);
+        for (int o = 0; o < to; o++)
+            for (int i = 0; i < tin(l); i++) h[w_off(l) + (size_t)o * lin(l) + i] = (float)((2.0 * u01(st) - 1.0) * k);
+        for (int o = 0; o < to; o++) h[b_off(l, nh) + o] = (float)((2.0 * u01(st) - 1.0) * k);
     }
     for (int f = 0; f < NIN; f++) d->in_lo[f] = 0.0, d->in_hi[f] = 1.0;
     for (int j = 0; j < NOUT; j++) d->out_lo[j] = 0.0, d->out_hi[j] = 1.0;
@@ -1197,35 +1465,47 @@ int props_dnn_create(uint64_t seed, props_dnn_t *out)
     return PROPS_OK;
 }
 
+int props_dnn_create(uint64_t seed, props_dnn_t *out) { return props_dnn_create_ex(seed, 4, NOUT, out); }
+
 void props_dnn_destroy(props_dnn_t net)
 {
     if (net) free_dnn(net);
 }
 
+int props_dnn_get_shape(props_dnn_t d, int *hidden_layers, int *outputs)
+{
+    if (!d) return fail(PROPS_EINVAL, "props_dnn_get_shape: null network");
+    if (hidden_layers) *hidden_layers = d->nhid;
+    if (outputs) *outputs = d->nout;
+    return PROPS_OK;
+}
+
 int props_dnn_get_layer(props_dnn_t d, int l, float *W, float *b)
 {
-    if (!d || l < 0 || l >= NL) return fail(PROPS_EINVAL, "props_dnn_get_layer: bad network or layer");
-    std::vector<float> h((size_t)lout(l) * lin(l) + lout(l));
-    PROPS_HIP_TRY(hipMemcpy(h.data(), d->master + kLay::w(l), h.size() * sizeof(float), hipMemcpyDeviceToHost));
-    for (int o = 0; o < tout(l); o++) {
+    if (!d || l < 0 || l > d->nhid) return fail(PROPS_EINVAL, "props_dnn_get_layer: bad network or layer");
+    const int nh = d->nhid, to = tout(l, nh, d->nout);
+    std::vector<float> h((size_t)lout(l, nh) * lin(l) + lout(l, nh));
+    PROPS_HIP_TRY(hipMemcpy(h.data(), d->master + w_off(l), h.size() * sizeof(float), hipMemcpyDeviceToHost));
+    for (int o = 0; o < to; o++) {
         if (W)
             for (int i = 0; i < tin(l); i++) W[(size_t)o * tin(l) + i] = h[(size_t)o * lin(l) + i];
-        if (b) b[o] = h[(size_t)lout(l) * lin(l) + o];
+        if (b) b[o] = h[(size_t)lout(l, nh) * lin(l) + o];
     }
     return PROPS_OK;
 }
 
 int props_dnn_set_layer(props_dnn_t d, int l, const float *W, const float *b)
 {
-    if (!d || l < 0 || l >= NL || !W || !b) return fail(PROPS_EINVAL, "props_dnn_set_layer: bad arguments");
-    std::vector<float> h((size_t)lout(l) * lin(l) + lout(l), 0.0f);
-    for (int o = 0; o < tout(l); o++) {
+    if (!d || l < 0 || l > d->nhid || !W || !b) return fail(PROPS_EINVAL, "props_dnn_set_layer: bad arguments");
+    const int nh = d->nhid, to = tout(l, nh, d->nout);
+    std::vector<float> h((size_t)lout(l, nh) * lin(l) + lout(l, nh), 0.0f);
+    for (int o = 0; o < to; o++) {
         for (int i = 0; i < tin(l); i++) h[(size_t)o * lin(l) + i] = W[(size_t)o * tin(l) + i];
-        h[(size_t)lout(l) * lin(l) + o] = b[o];
+        h[(size_t)lout(l, nh) * lin(l) + o] = b[o];
     }
-    PROPS_HIP_TRY(hipMemcpy(d->master + kLay::w(l), h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
-    PROPS_HIP_TRY(hipMemset(d->m + kLay::w(l), 0, h.size() * sizeof(float)));
-    PROPS_HIP_TRY(hipMemset(d->v + kLay::w(l), 0, h.size() * sizeof(float)));
+    PROPS_HIP_TRY(hipMemcpy(d->master + w_off(l), h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice));
+    PROPS_HIP_TRY(hipMemset(d->m + w_off(l), 0, h.size() * sizeof(float)));
+    PROPS_HIP_TRY(hipMemset(d->v + w_off(l), 0, h.size() * sizeof(float)));
     int rc = refresh_weights(d, nullptr);
     if (rc) return rc;
     PROPS_HIP_TRY(hipDeviceSynchronize());
@@ -1308,7 +1588,8 @@ int props_dnn_features(props_dnn_t d, const double *X, double *Y, int64_t n, voi
     if (n > 0x7fffffffLL) return fail(PROPS_ETOOBIG, "props_dnn_features: n too large");
     FwdArgs a{};
     a.Xd = X, a.Yd = Y, a.n = n;
-    a.Wf = d->fused, a.bias = d->master;
+    a.nhid = d->nhid, a.nout = d->nout;
+    a.Wf = d->fused;
     a.in_lo = d->scal, a.in_inv = d->scal + NIN;
     a.out_lo = d->scal + 2 * NIN, a.out_rng = d->scal + 2 * NIN + NOUT;
     a.logmask = d->logmask;
@@ -1350,34 +1631,6 @@ int props_features_hpz(const int *atoms, const double *W, int ns, int fuel, int 
     return PROPS_OK;
 }
 
-static int fit_scalers_dev(props_dnn_s *d, const float *X, const float *Y, int64_t n, hipStream_t s)
-{
-    const int B = 256;
-    const int64_t per = (n + B - 1) / B;
-    double *part = nullptr;
-    int rc;
-    if ((rc = dalloc(&part, (size_t)B * 2 * (NIN + NOUT)))) return rc;
-    hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, NIN), dim3(256), 0, s, X, n, NIN, 0u, per, part);
-    hipLaunchKernelGGL(minmax_partial_kernel, dim3(B, NOUT), dim3(256), 0, s, Y, n, NOUT, d->logmask, per,
-                       part + (size_t)B * 2 * NIN);
-    std::vector<double> h((size_t)B * 2 * (NIN + NOUT));
-    hipError_t e = hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(part);
-    if (e != hipSuccess) return fail(PROPS_EHIP, "fit scalers: %s", hipGetErrorString(e));
-    for (int f = 0; f < NIN + NOUT; f++) {
-        double lo = INFINITY, hi = -INFINITY;
-        for (int b = 0; b < B; b++) {
-            lo = std::min(lo, h[((size_t)f * B + b) * 2]);
-            hi = std::max(hi, h[((size_t)f * B + b) * 2 + 1]);
-        }
-        if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(PROPS_EINVAL, "train_dnn: non-finite data in column %d", f);
-        if (f < NIN) d->in_lo[f] = lo, d->in_hi[f] = hi;
-        else d->out_lo[f - NIN] = lo, d->out_hi[f - NIN] = hi;
-    }
-    return upload_scalers(d);
-}
-
 int props_dnn_grad(props_dnn_t d, const float *X, const float *Y, int64_t n, float *grad, float *loss,
                    void *hip_stream)
 {
@@ -1388,21 +1641,20 @@ int props_dnn_grad(props_dnn_t d, const float *X, const float *Y, int64_t n, flo
     int rc;
     if ((rc = ensure_train_scratch(d))) return rc;
     if ((rc = fwd_bwd(d, X, Y, n, 1, 0, 0, (int)n, s))) return rc;
-    std::vector<float> g(kLay::total), lp((n + 255) / 256);
+    const int nh = d->nhid;
+    const size_t nw = (size_t)((n + TILE_CELLS - 1) / TILE_CELLS) * FWD_WAVES;
+    std::vector<float> g(d->params()), lp(nw);
     PROPS_HIP_TRY(hipMemcpyAsync(g.data(), d->grad, g.size() * sizeof(float), hipMemcpyDeviceToHost, s));
     PROPS_HIP_TRY(hipMemcpyAsync(lp.data(), d->lpart, lp.size() * sizeof(float), hipMemcpyDeviceToHost, s));
     PROPS_HIP_TRY(hipStreamSynchronize(s));
     size_t o = 0;
-    for (int l = 0; l < NL; l++) {
-        for (int r = 0; r < tout(l); r++)
-            for (int i = 0; i < tin(l); i++) grad[o++] = g[kLay::w(l) + (size_t)r * lin(l) + i];
-        for (int r = 0; r < tout(l); r++) grad[o++] = g[kLay::b(l) + r];
+    for (int l = 0; l <= nh; l++) {
+        const int to = tout(l, nh, d->nout);
+        for (int r = 0; r < to; r++)
+            for (int i = 0; i < tin(l); i++) grad[o++] = g[w_off(l) + (size_t)r * lin(l) + i];
+        for (int r = 0; r < to; r++) grad[o++] = g[b_off(l, nh) + r];
     }
-    if (loss) {
-        double sl = 0;
-        for (float v : lp) sl += v;
-        *loss = (float)(sl / ((double)n * NOUT));
-    }
+    if (loss) *loss = (float)loss_of(lp, n, d->nout);
     return PROPS_OK;
 }
 
@@ -1424,18 +1676,18 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
     const float b1 = cfg->beta1 > 0 ? cfg->beta1 : 0.9f, b2 = cfg->beta2 > 0 ? cfg->beta2 : 0.999f;
     const float eps = cfg->eps > 0 ? cfg->eps : 1e-8f;
     const int64_t steps_per_epoch = (n + batch - 1) / batch;
-    const int64_t P = (int64_t)kLay::total;
+    const int64_t P = (int64_t)d->params();
     std::vector<float> lp;
     int64_t steps = 0;
-    float *lsum = nullptr;   // per-step loss partial sums of one epoch
-    const int lblocks = batch / 256;
-    if ((rc = dalloc(&lsum, (size_t)steps_per_epoch * lblocks))) return rc;
+    float *lsum = nullptr;   // per-step loss partials of one epoch (one per wave of 32 rows)
+    const int lslots = batch / CELLS_PER_WAVE;
+    if ((rc = dalloc(&lsum, (size_t)steps_per_epoch * lslots))) return rc;
     for (int e = 0; e < cfg->epochs; e++) {
         uint64_t pa, pc;
         epoch_perm(cfg->seed, d->epoch, n, pa, pc);
         const double prog = std::min(1.0, (double)d->epoch / total);
-        hipLaunchKernelGGL(fill_float_kernel, dim3((unsigned)((steps_per_epoch * lblocks + 255) / 256)), dim3(256), 0, s,
-                           lsum, steps_per_epoch * lblocks, 0.0f);
+        hipLaunchKernelGGL(fill_float_kernel, dim3((unsigned)((steps_per_epoch * lslots + 255) / 256)), dim3(256), 0, s,
+                           lsum, steps_per_epoch * lslots, 0.0f);
         const float lr = (float)(cfg->lr_min + 0.5 * (cfg->lr - cfg->lr_min) * (1.0 + std::cos(M_PI * prog)));
         for (int64_t st = 0; st < steps_per_epoch; st++) {
             const int64_t row0 = st * batch;
@@ -1444,8 +1696,8 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
                 (void)hipFree(lsum);
                 return rc;
             }
-            PROPS_HIP_TRY(hipMemcpyAsync(lsum + st * lblocks, d->lpart, sizeof(float) * ((m + 255) / 256),
-                                         hipMemcpyDeviceToDevice, s));
+            const size_t nw = (size_t)((m + TILE_CELLS - 1) / TILE_CELLS) * FWD_WAVES;
+            PROPS_HIP_TRY(hipMemcpyAsync(lsum + st * lslots, d->lpart, sizeof(float) * nw, hipMemcpyDeviceToDevice, s));
             d->step++;
             const float bc1 = 1.0f - std::pow(b1, (float)d->step), bc2 = 1.0f - std::pow(b2, (float)d->step);
             hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, d->master, d->grad,
@@ -1456,16 +1708,14 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
             }
             steps++;
         }
-        lp.resize((size_t)steps_per_epoch * lblocks);
+        lp.resize((size_t)steps_per_epoch * lslots);
         hipError_t err = hipMemcpyAsync(lp.data(), lsum, lp.size() * sizeof(float), hipMemcpyDeviceToHost, s);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         if (err != hipSuccess) {
             (void)hipFree(lsum);
             return fail(PROPS_EHIP, "train_dnn: %s", hipGetErrorString(err));
         }
-        double sl = 0;
-        for (float v : lp) sl += v;
-        if (rep && rep->loss) rep->loss[e] = (float)(sl / ((double)n * NOUT));
+        if (rep && rep->loss) rep->loss[e] = (float)loss_of(lp, n, d->nout);
         d->epoch++;
     }
     (void)hipFree(lsum);
@@ -1480,13 +1730,14 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
     return PROPS_OK;
 }
 
-// ---- checkpoint: "PROPSDNN" v2 | step | epoch | log-output mask | scalers | master | m | v
-// (v1, without the mask, loads with the (P, T, Y) surrogate's mask)
+// ---- checkpoint: "PROPSDNN" v3 | params | step | epoch | log-output mask | hidden layers |
+// outputs | scalers | master | m | v  (v1, v2: the 4-layer, 6-output network; v1 without the
+// mask loads with the (P, T, Y) surrogate's mask)
 int props_dnn_save(props_dnn_t d, const char *path)
 {
     ApiRange range_("props_dnn_save");
     if (!d || !path) return fail(PROPS_EINVAL, "props_dnn_save: null argument");
-    const size_t P = kLay::total;
+    const size_t P = d->params();
     std::vector<float> buf(3 * P);
     PROPS_HIP_TRY(hipDeviceSynchronize());
     PROPS_HIP_TRY(hipMemcpy(buf.data(), d->master, P * 4, hipMemcpyDeviceToHost));
@@ -1495,12 +1746,13 @@ int props_dnn_save(props_dnn_t d, const char *path)
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(PROPS_EINVAL, "props_dnn_save: cannot open %s", path);
     const char magic[8] = {'P', 'R', 'O', 'P', 'S', 'D', 'N', 'N'};
-    const uint32_t ver = 2;
+    const uint32_t ver = 3;
     const uint64_t np = P;
     const uint32_t mask = d->logmask;
+    const int32_t shape[2] = {d->nhid, d->nout};
     bool ok = std::fwrite(magic, 8, 1, f) == 1 && std::fwrite(&ver, 4, 1, f) == 1 && std::fwrite(&np, 8, 1, f) == 1 &&
               std::fwrite(&d->step, 8, 1, f) == 1 && std::fwrite(&d->epoch, 4, 1, f) == 1 &&
-              std::fwrite(&mask, 4, 1, f) == 1 &&
+              std::fwrite(&mask, 4, 1, f) == 1 && std::fwrite(shape, 4, 2, f) == 2 &&
               std::fwrite(d->in_lo, sizeof(d->in_lo), 1, f) == 1 && std::fwrite(d->in_hi, sizeof(d->in_hi), 1, f) == 1 &&
               std::fwrite(d->out_lo, sizeof(d->out_lo), 1, f) == 1 && std::fwrite(d->out_hi, sizeof(d->out_hi), 1, f) == 1 &&
               std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
@@ -1518,27 +1770,36 @@ int props_dnn_load(const char *path, props_dnn_t *out)
     char magic[8];
     uint32_t ver = 0;
     uint64_t np = 0;
-    props_dnn_t d = nullptr;
-    int rc = props_dnn_create(0, &d);
-    if (rc) {
-        std::fclose(f);
-        return rc;
-    }
-    const size_t P = kLay::total;
-    std::vector<float> buf(3 * P);
+    int64_t step = 0;
+    int32_t epoch = 0;
     uint32_t mask = kPTYLogMask;
+    int32_t shape[2] = {4, NOUT};
     bool ok = std::fread(magic, 8, 1, f) == 1 && std::memcmp(magic, "PROPSDNN", 8) == 0 && std::fread(&ver, 4, 1, f) == 1 &&
-              (ver == 1 || ver == 2) && std::fread(&np, 8, 1, f) == 1 && np == P && std::fread(&d->step, 8, 1, f) == 1 &&
-              std::fread(&d->epoch, 4, 1, f) == 1 && (ver == 1 || std::fread(&mask, 4, 1, f) == 1) &&
-              (mask >> NOUT) == 0 && std::fread(d->in_lo, sizeof(d->in_lo), 1, f) == 1 &&
-              std::fread(d->in_hi, sizeof(d->in_hi), 1, f) == 1 && std::fread(d->out_lo, sizeof(d->out_lo), 1, f) == 1 &&
-              std::fread(d->out_hi, sizeof(d->out_hi), 1, f) == 1 && std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+              (ver >= 1 && ver <= 3) && std::fread(&np, 8, 1, f) == 1 && std::fread(&step, 8, 1, f) == 1 &&
+              std::fread(&epoch, 4, 1, f) == 1 && (ver == 1 || std::fread(&mask, 4, 1, f) == 1) &&
+              (ver < 3 || std::fread(shape, 4, 2, f) == 2) && (mask >> NOUT) == 0;
+    props_dnn_t d = nullptr;
+    int rc = PROPS_OK;
+    if (ok) {
+        rc = props_dnn_create_ex(0, shape[0], shape[1], &d);
+        ok = rc == PROPS_OK && np == d->params();
+    }
+    std::vector<float> buf;
+    if (ok) {
+        buf.resize(3 * np);
+        ok = std::fread(d->in_lo, sizeof(d->in_lo), 1, f) == 1 && std::fread(d->in_hi, sizeof(d->in_hi), 1, f) == 1 &&
+             std::fread(d->out_lo, sizeof(d->out_lo), 1, f) == 1 && std::fread(d->out_hi, sizeof(d->out_hi), 1, f) == 1 &&
+             std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    }
     std::fclose(f);
     if (!ok) {
-        props_dnn_destroy(d);
-        return fail(PROPS_EINVAL, "props_dnn_load: %s is not a valid checkpoint", path);
+        if (d) props_dnn_destroy(d);
+        return fail(rc ? rc : PROPS_EINVAL, "props_dnn_load: %s is not a valid checkpoint", path);
     }
+    d->step = step;
+    d->epoch = epoch;
     d->logmask = mask;
+    const size_t P = np;
     if (hipMemcpy(d->master, buf.data(), P * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d->m, buf.data() + P, P * 4, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(d->v, buf.data() + 2 * P, P * 4, hipMemcpyHostToDevice) != hipSuccess ||

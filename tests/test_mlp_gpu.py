@@ -370,3 +370,81 @@ def test_label_generation_audited_by_oracle(props, orc, sp8):
         scale = ref["h_scale"] if k == "h" else np.abs(ref[k])
         assert np.max(np.abs(g - ref[k]) / scale) < 1e-10, k
     assert int((st != 0).sum().item()) == 0
+
+
+@pytest.mark.parametrize("hidden,outputs", [(3, 1), (3, 6), (4, 3)])
+def test_network_shapes_match_bf16_oracle(props, orc, sp8, hidden, outputs):
+    """Networks of the paper's depth (3 hidden layers) and with fewer outputs: forward on raw
+    features (props_dnn_features, several tiles, ragged) and every gradient element against
+    the bf16-emulating oracle of the same shape."""
+    import torch
+    n = 8192 + 77
+    X, L = labelled_states(orc, sp8, n, seed=51)
+    L = L[:outputs]
+    flags = omlp.LOG_OUTPUTS[:outputs]
+    mask = sum(1 << j for j, f in enumerate(flags) if f)
+    ilo, ihi, olo, ohi = omlp.fit_scalers(X.astype(np.float32).astype(np.float64).T,
+                                          L.astype(np.float32).astype(np.float64).T, flags)
+    pad = lambda v, fill: np.concatenate([v, np.full(6 - outputs, fill)])  # noqa: E731
+    params = rounded_params(omlp.init_params(np.random.default_rng(9), (10,) + (256,) * hidden + (outputs,)))
+    net = props.Network(seed=5, hidden_layers=hidden, outputs=outputs)
+    assert (net.hidden_layers, net.outputs) == (hidden, outputs)
+    net.set_log_outputs(mask)
+    set_params(net, params)
+    net.set_scalers(ilo, ihi, pad(olo, 0.0), pad(ohi, 1.0))
+    # forward on raw features
+    Y = torch.empty((outputs, n), dtype=torch.float64, device="cuda:0")
+    net.features(dev(X), Y, n)
+    torch.cuda.synchronize()
+    g = omlp.transform_outputs(Y.cpu().numpy().T, olo, ohi, flags)
+    y16, _ = omlp.forward_bf16(params, omlp.scale_inputs(X.T, ilo, ihi))
+    d = np.abs(g - y16)
+    print(f"\n[shape {hidden}x256 -> {outputs}] forward vs bf16 oracle: max {d.max():.3e} rms {np.sqrt((d ** 2).mean()):.3e}")
+    assert d.max() < FWD_MAX and np.sqrt((d ** 2).mean()) < FWD_RMS
+    # gradient
+    loss, gr = net.grad(dev(X.astype(np.float32)), dev(L.astype(np.float32)), n)
+    xs = omlp.scale_inputs(X.astype(np.float32).astype(np.float64).T, ilo, ihi)
+    t = omlp.transform_outputs(L.astype(np.float32).astype(np.float64).T, olo, ohi, flags).astype(np.float32).astype(np.float64)
+    y, cache = omlp.forward_bf16(params, xs)
+    grads, mags = omlp.backward_bf16(params, cache, y, t, magnitudes=True)
+    assert loss == pytest.approx(omlp.l1_loss(y, t), rel=1e-5)
+    off, worst = 0, 0.0
+    for (dW, db), (sW, sb, qW, qb) in zip(grads, mags):
+        o, i = dW.shape
+        gw = gr[off:off + o * i].reshape(o, i)
+        off += o * i
+        gb = gr[off:off + o]
+        off += o
+        worst = max(worst, float((np.abs(gw - dW) / (grad_bar(sW, qW) + 1e-30)).max()),
+                    float((np.abs(gb - db) / (grad_bar(sb, qb) + 1e-30)).max()))
+    assert off == gr.size
+    print(f"[shape {hidden}x256 -> {outputs}] gradient worst / bar {worst:.3f}")
+    assert worst <= 1.0
+
+
+def test_constant_training_feature_still_bounds_the_hull(props, sp8):
+    """A feature constant over the training data (here Y_N2 = 0) scales to 0 for the network,
+    but the box still holds only that value: a cell carrying some N2 is out of the hull (and
+    recomputed by the fallback), a cell without it is not."""
+    import torch
+    P, T, Y = synth.training_states(4096, seed=61)
+    Y = Y.copy()
+    Y[7] = 0.0
+    Y /= Y.sum(0, keepdims=True)
+    net = props.Network(seed=6)
+    X = np.vstack([P, T, Y])
+    lo, hi = X.min(1), X.max(1)
+    assert lo[9] == hi[9] == 0.0
+    net.set_scalers(lo, hi, np.zeros(6), np.ones(6))
+    n = 64
+    Pc, Tc, Yc = P[:n].copy(), T[:n].copy(), np.ascontiguousarray(Y[:, :n])
+    Yc[7, 1::2] = 0.01                     # N2 in every other cell
+    Yc[:, 1::2] /= Yc[:, 1::2].sum(0, keepdims=True)
+    st = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    outs = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in ("rho", "h")}
+    mech = props.Mechanism(sp8, synth.synthetic_kij(8))
+    net({"P": dev(Pc), "T": dev(Tc), "Y": dev(Yc)}, outs, n, fallback=mech, status=st)
+    torch.cuda.synchronize()
+    s = st.cpu().numpy()
+    assert np.all(s[0::2] == 0), s[0::2]
+    assert np.all(s[1::2] & 64) and np.all(s[1::2] & 128), s[1::2]
