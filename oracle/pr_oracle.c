@@ -40,6 +40,11 @@
  *
  * Everything is evaluated cell by cell in scalar double precision, with no reordering or
  * fusion beyond what the formulas state.  OpenMP parallelises over cells only (for timing).
+ *
+ * Parity unpinned: Chung's unlike-species combining rules of the pseudo-mixture and the
+ * mole-fraction-averaged dilute viscosity (pinned only by reductions: identical species,
+ * unit composition, permutation), and the dense terms of Chung's conductivity (B6 y and
+ * the B7 term).  No printed mixture value is available to pin them.
  */
 #include <math.h>
 #include <stdint.h>

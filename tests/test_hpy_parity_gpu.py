@@ -20,6 +20,8 @@ from parity_util import FIELDS, cell_kappa, compare, rel_err_stats, run_gpu
 pytestmark = pytest.mark.gpu
 
 FP64_RTOL = 1e-12
+# Mixed precision on the flame field: relative 2e-5 (measured at most 3.4e-6, mu)
+MIXED_RTOL = 2e-5
 SOLVER = ("psi", "alpha")
 ALL = FIELDS + SOLVER
 
@@ -271,7 +273,7 @@ def test_hpy_mixed_error_report(props, orc, sp8, kij8):
     stats = rel_err_stats(g, ref, fields=ALL)
     print("\n[mixed hpy] max/rms rel err: " + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in stats.items()))
     for f in ALL:
-        assert stats[f][0] <= 1e-3, (f, stats[f])
+        assert stats[f][0] <= MIXED_RTOL, (f, stats[f])
 
 
 @pytest.mark.parametrize("guess_rel", [0.3, None])

@@ -12,6 +12,12 @@ from parity_util import FIELDS, chung_kappa, compare, rel_err_stats, run_gpu
 pytestmark = pytest.mark.gpu
 
 FP64_RTOL = 1e-12
+# Mixed precision (FP32 where the policy allows): relative 2e-5 on the flame field, about 3x
+# the largest error measured there (6.7e-6, P from (rho, e)); on wide states 1e-6 times the
+# cell's condition number, since the FP32 parts round at 6e-8 relative before the same
+# cancellations the FP64 bar scales with (measured worst 0.17 of that bar, c).
+MIXED_RTOL = 2e-5
+MIXED_KAPPA_RTOL = 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -152,11 +158,13 @@ def test_mixed_precision_wide_states_poor_guess(props, orc, sp8, kij8, mode):
     g = run_gpu(props, props.Mechanism(sp8, kij8), getattr(props, mode), props.MIXED, n, inputs,
                 fields=FIELDS + ("iters",))
     assert np.array_equal(g["status"], ref["status"]), np.unique(g["status"] - ref["status"])
-    stats = rel_err_stats(g, ref, fields=[f for f in FIELDS if f not in ("mu", "lambda")])
+    fields = [f for f in FIELDS if f not in ("mu", "lambda")]
+    stats = rel_err_stats(g, ref, fields=fields)
     print(f"\n[mixed {mode.lower()} wide states] max/rms rel err: "
           + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in stats.items()), flush=True)
-    for f, (mx, _) in stats.items():
-        assert mx <= 1e-3, (f, mx)
+    worst = compare(g, ref, 1, MIXED_KAPPA_RTOL, fields=fields)
+    _report(f"mixed {mode.lower()} wide states (1e-6 x kappa)", worst)
+    assert max(worst.values()) <= 1.0, worst
     assert g["iters"].max() <= 40, np.bincount(g["iters"].astype(np.int64))
 
 
@@ -202,16 +210,14 @@ def test_mixed_precision_error_report(props, orc, sp8, kij8):
     assert np.all(g["status"] == 0), np.unique(g["status"])
     assert g["iters"].max() <= 8, np.bincount(g["iters"].astype(np.int64))
     print("\n[mixed rhoey] max/rms rel err: " + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in stats.items()))
-    for f in ("rho", "h", "cp"):
-        assert stats[f][0] <= 1e-3, (f, stats[f])
-    for f in ("T", "P", "Z", "e", "c", "mu", "lambda"):
-        assert stats[f][0] <= 1e-3, (f, stats[f])
+    for f in ("rho", "h", "cp", "T", "P", "Z", "e", "c", "mu", "lambda"):
+        assert stats[f][0] <= MIXED_RTOL, (f, stats[f])
     gp = run_gpu(props, gm, props.PTY, props.MIXED, n, {"P": P, "T": T, "Y": Y})
     refp = om.state_PT(P, T, Y)
     statsp = rel_err_stats(gp, refp)
     print("[mixed pty] max/rms rel err: " + ", ".join(f"{k}={v[0]:.2e}/{v[1]:.2e}" for k, v in statsp.items()))
     for f in ("rho", "h", "cp", "c", "mu", "lambda"):
-        assert statsp[f][0] <= 1e-3, (f, statsp[f])
+        assert statsp[f][0] <= MIXED_RTOL, (f, statsp[f])
 
 
 @pytest.mark.parametrize("mode", ["PTY", "RHOEY", "HPY"])
@@ -237,7 +243,7 @@ def test_mixed_precision_ragged_launch(props, orc, sp8, kij8, mode):
         assert np.all(g["status"] == 0), (n, np.unique(g["status"]))
         stats = rel_err_stats(g, ref)
         for f, (mx, _) in stats.items():
-            assert mx <= 1e-3, (mode, n, f, mx)
+            assert mx <= MIXED_RTOL, (mode, n, f, mx)
 
 
 # ------------------------------------------------------------------ edge cases
