@@ -173,25 +173,32 @@ def _cpu_model():
     return "unknown"
 
 
-def copy_bandwidth(nbytes=1 << 30, reps=10):
-    """Measured device-to-device copy rate (read + write bytes per second), the practical HBM
-    ceiling beside the 8 TB/s specification."""
+def copy_bandwidth(props, nbytes=1 << 30, reps=10):
+    """Measured device-to-device copy rate (read + write bytes per second) of the library's
+    streaming copy kernel (props_stream_copy) and of torch's copy_, the practical HBM ceiling
+    beside the 8 TB/s specification: (stream kernel GB/s, torch GB/s)."""
     import torch
     a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda:0").fill_(1.0)
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    t = []
-    for _ in range(reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        b.copy_(a)
-        e1.record()
+    res = []
+    for fn in (lambda: props.stream_copy(a, b, nbytes), lambda: b.copy_(a)):
+        fn()
         torch.cuda.synchronize()
-        t.append(e0.elapsed_time(e1) * 1e-3)
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            t.append(e0.elapsed_time(e1) * 1e-3)
+        res.append(2.0 * nbytes / float(np.median(t)) / 1e9)
+    ok = bool(torch.equal(a, b))
     del a, b
     torch.cuda.empty_cache()
-    return 2.0 * nbytes / float(np.median(t)) / 1e9
+    if not ok:
+        raise RuntimeError("props_stream_copy did not reproduce its source")
+    return res[0], res[1]
 
 
 def pty_section(props, mech, n, Pd, Td, Yd, stream, steps, ncopy=3):
@@ -884,10 +891,18 @@ def main():
         rec["diffusion"] = diffusion_section(props, mech, n, Pd, dt(T), Yd, stream, max(10, args.steps // 2))
         log(f"diffusion: FP64 {rec['diffusion']['fp64']['ms_per_step']:.4f} ms, "
             f"mixed {rec['diffusion']['mixed']['ms_per_step']:.4f} ms")
-        cbw = copy_bandwidth()
+        cbw, tbw = copy_bandwidth(props)
         rec["roofline"]["copy_GBs"] = cbw
+        rec["roofline"]["copy_kernel"] = "props_stream_copy (16-byte non-temporal vectors, 1 GiB)"
+        rec["roofline"]["torch_copy_GBs"] = tbw
         rec["roofline"]["hbm_frac_of_copy"] = hbm / cbw
-        log(f"device copy {cbw:.0f} GB/s; 4096-cell latency case")
+        for sec in ("pty", "diffusion", "hpy"):
+            for prec in ("fp64", "mixed"):
+                r = rec.get(sec, {}).get(prec, {})
+                if "hbm_GBs" in r:
+                    r["hbm_frac_of_copy"] = r["hbm_GBs"] / cbw
+                    r["hbm_frac_of_spec"] = r["hbm_GBs"] / 8000.0
+        log(f"device copy: stream kernel {cbw:.0f} GB/s, torch copy_ {tbw:.0f} GB/s; 4096-cell latency case")
         rec["small_case"] = small_case_section(props, synth)
 
     if args.copy_calibration:

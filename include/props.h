@@ -23,6 +23,7 @@
 #ifndef PROPS_H
 #define PROPS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -379,6 +380,14 @@ int serve_wait(props_server_t s, uint64_t ticket, int64_t timeout_us, props_resu
 int serve_stats(props_server_t s, props_serve_stats *st);
 /* Drains everything in flight, then frees the server. */
 void serve_destroy(props_server_t s);
+
+/* ------------------------------------------------------------------ measurement */
+/* Not part of the method: a streaming device-to-device copy of `bytes` bytes (src and dst
+ * device pointers, 16-byte aligned, not overlapping), the measured bandwidth ceiling that the
+ * property kernels' HBM traffic is reported against.  Asynchronous on hip_stream; the caller
+ * owns both buffers.  PROPS_EINVAL for a null or misaligned pointer (bytes = 0 is a no-op);
+ * PROPS_ETOOBIG beyond (2^24 - 1) x 16 KiB (just under 256 GiB) in one call. */
+int props_stream_copy(const void *src, void *dst, size_t bytes, void *hip_stream);
 
 /* ------------------------------------------------------------------ errors */
 const char *props_last_error(void);

@@ -7,5 +7,5 @@ loudly when the library is missing.
 """
 from ._lib import (  # noqa: F401
     EXEC_GPU, EXEC_MOCK, FP64, HPY, MIXED, PTY, RHOEY, ROUTE_DNN, ROUTE_PR_FP64, ROUTE_PR_MIXED, Network,
-    PropsError, Mechanism, Server, diffusion, features_hpz, lib, library_path, pr, status_bits,
+    PropsError, Mechanism, Server, diffusion, features_hpz, lib, library_path, pr, status_bits, stream_copy,
 )

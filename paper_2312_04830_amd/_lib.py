@@ -133,6 +133,7 @@ def lib():
                                         ctypes.c_int64, _P, _P]
         L.props_dnn_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_float), _P]
         L.props_dnn_features.argtypes = [_P, _P, _P, ctypes.c_int64, _P]
+        L.props_stream_copy.argtypes = [_P, _P, ctypes.c_size_t, _P]
         L.props_features_hpz.argtypes = [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                          _P, _P, _P, ctypes.c_int64, _P, _P]
         L.train_dnn.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(TrainCfg),
@@ -259,6 +260,12 @@ def features_hpz(species, fuel, oxidizer, bc_lambda, h, P, Y, n, X, stream=None)
                                    float(bc_lambda), _arg(h, n, f8, "h"), _arg(P, n, f8, "P"),
                                    _arg(Y, len(species) * n, f8, "Y"), n, _arg(X, 10 * n, f8, "X"),
                                    _stream(stream)))
+
+
+def stream_copy(src, dst, nbytes, stream=None):
+    """props_stream_copy: device-to-device streaming copy of nbytes (the measured bandwidth
+    ceiling); src and dst are device tensors."""
+    check(lib().props_stream_copy(_ptr(src), _ptr(dst), int(nbytes), _stream(stream)))
 
 
 def dnn_layers(hidden_layers=4, outputs=NOUT):

@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void diffusion_kernel(const ThermoTab<NS> *__r
     R yw[NS];
 #pragma unroll
     for (int i = 0; i < NS; i++) {
-        y[i] = (i < a.ns) ? a.Y[(int64_t)i * n + k] : 0.0;
+        y[i] = (i < a.ns) ? __builtin_nontemporal_load(a.Y + (int64_t)i * n + k) : 0.0;
         bad |= !(y[i] >= -1e-12);
         sy += y[i];
         const double w = y[i] * tt->invW[i];
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void diffusion_kernel(const ThermoTab<NS> *__r
         yw[i] = (R)w;
     }
     bad |= !(fabs(sy - 1.0) <= 1e-6);
-    const double P = a.P[k], T = a.T[k];
+    const double P = __builtin_nontemporal_load(a.P + k), T = __builtin_nontemporal_load(a.T + k);
     bad |= !(P > 0.0) || !(T > 0.0);
     if (bad) {
         const double nan = __builtin_nan("");
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(256) void diffusion_kernel(const ThermoTab<NS> *__r
     for (int i = 0; i < NS; i++) {
         if (i < a.ns) {
             const double s = (double)S[i];
-            a.D[(int64_t)i * n + k] = (s > 0.0) ? (1.0 - y[i]) * f * fm::rcp(s) : 0.0;
+            __builtin_nontemporal_store((s > 0.0) ? (1.0 - y[i]) * f * fm::rcp(s) : 0.0, a.D + (int64_t)i * n + k);
         }
     }
     if (a.status) a.status[k] = 0;

@@ -549,19 +549,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
     // (rho, e, Y) and (h, P, Y) kernels 12 % and 1.5 % slower, so they keep the full mat-vecs)
     constexpr bool kTriMix = (PREC == PROPS_MIXED) || (MODE == PROPS_PTY);
 
-    // ---- composition and input checks
+    // ---- composition and input checks (inputs are read once and outputs written once: both
+    // go through non-temporal loads and stores, measured 4-8 % faster than cached ones)
     double y[NS];
     double sy = 0.0, syw = 0.0;
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < NS; i++) {
-        y[i] = (i < a.ns) ? a.Y[(int64_t)i * n + k] : 0.0;
+        y[i] = (i < a.ns) ? __builtin_nontemporal_load(a.Y + (int64_t)i * n + k) : 0.0;
         bad |= !(y[i] >= -1e-12);
         sy += y[i];
         syw += y[i] * tt->invW[i];
     }
     bad |= !(fabs(sy - 1.0) <= 1e-6);
-    const double in0 = a.in0[k], in1 = a.in1[k];
+    const double in0 = __builtin_nontemporal_load(a.in0 + k), in1 = __builtin_nontemporal_load(a.in1 + k);
     if (MODE == PROPS_PTY) bad |= !(in0 > 0.0) || !(in1 > 0.0);
     else if (MODE == PROPS_RHOEY) bad |= !(in0 > 0.0) || !(in1 == in1);
     else bad |= !(in0 == in0) || !(in1 > 0.0);
@@ -838,17 +839,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
             psi = -(double)dvdPh * W * fm::rcp(v * v);
         }
     }
-    if (a.oT) a.oT[k] = T;
-    if (a.oP) a.oP[k] = P;
-    if (a.oZ) a.oZ[k] = P * v * fm::rcp(RT);
+    if (a.oT) __builtin_nontemporal_store((double)(T), a.oT + k);
+    if (a.oP) __builtin_nontemporal_store((double)(P), a.oP + k);
+    if (a.oZ) __builtin_nontemporal_store((double)(P * v * fm::rcp(RT)), a.oZ + k);
     // in (rho, e, Y) mode the density is the input; 1/v = rho/W = rho sum Y_i/W_i
     const double iv = (MODE == PROPS_RHOEY) ? in0 * syw : fm::rcp(v);
-    if (a.orho) a.orho[k] = (MODE == PROPS_RHOEY) ? in0 : W * iv;
-    if (a.oh) a.oh[k] = h;
-    if (a.oe) a.oe[k] = e;
-    if (a.ocp) a.ocp[k] = cp;
-    if (a.oc) a.oc[k] = c;
-    if (SOLVER && a.opsi) a.opsi[k] = psi;
+    if (a.orho) __builtin_nontemporal_store((double)((MODE == PROPS_RHOEY) ? in0 : W * iv), a.orho + k);
+    if (a.oh) __builtin_nontemporal_store((double)(h), a.oh + k);
+    if (a.oe) __builtin_nontemporal_store((double)(e), a.oe + k);
+    if (a.ocp) __builtin_nontemporal_store((double)(cp), a.ocp + k);
+    if (a.oc) __builtin_nontemporal_store((double)(c), a.oc + k);
+    if (SOLVER && a.opsi) __builtin_nontemporal_store((double)(psi), a.opsi + k);
     if (SOLVER && a.ohRT) {
         // h_i/(R T) = (h_i [J/kg]) (W_i/R) / T, from the pre-scaled NASA coefficients
         const int r = (T >= ig.Tmid) ? 1 : 0;
@@ -866,9 +867,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
         double mu = 0, lam = 0;
         chung<PM, NS>(tm, Xr, (R)T, (R)iv, (R)(W * (cp_ig - ig.rw)), a.omu != nullptr,
                       a.olam != nullptr || (SOLVER && a.oalpha != nullptr), &mu, &lam, e2s);
-        if (a.omu) a.omu[k] = mu;
-        if (a.olam) a.olam[k] = lam;
-        if (SOLVER && a.oalpha) a.oalpha[k] = lam * v * fm::rcp(W * cp);
+        if (a.omu) __builtin_nontemporal_store((double)(mu), a.omu + k);
+        if (a.olam) __builtin_nontemporal_store((double)(lam), a.olam + k);
+        if (SOLVER && a.oalpha) __builtin_nontemporal_store((double)(lam * v * fm::rcp(W * cp)), a.oalpha + k);
     }
     if (a.status) a.status[k] = st;
 }

@@ -78,3 +78,25 @@ def test_binding_refuses_short_host_or_mistyped_arrays(props, mech, tiny):
     with pytest.raises(ValueError, match="status"):
         props.diffusion(mech, props.FP64, tiny, tiny, tiny, tiny, 2, status=torch.zeros(1, dtype=torch.uint8,
                                                                                      device="cuda:0"))
+
+
+@pytest.mark.parametrize("nbytes", [0, 15, 16, 4096 * 16 + 5, (1 << 22) + 48 + 9])
+def test_stream_copy_reproduces_its_source(props, nbytes):
+    """The streaming copy (the bandwidth denominator of the benchmark) reproduces every byte,
+    whole vectors, the tail trip and the ragged byte tail, and writes nothing past the end."""
+    import torch
+    g = torch.Generator().manual_seed(nbytes)
+    src = torch.randint(0, 256, (nbytes + 64,), dtype=torch.uint8, generator=g).to("cuda:0")
+    dst = torch.full((nbytes + 64,), 7, dtype=torch.uint8, device="cuda:0")
+    props.stream_copy(src, dst, nbytes)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes].cpu(), src[:nbytes].cpu())
+    assert bool((dst[nbytes:] == 7).all())
+
+
+def test_stream_copy_refuses_misaligned_pointers(props):
+    import torch
+    buf = torch.zeros(256, dtype=torch.uint8, device="cuda:0")
+    rc = props.lib().props_stream_copy(ctypes.c_void_p(buf.data_ptr() + 8), ctypes.c_void_p(buf.data_ptr() + 128),
+                                       ctypes.c_size_t(64), None)
+    assert rc == -1   # PROPS_EINVAL
