@@ -906,10 +906,12 @@ def main():
         rec["small_case"] = small_case_section(props, synth)
 
     if args.copy_calibration:
+        # three launches of the library's streaming copy over 1 GiB: the plain copy of known
+        # size against which the FETCH_SIZE / WRITE_SIZE counters are scaled
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         dst = torch.empty_like(src)
         for _ in range(3):
-            dst.copy_(src)
+            props.stream_copy(src, dst, src.numel() * 8)
         torch.cuda.synchronize()
         rec["copy_calibration_bytes"] = 2 * src.numel() * 8
         del src, dst
