@@ -50,7 +50,7 @@ class _Mech(ctypes.Structure):
 CELL_DTYPE = np.dtype([(n, "f8") for n in (
     "T", "P", "Z", "rho", "v", "W", "h", "e", "cp", "cv", "c", "mu", "lambda",
     "am", "dam", "d2am", "bm", "A", "B", "h_ig", "e_ig", "cp_ig", "cv_ig",
-    "h_scale", "e_scale", "kappa_Z", "kappa_cp", "kappa_T", "psi", "alpha")] +
+    "h_scale", "e_scale", "kappa_Z", "kappa_cp", "kappa_T", "psi", "alpha", "mu_scale", "lambda_scale")] +
     [("hRT", "f8", (MAXNS,)), ("roots", "f8", (3,)), ("nroots", "i4"), ("nphys", "i4"), ("status", "i4"), ("iters", "i4")])
 
 _lib = None

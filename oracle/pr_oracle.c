@@ -94,6 +94,7 @@ typedef struct {
     double h_scale, e_scale;          /* sums of magnitudes, for relative comparisons */
     double kappa_Z, kappa_cp, kappa_T; /* condition numbers, for tolerance scaling */
     double psi, alpha;                /* (d rho/d P)_h [s^2/m^2]; lambda/(rho c_p) [m^2/s] */
+    double mu_scale, lambda_scale;    /* sums of the magnitudes of the terms of mu and lambda */
     double hRT[ORC_MAXNS];            /* h_i/(R T) of each species (ideal-gas standard state) */
     double roots[3];
     int32_t nroots, nphys;
@@ -368,7 +369,8 @@ double orc_chung_mu0(double T, double Tc, double Vc_cm3, double M, double omega,
  * parameters, at T, molar density rho [mol/m^3], with ideal-gas molar Cv [J/(mol K)] and
  * low-pressure viscosity eta0 [Pa s]. */
 double orc_chung_lambda_eta0(double eta0, double T, double rho, double Tc, double Vc_cm3,
-                             double M, double omega, double mu_r, double kappa, double Cv)
+                             double M, double omega, double mu_r, double kappa, double Cv,
+                             double *scale)
 {
     double mr4 = mu_r * mu_r * mu_r * mu_r;
     double Bc[7];
@@ -384,7 +386,10 @@ double orc_chung_lambda_eta0(double eta0, double T, double rho, double Tc, doubl
     double y = rho * 1e-6 * Vc_cm3 / 6.0;
     double G2 = orc_chung_G2(y, Bc);
     double q = 3.586e-3 * sqrt(Tc / Mkg) / pow(Vc_cm3, 2.0 / 3.0);
-    return 31.2 * eta0 * psi / Mkg * (1.0 / G2 + Bc[5] * y) + q * Bc[6] * y * y * sqrt(Tr) * G2;
+    double a = 31.2 * eta0 * psi / Mkg;
+    double dense = q * Bc[6] * y * y * sqrt(Tr) * G2;
+    if (scale) *scale = fabs(a / G2) + fabs(a * Bc[5] * y) + fabs(dense);
+    return a * (1.0 / G2 + Bc[5] * y) + dense;
 }
 
 /* The same with the fluid's own Chung low-pressure viscosity (the textbook form). */
@@ -392,7 +397,7 @@ double orc_chung_lambda(double T, double rho, double Tc, double Vc_cm3, double M
                         double omega, double mu_r, double kappa, double Cv)
 {
     double eta0 = orc_chung_mu0(T, Tc, Vc_cm3, M, omega, mu_r, kappa);
-    return orc_chung_lambda_eta0(eta0, T, rho, Tc, Vc_cm3, M, omega, mu_r, kappa, Cv);
+    return orc_chung_lambda_eta0(eta0, T, rho, Tc, Vc_cm3, M, omega, mu_r, kappa, Cv, NULL);
 }
 
 /* Chung dense-fluid viscosity [Pa s] built on a given low-pressure viscosity eta0:
@@ -400,7 +405,7 @@ double orc_chung_lambda(double T, double rho, double Tc, double Vc_cm3, double M
  * + eta**] with its dilute factor 36.344 sqrt(M Tc) sqrt(T*) Fc/(Vc^(2/3) Omega_v)
  * replaced by eta0. */
 double orc_chung_mu_eta0(double eta0, double T, double rho, double Tc, double Vc_cm3,
-                         double M, double omega, double mu_r, double kappa)
+                         double M, double omega, double mu_r, double kappa, double *scale)
 {
     double mr4 = mu_r * mu_r * mu_r * mu_r;
     double E[10];
@@ -410,7 +415,9 @@ double orc_chung_mu_eta0(double eta0, double T, double rho, double Tc, double Vc
     double y = rho * 1e-6 * Vc_cm3 / 6.0;
     double G2 = orc_chung_G2(y, E);
     double muss = E[6] * y * y * G2 * exp(E[7] + E[8] / Ts + E[9] / (Ts * Ts));
-    return eta0 * (1.0 / G2 + E[5] * y) + 36.344 * muss * sqrt(M * Tc) / pow(Vc_cm3, 2.0 / 3.0) * 1e-7;
+    double dense = 36.344 * muss * sqrt(M * Tc) / pow(Vc_cm3, 2.0 / 3.0) * 1e-7;
+    if (scale) *scale = fabs(eta0 / G2) + fabs(eta0 * E[5] * y) + fabs(dense);
+    return eta0 * (1.0 / G2 + E[5] * y) + dense;
 }
 
 /* Mixture transport at T and molar density rho with mole fractions X (paper, Section 2:
@@ -420,7 +427,7 @@ double orc_chung_mu_eta0(double eta0, double T, double rho, double Tc, double Vc
  * the low-pressure viscosity entering both mu and lambda is the mole-fraction average of
  * the species' own low-pressure Chung viscosities. */
 void orc_transport(const orc_mech *m, const double *X, double T, double rho, double Cv,
-                   double *mu, double *lam)
+                   double *mu, double *lam, double *mu_scale, double *lam_scale)
 {
     int n = m->ns;
     double eta0 = 0;
@@ -461,8 +468,8 @@ void orc_transport(const orc_mech *m, const double *X, double T, double rho, dou
     double Vcm = pow(sm / 0.809, 3);
     double Tcm = 1.2593 * em;
     double murm = 131.3 * mum / sqrt(Vcm * Tcm);
-    *mu = orc_chung_mu_eta0(eta0, T, rho, Tcm, Vcm, Mm, wm, murm, km);
-    *lam = orc_chung_lambda_eta0(eta0, T, rho, Tcm, Vcm, Mm, wm, murm, km, Cv);
+    *mu = orc_chung_mu_eta0(eta0, T, rho, Tcm, Vcm, Mm, wm, murm, km, mu_scale);
+    *lam = orc_chung_lambda_eta0(eta0, T, rho, Tcm, Vcm, Mm, wm, murm, km, Cv, lam_scale);
 }
 
 /* ----------------------------------------------------------------------------------- */
@@ -555,7 +562,7 @@ static void orc_fill_nan(orc_cell *c)
     double nan = NAN;
     c->T = c->P = c->Z = c->rho = c->v = nan;
     c->h = c->e = c->cp = c->cv = c->c = c->mu = c->lambda = nan;
-    c->psi = c->alpha = nan;
+    c->psi = c->alpha = c->mu_scale = c->lambda_scale = nan;
     for (int i = 0; i < ORC_MAXNS; i++) c->hRT[i] = nan;
 }
 
@@ -622,10 +629,10 @@ static void orc_props_vT(const orc_mech *m, const double *Y, const double *X, do
     c->psi = -(W / (v * v)) * dvdP_h;
     for (int i = 0; i < ORC_MAXNS; i++) c->hRT[i] = (i < m->ns) ? orc_nasa_h_RT(&m->sp[i], T) : 0.0;
     if (want_transport) {
-        orc_transport(m, X, T, 1.0 / v, W * cvig, &c->mu, &c->lambda);
+        orc_transport(m, X, T, 1.0 / v, W * cvig, &c->mu, &c->lambda, &c->mu_scale, &c->lambda_scale);
         c->alpha = c->lambda / (c->rho * c->cp);
     } else {
-        c->mu = c->lambda = c->alpha = NAN;
+        c->mu = c->lambda = c->alpha = c->mu_scale = c->lambda_scale = NAN;
     }
 }
 

@@ -48,17 +48,20 @@ def cell_kappa(ref, mode):
     return k
 
 
-def compare(gpu, ref, mode, rtol, fields=FIELDS, mask=None, kappa=True, extra=None):
+def compare(gpu, ref, mode, rtol, fields=FIELDS, mask=None, kappa=True, extra=None, scales=None):
     """Return {field: worst err/tol}; h and e are compared against their sums of
-    magnitudes (they cross zero), everything else relative to itself.  extra: optional
-    {field: per-cell factor} multiplying that field's condition number."""
+    magnitudes (they cross zero), everything else relative to itself unless `scales` gives
+    a per-cell magnitude for it.  extra: optional {field: per-cell factor} multiplying that
+    field's condition number."""
     k0 = cell_kappa(ref, mode) if kappa else np.ones(len(ref))
     worst = {}
     for f in fields:
         k = k0 * extra[f] if extra and f in extra else k0
         g = gpu[f]
         r = ref["lambda"] if f == "lambda" else ref[f]
-        if f == "h":
+        if scales and f in scales:
+            scale = scales[f]
+        elif f == "h":
             scale = ref["h_scale"]
         elif f == "e":
             scale = ref["e_scale"]

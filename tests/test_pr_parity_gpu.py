@@ -112,11 +112,7 @@ def test_rhoey_fp64_wide_states_poor_guess(props, orc, sp8, kij8, guess_rel):
     8-species compositions, started from a poor guess (30 % spread, clipped into the bracket
     by the kernel where it falls outside) or from the top of the bracket: the iteration's
     bisection fallbacks and third-order steps meet the oracle's plain Newton at every cell.
-    The thermodynamic outputs are compared; transport is not: at such arbitrary compositions
-    and densities Chung's dense-fluid viscosity cancels (and turns negative for ~1 % of the
-    cells), so the two sides agree only to that cancellation's rounding, which the
-    thermodynamic condition number of the tolerance does not cover.  Transport parity is
-    tested on the flame field's compositions."""
+    The thermodynamic outputs are compared here, transport in the test below."""
     rng = np.random.default_rng(77)
     n = 2048
     P = rng.uniform(1.0e6, 30.0e6, n)
@@ -134,6 +130,38 @@ def test_rhoey_fp64_wide_states_poor_guess(props, orc, sp8, kij8, guess_rel):
     _report(f"rhoey fp64 wide states guess={guess_rel}", worst)
     assert max(worst.values()) <= 1.0, worst
     assert g["iters"].max() <= 40, np.bincount(g["iters"].astype(np.int64))
+
+
+def test_rhoey_fp64_wide_states_transport(props, orc, sp8, kij8):
+    """Chung's mu and lambda on the wide states above.  At such arbitrary compositions and
+    densities the dense-fluid terms can cancel against the dilute ones (mu turns negative on
+    about 1 % of the cells, R30), and for mixtures rich in H2 the G2 denominator nears zero
+    (R31), so each cell's bar is 1e-12 relative to the sum of the magnitudes of the output's
+    terms (the oracle's mu_scale, lambda_scale), times the thermodynamic condition number
+    (T and rho enter the correlation) and the G2 denominator's (chung_kappa)."""
+    rng = np.random.default_rng(77)
+    n = 2048
+    P = rng.uniform(1.0e6, 30.0e6, n)
+    T = rng.uniform(100.0, 4800.0, n)
+    Y = rng.uniform(0.0, 1.0, (8, n))
+    Y /= Y.sum(axis=0)
+    om = orc.Mech(sp8, kij8)
+    st = om.state_PT(P, T, Y, transport=False)
+    ref = om.state_rhoe(st["rho"], st["e"], Y)
+    Tg = synth.temperature_guess(T, seed=78, rel=0.3)
+    g = run_gpu(props, props.Mechanism(sp8, kij8), props.RHOEY, props.FP64, n,
+                {"rho": st["rho"], "e": st["e"], "Y": Y, "T_guess": Tg})
+    assert np.array_equal(g["status"], ref["status"])
+    kmu, klam = chung_kappa(sp8, Y)
+    ok = ref["status"] == 0
+    print(f"\n[wide transport] mu < 0 on {int((ref['mu'][ok] < 0).sum())} of {int(ok.sum())} cells; "
+          f"max cancellation {np.nanmax(ref['mu_scale'][ok] / np.abs(ref['mu'][ok])):.3g} (mu), "
+          f"{np.nanmax(ref['lambda_scale'][ok] / np.abs(ref['lambda'][ok])):.3g} (lambda); max G2 kappa "
+          f"{kmu.max():.3g} / {klam.max():.3g}", flush=True)
+    worst = compare(g, ref, 1, FP64_RTOL, fields=("mu", "lambda"), mask=ok, extra={"mu": kmu, "lambda": klam},
+                    scales={"mu": ref["mu_scale"], "lambda": ref["lambda_scale"]})
+    _report("rhoey fp64 wide states transport", worst)
+    assert max(worst.values()) <= 1.0, worst
 
 
 @pytest.mark.parametrize("mode", ["RHOEY", "HPY"])
