@@ -89,10 +89,25 @@ __host__ __device__ inline size_t w_off(int l)
 }
 __host__ __device__ inline size_t b_off(int l, int nh) { return w_off(l) + (size_t)lout(l, nh) * lin(l); }
 __host__ __device__ inline size_t total_params(int nh) { return w_off(nh) + (size_t)OUT_PAD * HID + OUT_PAD; }
-__host__ __device__ inline size_t nat_off(int l) { return l == 0 ? 0 : (size_t)HID * IN_PAD + (size_t)(l - 1) * HID * HID; }
-__host__ __device__ inline size_t nat_total(int nh) { return nat_off(nh) + (size_t)OUT_PAD * HID; }
 __host__ __device__ inline size_t f_off(int l) { return l == 0 ? 0 : (size_t)HID * IROW + (size_t)(l - 1) * HID * HROW; }
 __host__ __device__ inline size_t f_total(int nh) { return f_off(nh) + (size_t)FOUT_ROWS * HROW; }
+// Backward-data layout: the transposed weights of layers 1..nh, rows = the layer's inputs
+// (256 hidden features), K = the layer's outputs.  Hidden layers l = 1..nh-1 take the
+// accumulator permutation on K (their dz arrives in registers) and rows of HROW; the output
+// layer (K = 16, dz read from memory in natural order) takes rows of IROW, after them.
+__host__ __device__ inline size_t bf_off(int l, int nh) { return l < nh ? (size_t)(l - 1) * HID * HROW : (size_t)(nh - 1) * HID * HROW; }
+__host__ __device__ inline size_t bf_total(int nh) { return (size_t)(nh - 1) * HID * HROW + (size_t)HID * IROW; }
+// Layout of the saved hidden-layer arrays (z, h, and dz written over z; logically
+// [n][256]): the four features 32 ob + 8 q + 4 hh + (0..3) of a cell sit next to those of the
+// other lanes of the same wave that hold them, 64 lanes x 8 bytes = 512 bytes per (32-cell
+// group, block ob, q), in lane order (hh, cell % 32).  Every save by the forward and every
+// reload by the backward (the same lane mapping) is then one coalesced 512-byte access, and
+// cells 2c, 2c + 1 of a group with the same four features are 16 contiguous bytes, which the
+// weight-gradient loader turns into (k even, k odd) pairs.
+__host__ __device__ inline int64_t tm_idx(int64_t cell, int f)
+{
+    return ((((cell >> 5) * 8 + (f >> 5)) * 4 + ((f >> 3) & 3)) * 64 + ((f >> 2) & 1) * 32 + (cell & 31)) * 4 + (f & 3);
+}
 // true (unpadded) shapes
 __host__ __device__ inline int tout(int l, int nh, int nout) { return l == nh ? nout : HID; }
 __host__ __device__ inline int tin(int l) { return l == 0 ? NIN : HID; }
@@ -309,13 +324,13 @@ __device__ __forceinline__ bf16x8 ring_step(Ring &r, bf16x8 incoming)
 }
 
 // Training saves of one 32-feature block of a hidden layer: bf16 pre-activations z into zl and
-// the packed bf16 activations p (8 pairs) into hl, in natural feature order [cell][256].
+// the packed bf16 activations p (8 pairs) into hl, in the saved-array layout (tm_idx).
 __device__ __forceinline__ void save_block(bf16_t *zl, bf16_t *hl, int64_t cell, int ob, int h, const f32x16 &z,
                                            const unsigned *p)
 {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        const int64_t off = cell * HID + 32 * ob + 8 * q + 4 * h;
+        const int64_t off = tm_idx(cell, 32 * ob + 8 * q + 4 * h);
         *reinterpret_cast<uint2 *>(zl + off) =
             make_uint2(pack_bf16x2(z[4 * q], z[4 * q + 1]), pack_bf16x2(z[4 * q + 2], z[4 * q + 3]));
         *reinterpret_cast<uint2 *>(hl + off) = make_uint2(p[2 * q], p[2 * q + 1]);
@@ -702,103 +717,237 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_fwd_kernel(FwdArgs a)
     __builtin_amdgcn_s_waitcnt(0);   // no weight load still in flight when the workgroup ends
 }
 
-// ------------------------------------------------------------------ input-gradient GEMM
-// C[m][n] = bf16( (sum_k A[m][k] B[n][k]) gelu'(Z[m][n]) ): dz_{l-1} = (dz_l W_l) * GELU'(z_{l-1})
-// with A = dz_l (rows = batch, K = the layer's padded outputs, 256 or 16), B = W_l transposed
-// ([256 inputs][K]), both contiguous along K, and Z the bf16 pre-activations [M][256].  Tiles of
-// 128 rows x all 256 columns (so each row of dz is read once) per 256-thread workgroup: 2 x 2
-// waves of 64 x 128, i.e. 2 x 4 accumulator blocks of v_mfma_f32_32x32x16_bf16; K in steps of
-// 32 staged in LDS (rows padded by 16 bytes, so the 32 lanes of a fragment read hit distinct
-// banks), double-buffered: the next step's global loads are in flight during this step's MFMAs.
-template <int K>
-__global__ __launch_bounds__(256, 2) void gemm_dh_kernel(const bf16_t *__restrict__ A, const bf16_t *__restrict__ B,
-                                                      const bf16_t *__restrict__ Z, bf16_t *__restrict__ C, int M)
+// ------------------------------------------------------------------ fused backward (data)
+// dz of every hidden layer for a 256-cell tile in one pass, output layer to input:
+//   dz_{nh-1} = (W_out^T dz_out) o GELU'(z_{nh-1}),  dz_{t-1} = (W_t^T dz_t) o GELU'(z_{t-1}),
+// with the same layout tricks as the forward: cells are the N side of the MFMA (32 per wave),
+// the transposed weights (rows = the layer's inputs, K = its outputs in the accumulator
+// permutation) stream through the ring of three LDS slot pairs, and each dz stays in
+// registers as the next layer's B operand.  Each dz_t is written over z_t (the lane that
+// reads a z value is the one that writes its dz, two blocks later), where the weight-gradient
+// GEMMs read it.  W_out^T (K = 16) sits in its own LDS region after the ring.
+struct BwdArgs {
+    const bf16_t *Wb;      // backward-data weights (bf_off layout)
+    const bf16_t *dzo;     // [n][16] d loss / d output
+    bf16_t *zs;            // hidden layer t's z at zs + t lstride, overwritten by its dz
+    int64_t lstride;
+    int64_t n;
+    int nhid;
+};
+constexpr int BWD_WOUT = NRING * 2 * SLOT_BYTES;          // byte offset of W_out^T in LDS
+constexpr int BWD_LDS_BYTES = BWD_WOUT + HID * IROW * 2;  // 113,664 B
+
+// weights of block k of the per-tile backward sequence: hidden layer l = nh - 1 - k / 8,
+// 32-row block k % 8 of its transpose
+__device__ __forceinline__ void bwd_stage_pair(unsigned char *lds, const BwdArgs &a, int rp, int p)
 {
-    constexpr int KS = K < 32 ? K : 32;       // k per step
-    constexpr int NST = K / KS;
-    constexpr int LDR = KS + 8;               // bf16 per padded LDS row
-    constexpr int CPR = KS / 8;               // 16-byte chunks per row and step
-    constexpr int CA = 128 * CPR, CB = 256 * CPR;
-    constexpr int PA = (CA + 255) / 256, PB = (CB + 255) / 256;
-    __shared__ __attribute__((aligned(16))) bf16_t As[2][128][LDR];
-    __shared__ __attribute__((aligned(16))) bf16_t Bs[2][256][LDR];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w >> 1, wn = w & 1;
-    const int h = lane >> 5, col = lane & 31;
-    const int m0 = blockIdx.x * 128;
-    uint4 ra[PA], rb[PB];
-    auto load = [&](int k0) {
+    const bf16_t *wb = a.Wb;
+    asm volatile("" : "+s"(wb));
+    const int nh = a.nhid;
 #pragma unroll
-        for (int p = 0; p < PA; p++) {
-            const int q = t + 256 * p;
-            const int r = q / CPR, c8 = q % CPR;
-            ra[p] = make_uint4(0, 0, 0, 0);
-            if (q < CA && m0 + r < M) ra[p] = *reinterpret_cast<const uint4 *>(A + (int64_t)(m0 + r) * K + k0 + 8 * c8);
-        }
-#pragma unroll
-        for (int p = 0; p < PB; p++) {
-            const int q = t + 256 * p;
-            const int r = q / CPR, c8 = q % CPR;
-            rb[p] = make_uint4(0, 0, 0, 0);
-            if (q < CB) rb[p] = *reinterpret_cast<const uint4 *>(B + (int64_t)r * K + k0 + 8 * c8);
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int p = 0; p < PA; p++) {
-            const int q = t + 256 * p;
-            if (q < CA) *reinterpret_cast<uint4 *>(&As[buf][q / CPR][8 * (q % CPR)]) = ra[p];
-        }
-#pragma unroll
-        for (int p = 0; p < PB; p++) {
-            const int q = t + 256 * p;
-            if (q < CB) *reinterpret_cast<uint4 *>(&Bs[buf][q / CPR][8 * (q % CPR)]) = rb[p];
-        }
-    };
-    f32x16 acc[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = f32x16{};
-    load(0);
-    store(0);
-    __syncthreads();
-#pragma unroll 1
-    for (int st = 0; st < NST; st++) {
-        const int buf = st & 1;
-        if (st + 1 < NST) load((st + 1) * KS);
-#pragma unroll
-        for (int kb = 0; kb < KS / 16; kb++) {
-            bf16x8 af[2], bfr[4];
-#pragma unroll
-            for (int i = 0; i < 2; i++)
-                af[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][wm * 64 + i * 32 + col][kb * 16 + 8 * h]);
-#pragma unroll
-            for (int j = 0; j < 4; j++)
-                bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][wn * 128 + j * 32 + col][kb * 16 + 8 * h]);
-#pragma unroll
-            for (int i = 0; i < 2; i++)
-#pragma unroll
-                for (int j = 0; j < 4; j++) acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
-        }
-        if (st + 1 < NST) store(buf ^ 1);
-        __syncthreads();
+    for (int j = 0; j < 2; j++) {
+        const int k = 2 * p + j;
+        const int l = nh - 1 - k / 8, ob = k % 8;
+        stage_async(lds + (2 * rp + j) * SLOT_BYTES, wb + bf_off(l, nh) + (size_t)ob * 32 * HROW, SLOT_BYTES);
     }
-    // C layout of the 32 x 32 blocks: column = lane % 32 (n), rows 8q + 4h + (0..3) (m)
+}
+
+__device__ __forceinline__ void bwd_pair_top(unsigned char *lds, const BwdArgs &a, int rp, int pn, bool stage)
+{
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (stage) bwd_stage_pair(lds, a, rp == 0 ? NRING - 1 : rp - 1, pn);
+}
+
+// The 16 z values of one block of hidden layer t for this lane (rows 32 ob + 8q + 4h + r),
+// four 8-byte loads from the saved-array layout (tm_idx), and the matching dz store
+struct ZBlk {
+    uint2 q[4];
+};
+__device__ __forceinline__ void load_zblk(const bf16_t *zl, int64_t cell, int ob, int h, ZBlk &z)
+{
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int q = 0; q < 4; q++) z.q[q] = *reinterpret_cast<const uint2 *>(zl + tm_idx(cell, 32 * ob + 8 * q + 4 * h));
+}
+__device__ __forceinline__ float zval(const ZBlk &z, int v)
+{
+    const uint2 w = z.q[v >> 2];
+    const unsigned u = ((v & 3) < 2) ? w.x : w.y;
+    return (v & 1) ? __builtin_bit_cast(float, u & 0xffff0000u) : __builtin_bit_cast(float, u << 16);
+}
+__device__ __forceinline__ void store_dzblk(bf16_t *zl, int64_t cell, int ob, int h, const unsigned (&pg)[8])
+{
 #pragma unroll
-        for (int v = 0; v < 16; v++) {
-            const int m = m0 + wm * 64 + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-            if (m < M) {
+    for (int q = 0; q < 4; q++)
+        *reinterpret_cast<uint2 *>(zl + tm_idx(cell, 32 * ob + 8 * q + 4 * h)) = make_uint2(pg[2 * q], pg[2 * q + 1]);
+}
+
+// One 32-row block of a hidden layer's transpose (16 K blocks, no bias) at `cur`, with the
+// pending block's dz = dh o GELU'(z) formed one value per step into pg (the forward's
+// interleave, with GELU' in place of GELU).  FIRST: the pending block is the previous
+// layer's last one (act[14], act[15]): its 16 values are done by step 13 (two at steps 0
+// and 1) and act[14], act[15] are filled before steps 14 and 15, which read them.  The
+// stream continues into the block at `nx`.
+template <bool FIRST>
+__device__ __forceinline__ f32x16 bwd_block(const unsigned char *lds, BlkAddr cur, BlkAddr nx, Ring &ring,
+                                            bf16x8 (&act)[16], const f32x16 &pz, const ZBlk &zp, unsigned (&pg)[8])
+{
+    constexpr int NS = 16;
+    f32x16 acc = {};
+    float gv[16];
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const int n = wn * 128 + j * 32 + col;
-                    const float d = acc[i][j][v] * gelu_grad_f(bf16_to_f(Z[(int64_t)m * HID + n]));
-                    C[(int64_t)m * HID + n] = to_bf16(d);
+    for (int s = 0; s < NS; s++) {
+        if (FIRST && s == 14) {
+            act[14] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
+            act[15] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
+        }
+        const int u = s + FPF;
+        const bf16x8 af = ring_step(ring, u < NS ? lds_at(lds, cur.k, u * 32) : lds_at(lds, nx.k, (u - NS) * 32));
+        acc = (s == 0) ? mfma32(af, act[0], f32x16{}) : mfma32(af, act[s], acc);
+        // FIRST: two values at steps 0 and 1, one at steps 2..13 (all 16 before step 14)
+        const int v0 = FIRST ? (s < 2 ? 2 * s : s + 2) : s;
+        const int nv = FIRST ? (s < 2 ? 2 : (s < 14 ? 1 : 0)) : 1;
+#pragma unroll
+        for (int w = 0; w < nv; w++) {
+            const int v = v0 + w;
+            gv[v] = pz[v] * gelu_grad_f(zval(zp, v));
+            if (v & 1) pg[v >> 1] = pack_bf16x2(gv[v - 1], gv[v]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    return acc;
+}
+
+__device__ __forceinline__ void dz_epilogue(const f32x16 &pz, const ZBlk &zp, unsigned (&pg)[8])
+{
+#pragma unroll
+    for (int q = 0; q < 8; q++)
+        pg[q] = pack_bf16x2(pz[2 * q] * gelu_grad_f(zval(zp, 2 * q)), pz[2 * q + 1] * gelu_grad_f(zval(zp, 2 * q + 1)));
+}
+
+__global__ __launch_bounds__(FWD_THREADS, 1) void mlp_bwd_kernel(BwdArgs a)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int h = lane >> 5;
+    const int col = lane & 31;
+    const int nh = a.nhid;
+    const int PT = 4 * (nh - 1);            // pairs per tile: 8 (nh - 1) hidden blocks
+    const int64_t ntiles = (a.n + TILE_CELLS - 1) / TILE_CELLS;
+    if ((int64_t)blockIdx.x >= ntiles) return;
+    constexpr unsigned PAIR = 2 * SLOT_BYTES;
+    const auto next_rp = [](int r) { return r == NRING - 1 ? 0 : r + 1; };
+
+    // prologue: W_out^T into its region, the first two pairs into ring pairs 0 and 1
+    {
+        const bf16_t *wb = a.Wb;
+        asm volatile("" : "+s"(wb));
+        stage_async(lds + BWD_WOUT, wb + bf_off(nh, nh), HID * IROW * 2);
+    }
+    bwd_stage_pair(lds, a, 0, 0);
+    bwd_stage_pair(lds, a, 1, 1);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    int rp = 2;                              // the ring pair before the first hidden pair
+    Ring ring;
+    {
+        const BlkAddr b0 = hid_addr(0, col, h);
+#pragma unroll
+        for (int d = 0; d < FPF; d++) ring.f[d] = lds_at(lds, b0.k, d * 32);
+    }
+
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const bool more = tile + gridDim.x < ntiles;
+        const int64_t cell = tile * TILE_CELLS + wave * CELLS_PER_WAVE + col;
+        const bool live = cell < a.n;
+        const int64_t cl = live ? cell : 0;  // dead lanes read cell 0 and write nothing
+        bf16x8 act[16];
+        bf16x8 nxt[14];
+        f32x16 pz;
+        // The tile's blocks j = 8 (nh - 1 - t) + ob run from hidden layer t = nh - 1 (the
+        // output step) down to t = 0.  z of block j is loaded two blocks ahead, into a
+        // three-deep shift register: zq[0] the pending block's, zq[1] the current one's,
+        // zq[2] the next one's.
+        const auto zrow = [&](int t) { return a.zs + t * a.lstride; };
+        ZBlk zq[3];
+        const auto zshift = [&](int t2, int ob2) {   // after a block: turn, then load block (t2, ob2)
+            zq[0] = zq[1];
+            zq[1] = zq[2];
+            if (t2 >= 0) load_zblk(zrow(t2), cl, ob2, h, zq[2]);
+        };
+        load_zblk(zrow(nh - 1), cl, 0, h, zq[1]);
+        load_zblk(zrow(nh - 1), cl, 1, h, zq[2]);
+        // ---- output layer: dh_{nh-1} = W_out^T dz_out, eight 32-row blocks of one MFMA each;
+        // the dz of block ob - 1 is formed beside block ob
+        const bf16x8 dzb = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(a.dzo + cl * OUT_PAD + 8 * h));
+        {
+            const unsigned wl = l0_addr((unsigned)BWD_WOUT, col, h).k;   // row 32 ob + col, K slot 8h
+#pragma unroll
+            for (int ob = 0; ob < 8; ob++) {
+                const bf16x8 af = lds_at(lds, wl, ob * 32 * IROW * 2);
+                const f32x16 z = mfma32(af, dzb, f32x16{});
+                if (ob > 0) {
+                    unsigned pg[8];
+                    dz_epilogue(pz, zq[0], pg);
+                    act[2 * ob - 2] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
+                    act[2 * ob - 1] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
+                    if (live) store_dzblk(zrow(nh - 1), cl, ob - 1, h, pg);
                 }
+                pz = z;
+                // block j + 2 = ob + 2: still the output step's, or layer nh - 2's first two
+                if (ob + 2 < 8) zshift(nh - 1, ob + 2);
+                else zshift(nh - 2, ob - 6);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
+
+        // ---- hidden layers l = nh - 1 .. 1 (weights W_l): dh_{l-1} = W_l^T dz_l, then
+        // dz_{l-1} = dh o GELU'(z_{l-1}); ring sequence block k = 8 (nh - 1 - l) + ob, even
+        // ob open a pair
+#pragma unroll 1
+        for (int l = nh - 1; l >= 1; l--) {
+            const int t = l - 1;             // the hidden layer whose dz this pass forms
+#pragma unroll
+            for (int ob = 0; ob < 8; ob++) {
+                const int kseq = 8 * (nh - 1 - l) + ob;
+                if (!(ob & 1)) {
+                    rp = next_rp(rp);
+                    const int pn = kseq / 2 + 2;
+                    bwd_pair_top(lds, a, rp, pn < PT ? pn : pn - PT, pn < PT || more);
+                }
+                const unsigned base = rp * PAIR;
+                const BlkAddr cur = hid_addr((ob & 1) ? base + SLOT_BYTES : base, col, h);
+                const BlkAddr nx = hid_addr((ob & 1) ? next_rp(rp) * PAIR : base + SLOT_BYTES, col, h);
+                unsigned pg[8];
+                f32x16 acc;
+                if (ob == 0) {
+                    // pending: the last block of layer t + 1
+                    acc = bwd_block<true>(lds, cur, nx, ring, act, pz, zq[0], pg);
+                    if (live) store_dzblk(zrow(t + 1), cl, 7, h, pg);
+                } else {
+                    acc = bwd_block<false>(lds, cur, nx, ring, act, pz, zq[0], pg);
+                    nxt[2 * ob - 2] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
+                    nxt[2 * ob - 1] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
+                    if (live) store_dzblk(zrow(t), cl, ob - 1, h, pg);
+                }
+                pz = acc;
+                if (ob + 2 < 8) zshift(t, ob + 2);
+                else zshift(t - 1, ob - 6);     // none past layer 0 (t - 1 < 0)
+            }
+#pragma unroll
+            for (int kb = 0; kb < 14; kb++) act[kb] = nxt[kb];
+        }
+        // ---- the tile's last block (layer 0, block 7): its dz has no MFMA beside it
+        {
+            unsigned pg[8];
+            dz_epilogue(pz, zq[0], pg);
+            if (live) store_dzblk(zrow(0), cl, 7, h, pg);
+        }
+        // the next tile's first hidden pair is the next ring pair; its fragments were
+        // prefetched by this tile's last hidden block
+    }
+    __builtin_amdgcn_s_waitcnt(0);
 }
 
 // ------------------------------------------------------------------ training helpers
@@ -834,11 +983,11 @@ __global__ void adam_kernel(float *w, const float *gr, float *m, float *v, int64
     w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
 }
 
-// FP32 master -> bf16 transposed [in][out] (the B operand of dz W, contiguous along its K
-// = out) and fused (row-padded, k-permuted) layouts; each fused row also receives its bias
+// FP32 master -> bf16 in the backward-data layout (rows = inputs, K slots = outputs) and the
+// fused forward layout (row-padded, k-permuted); each fused row also receives its bias
 // as three bf16 parts hi + mid + lo (exact: each part takes the next 8 bits of the FP32
 // significand), in the slots after the inputs.
-__global__ void convert_weights_kernel(const float *master, bf16_t *nat, bf16_t *fused, int nh)
+__global__ void convert_weights_kernel(const float *master, bf16_t *fused, bf16_t *bwd, int nh)
 {
     const int l = blockIdx.y;
     const int rows = lout(l, nh), cols = lin(l), rowlen = lrow(l);
@@ -847,7 +996,11 @@ __global__ void convert_weights_kernel(const float *master, bf16_t *nat, bf16_t 
         const int o = (int)(e / cols), i = (int)(e % cols);
         const float wv = master[w_off(l) + e];
         const bf16_t b = to_bf16(wv);
-        nat[nat_off(l) + (int64_t)i * rows + o] = b;   // transposed: [in][out]
+        if (l >= 1) {
+            // backward-data layout: row i, K slot of output o
+            const int brow = (l == nh) ? IROW : HROW;
+            bwd[bf_off(l, nh) + (int64_t)i * brow + ((l == nh) ? o : kslot(o))] = b;
+        }
         // layer 0 keeps the natural input order in its one 16-deep K block (inputs >= 16
         // are padding); later layers take the permutation of the accumulator layout
         if (l == 0 && i >= FK0) continue;
@@ -946,14 +1099,23 @@ __device__ __forceinline__ void kw_interleave(uint4 x, uint4 y, uint4 &lo, uint4
     hi = make_uint4(d[4], d[5], d[6], d[7]);
 }
 
-template <int TM, int TN, int WAVES_M>
+// (cells 2kp, 2kp + 1) x four features, as one 16-byte load from the saved-array layout
+// (tm_idx): {c f0 f1, c f2 f3, c+1 f0 f1, c+1 f2 f3} -> the four (c, c+1) pairs
+__device__ __forceinline__ uint4 kw_interleave4(uint4 x)
+{
+    return make_uint4((x.x & 0xffffu) | (x.z << 16), (x.x >> 16) | (x.z & 0xffff0000u), (x.y & 0xffffu) | (x.w << 16),
+                      (x.y >> 16) | (x.w & 0xffff0000u));
+}
+
+// AT / BT: the operand is in the saved-array layout (tm_idx, width 256) rather than
+// row-major [K][ld].
+template <int TM, int TN, int WAVES_M, bool AT, bool BT>
 __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int lda, int M, const bf16_t *B, int ldb,
                                                           int N, int K, int kchunk, float *C, int ldc, int64_t strideC,
                                                           float *Cb)
 {
     constexpr int WAVES_N = 4 / WAVES_M;
     constexpr int BM = TM / WAVES_M / 32, BN = TN / WAVES_N / 32;
-    constexpr int CA = TM / 8, CB = TN / 8;   // 16-byte column chunks per k row
     __shared__ __attribute__((aligned(16))) unsigned As[2][16][TM + KW_PAD];
     __shared__ __attribute__((aligned(16))) unsigned Bs[2][16][TN + KW_PAD];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -962,15 +1124,28 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
     const int kbeg = blockIdx.z * kchunk;
     const int kend = min(K, kbeg + kchunk);
-    // loader work items: (pair row kp, 16-byte column chunk) for A then B
+    // loader work items of one 32-deep K step, A then B: a row-major operand has 16 pair rows
+    // x width/8 column chunks (two 16-byte row loads each, eight pairs); a saved-array operand
+    // 16 pair rows x width/4 feature quads (one 16-byte load each, four pairs)
+    constexpr int CA = AT ? TM / 4 : TM / 8, CB = BT ? TN / 4 : TN / 8;
     constexpr int NA = 16 * CA, NB = 16 * CB;
     constexpr int PER = (NA + NB + 255) / 256;
-    auto item = [&](int q, bool &isA, int &kp, int &c8) {
+    // A saved-array operand's piece (kp, cc) is the (16 cc + kp)-th 16 bytes of a contiguous
+    // run; each wave takes 64 pieces (1 KB) of it, four cc by sixteen kp, and its lanes are
+    // ordered so that eight (and sixteen) neighbouring lanes write LDS rows kp, columns 4cc
+    // on distinct banks: lane 16 g + e takes kp = 8 (g & 1) + e / 2, cc = 4 G + 2 (g >> 1) + e % 2.
+    auto item = [&](int q, bool &isA, int &kp, int &cc) {
         isA = q < NA;
         const int qq = isA ? q : q - NA;
-        const int cc = isA ? CA : CB;
-        kp = qq / cc;
-        c8 = qq % cc;
+        const int cw = isA ? CA : CB;
+        if (isA ? AT : BT) {
+            const int G = qq >> 6, l = qq & 63, e = l & 15, g = l >> 4;
+            kp = 8 * (g & 1) + (e >> 1);
+            cc = 4 * G + 2 * (g >> 1) + (e & 1);
+        } else {
+            kp = qq / cw;
+            cc = qq % cw;
+        }
     };
     auto load = [&](int k0, uint4 (&rx)[PER][2]) {
 #pragma unroll
@@ -979,33 +1154,53 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
             rx[p][0] = rx[p][1] = make_uint4(0, 0, 0, 0);
             if (q < NA + NB) {
                 bool isA;
-                int kp, c8;
-                item(q, isA, kp, c8);
-                const int col = (isA ? m0 : n0) + 8 * c8;
+                int kp, cc;
+                item(q, isA, kp, cc);
+                const bool tm = isA ? AT : BT;
                 const int lim = isA ? M : N;
                 const bf16_t *src = isA ? A : B;
-                const int ld = isA ? lda : ldb;
+                const int k = k0 + 2 * kp;
+                if (tm) {
+                    // the tile's 32 cells x width features are one contiguous run of the saved
+                    // layout from tm_idx(k0, first feature); item (kp, cc) is its 16 * cc + kp-th
+                    // 16-byte piece (cells 2kp, 2kp + 1, features 4cc .. 4cc + 3)
+                    const int f = (isA ? m0 : n0) + 4 * cc;
+                    if (k < kend && f < lim) {
+                        const bf16_t *run = src + tm_idx(k0, isA ? m0 : n0);
+                        rx[p][0] = *reinterpret_cast<const uint4 *>(run + 8 * (16 * cc + kp));
+                    }
+                } else {
+                    const int col = (isA ? m0 : n0) + 8 * cc;
+                    const int ld = isA ? lda : ldb;
 #pragma unroll
-                for (int e = 0; e < 2; e++) {
-                    const int k = k0 + 2 * kp + e;
-                    if (k < kend && col < lim) rx[p][e] = *reinterpret_cast<const uint4 *>(src + (int64_t)k * ld + col);
+                    for (int e = 0; e < 2; e++)
+                        if (k + e < kend && col < lim) rx[p][e] = *reinterpret_cast<const uint4 *>(src + (int64_t)(k + e) * ld + col);
                 }
             }
         }
     };
-    auto store = [&](int buf, const uint4 (&rx)[PER][2]) {
+    // the ragged end's odd cell (past n) is cleared here rather than at the load, so that no
+    // load has to complete before the next one is issued
+    auto store = [&](int buf, int k0, const uint4 (&rx)[PER][2]) {
 #pragma unroll
         for (int p = 0; p < PER; p++) {
             const int q = t + 256 * p;
             if (q < NA + NB) {
                 bool isA;
-                int kp, c8;
-                item(q, isA, kp, c8);
-                uint4 lo, hi;
-                kw_interleave(rx[p][0], rx[p][1], lo, hi);
-                unsigned *dst = isA ? &As[buf][kp][8 * c8] : &Bs[buf][kp][8 * c8];
-                *reinterpret_cast<uint4 *>(dst) = lo;
-                *reinterpret_cast<uint4 *>(dst + 4) = hi;
+                int kp, cc;
+                item(q, isA, kp, cc);
+                if (isA ? AT : BT) {
+                    uint4 v = rx[p][0];
+                    if (k0 + 2 * kp + 1 >= kend) v.z = v.w = 0u;
+                    unsigned *dst = isA ? &As[buf][kp][4 * cc] : &Bs[buf][kp][4 * cc];
+                    *reinterpret_cast<uint4 *>(dst) = kw_interleave4(v);
+                } else {
+                    uint4 lo, hi;
+                    kw_interleave(rx[p][0], rx[p][1], lo, hi);
+                    unsigned *dst = isA ? &As[buf][kp][8 * cc] : &Bs[buf][kp][8 * cc];
+                    *reinterpret_cast<uint4 *>(dst) = lo;
+                    *reinterpret_cast<uint4 *>(dst + 4) = hi;
+                }
             }
         }
     };
@@ -1019,7 +1214,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
     int buf = 0;
     if (kbeg < kend) {
         load(kbeg, rx);
-        store(0, rx);
+        store(0, kbeg, rx);
     }
     __syncthreads();
     for (int k0 = kbeg; k0 < kend; k0 += 32) {
@@ -1058,7 +1253,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
                 csum += __builtin_bit_cast(float, v & 0xffff0000u);
             }
         }
-        if (more) store(buf ^ 1, rx);
+        if (more) store(buf ^ 1, k0 + 32, rx);
         __syncthreads();
         buf ^= 1;
     }
@@ -1088,14 +1283,14 @@ struct props_dnn_s {
     int device = 0;
     int nhid = 4, nout = NOUT;
     float *master = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;   // device FP32
-    bf16_t *nat = nullptr, *fused = nullptr;
+    bf16_t *fused = nullptr, *bwd = nullptr;
     double *scal = nullptr;        // device: in_lo[10], in_inv[10], out_lo[6], out_rng[6], out_inv[6]
     double in_lo[NIN], in_hi[NIN], out_lo[NOUT], out_hi[NOUT];
     unsigned logmask = kPTYLogMask;   // outputs trained on their logarithm
     int64_t step = 0;
     int epoch = 0;
     // forward/backward scratch for one batch
-    bf16_t *h0 = nullptr, *zs[MAX_HIDDEN] = {}, *hs[MAX_HIDDEN] = {}, *dz = nullptr, *dz2 = nullptr, *dzo = nullptr;
+    bf16_t *h0 = nullptr, *zs[MAX_HIDDEN] = {}, *hs[MAX_HIDDEN] = {}, *dzo = nullptr;
     float *part = nullptr, *lpart = nullptr;
     int *fb_idx = nullptr, *fb_count = nullptr;
     int64_t fb_cap = 0;
@@ -1124,8 +1319,8 @@ static int upload_scalers(props_dnn_s *d)
 
 static int refresh_weights(props_dnn_s *d, hipStream_t s)
 {
-    hipLaunchKernelGGL(convert_weights_kernel, dim3(64, d->nhid + 1), dim3(256), 0, s, d->master, d->nat, d->fused,
-                       d->nhid);
+    hipLaunchKernelGGL(convert_weights_kernel, dim3(64, d->nhid + 1), dim3(256), 0, s, d->master, d->fused,
+                       d->bwd, d->nhid);
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
 }
@@ -1140,7 +1335,7 @@ static int dalloc(T **p, size_t count)
 
 static void free_dnn(props_dnn_s *d)
 {
-    void *ps[] = {d->master, d->grad, d->m, d->v, d->nat, d->fused, d->scal, d->h0, d->dz, d->dz2, d->dzo,
+    void *ps[] = {d->master, d->grad, d->m, d->v, d->fused, d->bwd, d->scal, d->h0, d->dzo,
                   d->part, d->lpart, d->fb_idx, d->fb_count};
     for (void *p : ps)
         if (p) (void)hipFree(p);
@@ -1154,14 +1349,16 @@ static int alloc_dnn(props_dnn_s *d)
     int rc;
     const size_t P = d->params();
     if ((rc = dalloc(&d->master, P)) || (rc = dalloc(&d->grad, P)) || (rc = dalloc(&d->m, P)) ||
-        (rc = dalloc(&d->v, P)) || (rc = dalloc(&d->nat, nat_total(d->nhid))) ||
-        (rc = dalloc(&d->fused, f_total(d->nhid))) || (rc = dalloc(&d->scal, (size_t)NIN * 2 + NOUT * 3)) ||
+        (rc = dalloc(&d->v, P)) ||
+        (rc = dalloc(&d->fused, f_total(d->nhid))) || (rc = dalloc(&d->bwd, bf_total(d->nhid))) ||
+        (rc = dalloc(&d->scal, (size_t)NIN * 2 + NOUT * 3)) ||
         (rc = dalloc(&d->fb_count, 1)))
         return rc;
     PROPS_HIP_TRY(hipMemset(d->grad, 0, P * sizeof(float)));
     PROPS_HIP_TRY(hipMemset(d->m, 0, P * sizeof(float)));
     PROPS_HIP_TRY(hipMemset(d->v, 0, P * sizeof(float)));
     PROPS_HIP_TRY(hipMemset(d->fused, 0, f_total(d->nhid) * sizeof(bf16_t)));
+    PROPS_HIP_TRY(hipMemset(d->bwd, 0, bf_total(d->nhid) * sizeof(bf16_t)));
     return PROPS_OK;
 }
 
@@ -1170,7 +1367,7 @@ static int ensure_train_scratch(props_dnn_s *d)
     if (d->h0) return PROPS_OK;
     int rc;
     const size_t B = MAX_BATCH;
-    if ((rc = dalloc(&d->h0, B * IN_PAD)) || (rc = dalloc(&d->dz, B * HID)) || (rc = dalloc(&d->dz2, B * HID)) ||
+    if ((rc = dalloc(&d->h0, B * IN_PAD)) ||
         (rc = dalloc(&d->dzo, B * OUT_PAD)) ||
         (rc = dalloc(&d->part, (size_t)SPLITW * (HID * HID + HID))) ||
         (rc = dalloc(&d->lpart, (size_t)B / CELLS_PER_WAVE + 64)))
@@ -1193,6 +1390,21 @@ static int fwd_grid(int64_t n)
     }
     const int64_t tiles = (n + TILE_CELLS - 1) / TILE_CELLS;
     return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, (int64_t)cus));
+}
+
+static std::once_flag g_bwd_lds_once;
+static hipError_t g_bwd_lds_err = hipSuccess;
+static int launch_bwd(const BwdArgs &b, hipStream_t s)
+{
+    std::call_once(g_bwd_lds_once, [] {
+        g_bwd_lds_err = hipFuncSetAttribute((const void *)mlp_bwd_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                            BWD_LDS_BYTES);
+    });
+    if (g_bwd_lds_err != hipSuccess)
+        return fail(PROPS_EHIP, "hipFuncSetAttribute(LDS %d B): %s", BWD_LDS_BYTES, hipGetErrorString(g_bwd_lds_err));
+    hipLaunchKernelGGL(mlp_bwd_kernel, dim3(fwd_grid(b.n)), dim3(FWD_THREADS), BWD_LDS_BYTES, s, b);
+    PROPS_HIP_TRY(hipGetLastError());
+    return PROPS_OK;
 }
 
 static std::once_flag g_lds_once;
@@ -1222,14 +1434,16 @@ static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float 
     splits = (n + kchunk - 1) / kchunk;
     const int64_t stride = (int64_t)O * I + O;
     float *pb = part + (int64_t)O * I;
+    // hidden layers: both operands in the saved-array layout; layer 0: dz saved, the inputs
+    // row-major [n][32]; output layer: dz row-major [n][16], h saved
     if (O % 128 == 0 && I % 128 == 0) {
-        hipLaunchKernelGGL((gemm_wgrad_kernel<128, 128, 2>), dim3(I / 128, O / 128, splits), dim3(256), 0, s,
+        hipLaunchKernelGGL((gemm_wgrad_kernel<128, 128, 2, true, true>), dim3(I / 128, O / 128, splits), dim3(256), 0, s,
                            dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
     } else if (O % 128 == 0 && I == 32) {
-        hipLaunchKernelGGL((gemm_wgrad_kernel<128, 32, 4>), dim3(1, O / 128, splits), dim3(256), 0, s,
+        hipLaunchKernelGGL((gemm_wgrad_kernel<128, 32, 4, true, false>), dim3(1, O / 128, splits), dim3(256), 0, s,
                            dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
     } else if (O <= 32 && O % 8 == 0 && I % 128 == 0) {
-        hipLaunchKernelGGL((gemm_wgrad_kernel<32, 128, 1>), dim3(I / 128, 1, splits), dim3(256), 0, s,
+        hipLaunchKernelGGL((gemm_wgrad_kernel<32, 128, 1, false, true>), dim3(I / 128, 1, splits), dim3(256), 0, s,
                            dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
     } else {
         return fail(PROPS_EINVAL, "wgrad: unsupported layer shape %d x %d", O, I);
@@ -1268,31 +1482,27 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
     a.dzo = d->dzo;
     a.lpart = d->lpart;
     if ((rc = launch_fwd(true, a, s))) return rc;
-    // layer by layer, output to input
-    const bf16_t *dzl = d->dzo;
+    // dz of every hidden layer in one fused pass, written over the saved z
+    BwdArgs bw{};
+    bw.Wb = d->bwd;
+    bw.dzo = d->dzo;
+    bw.zs = d->zs[0];
+    bw.lstride = (int64_t)MAX_BATCH * HID;
+    bw.n = n;
+    bw.nhid = nh;
+    if ((rc = launch_bwd(bw, s))) return rc;
+    // weight and bias gradients, output layer to input: dW_l = dz_l^T h_{l-1}, db_l = sum dz_l
+    // (M = O, N = I, K = n), split over the batch
     for (int l = nh; l >= 0; l--) {
         const int O = lout(l, nh), I = lin(l);
+        const bf16_t *dzl = (l == nh) ? d->dzo : d->zs[l];
         const bf16_t *hprev = (l == 0) ? d->h0 : d->hs[l - 1];
-        // dW = dz^T h and db = sum dz  (M = O, N = I, K = n), split over the batch
         int splits = 0;
         if ((rc = wgrad(dzl, O, hprev, I, n, d->part, splits, s))) return rc;
         const int64_t cnt = (int64_t)O * I + O;
         hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
                            d->part, splits, cnt, cnt, d->grad + w_off(l));
         PROPS_HIP_TRY(hipGetLastError());
-        if (l > 0) {
-            // dz_{l-1} = (dz W) * gelu'(z_{l-1})  (M = n, N = 256, K = O)
-            bf16_t *out = (dzl == d->dz) ? d->dz2 : d->dz;
-            const unsigned blocks = (unsigned)((n + 127) / 128);
-            if (O == HID)
-                hipLaunchKernelGGL(gemm_dh_kernel<HID>, dim3(blocks), dim3(256), 0, s, dzl, d->nat + nat_off(l),
-                                   d->zs[l - 1], out, n);
-            else
-                hipLaunchKernelGGL(gemm_dh_kernel<OUT_PAD>, dim3(blocks), dim3(256), 0, s, dzl, d->nat + nat_off(l),
-                                   d->zs[l - 1], out, n);
-            PROPS_HIP_TRY(hipGetLastError());
-            dzl = out;
-        }
     }
     return PROPS_OK;
 }
