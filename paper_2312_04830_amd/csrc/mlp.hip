@@ -47,6 +47,7 @@ namespace props {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned short bf16_t;  // storage type of a bfloat16
 
 constexpr int NIN = PROPS_DNN_IN, NOUT = PROPS_DNN_OUT, HID = PROPS_DNN_HIDDEN;
@@ -67,8 +68,12 @@ constexpr int LDS_BYTES = NRING * 2 * SLOT_BYTES;         // 101,376 B per workg
 constexpr int L0_BYTES = HID * IROW * 2;                  // layer 0 whole: 12,288 B, one slot
 static_assert(L0_BYTES <= SLOT_BYTES, "layer 0 fits one slot");
 constexpr int MAX_BATCH = 65536;
-constexpr int SPLITW = 128;    // batch splits of the weight-gradient GEMMs (32: 89M, 64: 106M,
-                               // 128: 115M, 256: 108M training samples/s)
+// batch splits of the weight-gradient GEMMs (multiples of 8).  Each workgroup walks its
+// split's K range one 32-cell step at a time with one step in flight, so the time follows the
+// split length: on a 65,536 batch 32 / 64 / 128 splits of the 256 x 256 layers take 85 / 52
+// / 36 us, and 128 / 256 splits of the input layer 27 / 21 us.
+constexpr int SPLIT_HID = 128;
+constexpr int SPLIT_IO = 256;
 // LDS fragment prefetch distance of the A-fragment stream, in matrix-core steps
 constexpr int FPF = 3;
 // Outputs of the (P, T, Y) surrogate trained on their logarithm: rho, cp, mu, lambda
@@ -89,6 +94,15 @@ __host__ __device__ inline size_t w_off(int l)
 }
 __host__ __device__ inline size_t b_off(int l, int nh) { return w_off(l) + (size_t)lout(l, nh) * lin(l); }
 __host__ __device__ inline size_t total_params(int nh) { return w_off(nh) + (size_t)OUT_PAD * HID + OUT_PAD; }
+static_assert((IN_PAD * HID + HID) % 2 == 0 && (HID * HID + HID) % 2 == 0 && (OUT_PAD * HID + OUT_PAD) % 2 == 0,
+              "layer parameter counts are even (the step kernel takes parameters in pairs)");
+// split-K partials of one step, every layer side by side (W then b of each split, as in the
+// master)
+inline size_t part_floats(int nh)
+{
+    return (size_t)SPLIT_IO * ((size_t)HID * IN_PAD + HID + (size_t)OUT_PAD * HID + OUT_PAD) +
+           (size_t)(nh - 1) * SPLIT_HID * ((size_t)HID * HID + HID);
+}
 __host__ __device__ inline size_t f_off(int l) { return l == 0 ? 0 : (size_t)HID * IROW + (size_t)(l - 1) * HID * HROW; }
 __host__ __device__ inline size_t f_total(int nh) { return f_off(nh) + (size_t)FOUT_ROWS * HROW; }
 // Backward-data layout: the transposed weights of layers 1..nh, rows = the layer's inputs
@@ -951,73 +965,113 @@ __global__ __launch_bounds__(FWD_THREADS, 1) void mlp_bwd_kernel(BwdArgs a)
 }
 
 // ------------------------------------------------------------------ training helpers
-// out[i] = sum_s part[s * stride + i] in order s = 0..S-1 (deterministic split-K reduction),
-// with the result written to dst[i] (gradient of a weight matrix and its bias).
-__global__ void reduce_partials_kernel(const float *part, int S, int64_t stride, int64_t count, float *dst)
+// Where each layer's split-K partials sit: layer l's split z holds its W and b (in master
+// order) at part[l] + z * (off[l + 1] - off[l]); off[l] = w_off(l).
+struct GradParts {
+    int64_t off[MAX_HIDDEN + 2];
+    const float *part[MAX_HIDDEN + 1];
+    int splits[MAX_HIDDEN + 1];
+    int nl;
+};
+
+// bf16 copies of one master weight (element i of layer l, rows x cols) in the forward's fused
+// layout and, after layer 0, the backward-data layout
+__device__ __forceinline__ void put_weight(bf16_t *fused, bf16_t *bwd, int l, int nh, int64_t i, float wv)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    float s = 0.f;
-    int k = 0;
-    for (; k + 8 <= S; k += 8) {   // eight partials in flight, summed in order
-        float v[8];
-#pragma unroll
-        for (int j = 0; j < 8; j++) v[j] = part[(k + j) * stride + i];
-#pragma unroll
-        for (int j = 0; j < 8; j++) s += v[j];
+    const int cols = lin(l), rowlen = lrow(l);
+    const int o = (int)(i / cols), c = (int)(i % cols);
+    const bf16_t b = to_bf16(wv);
+    if (l >= 1) {
+        // backward-data layout: row c, K slot of output o
+        const int brow = (l == nh) ? IROW : HROW;
+        bwd[bf_off(l, nh) + (int64_t)c * brow + ((l == nh) ? o : kslot(o))] = b;
     }
-    for (; k < S; k++) s += part[k * stride + i];
-    dst[i] = s;
+    // layer 0 keeps the natural input order in its one 16-deep K block (inputs >= 16 are
+    // padding); later layers take the permutation of the accumulator layout
+    if (l == 0 && c >= FK0) return;
+    fused[f_off(l) + (int64_t)o * rowlen + ((l == 0) ? c : kslot(c))] = b;
 }
 
-__global__ void adam_kernel(float *w, const float *gr, float *m, float *v, int64_t n, float lr,
-                            float b1, float b2, float eps, float bc1, float bc2)
+// a bias in the fused layout: three bf16 parts hi + mid + lo after the row's inputs (exact:
+// each part takes the next 8 bits of the FP32 significand)
+__device__ __forceinline__ void put_bias(bf16_t *fused, int l, int o, float bv)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = gr[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    const bf16_t hi = to_bf16(bv);
+    const float r1 = bv - bf16_to_f(hi);
+    const bf16_t mid = to_bf16(r1);
+    const bf16_t lo = to_bf16(r1 - bf16_to_f(mid));
+    bf16_t *dst = fused + f_off(l) + (int64_t)o * lrow(l) + (l == 0 ? FK0 : HID);
+    dst[0] = hi;
+    dst[1] = mid;
+    dst[2] = lo;
 }
 
-// FP32 master -> bf16 in the backward-data layout (rows = inputs, K slots = outputs) and the
-// fused forward layout (row-padded, k-permuted); each fused row also receives its bias
-// as three bf16 parts hi + mid + lo (exact: each part takes the next 8 bits of the FP32
-// significand), in the slots after the inputs.
+// One thread per pair of master parameters e, e + 1 (layer sizes and offsets are even): the
+// gradient g = sum_z part_z[e] over the splits in order z = 0, 1, ... (a deterministic
+// split-K reduction).  Without Adam, g is written to grad.  With Adam: the moments and the
+// FP32 master take the step
+//   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,  w -= lr (m / bc1) / (sqrt(v / bc2) + eps)
+// (bc1, bc2: the bias corrections 1 - b^t), and the new weight goes straight to its bf16 copies.
+__global__ __launch_bounds__(256) void grad_step_kernel(GradParts L, int nh, float *grad, float *w, float *m,
+                                                        float *v, bf16_t *fused, bf16_t *bwd, int adam, float lr,
+                                                        float b1, float b2, float eps, float bc1, float bc2)
+{
+    const int64_t e0 = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (e0 >= L.off[L.nl]) return;
+    int l = 0;
+    while (l + 1 < L.nl && e0 >= L.off[l + 1]) l++;
+    const int64_t i0 = e0 - L.off[l], cnt = L.off[l + 1] - L.off[l];
+    const f32x2 *src = reinterpret_cast<const f32x2 *>(L.part[l] + i0);
+    const int64_t zs = cnt / 2;
+    const int S = L.splits[l];
+    float g[2] = {0.f, 0.f};
+    int z = 0;
+    for (; z + 16 <= S; z += 16) {   // sixteen partials in flight, summed in order
+        f32x2 pv[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) pv[j] = __builtin_nontemporal_load(src + (z + j) * zs);
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            g[0] += pv[j].x;
+            g[1] += pv[j].y;
+        }
+    }
+    for (; z < S; z++) {
+        const f32x2 pv = src[z * zs];
+        g[0] += pv.x;
+        g[1] += pv.y;
+    }
+    if (!adam) {
+        grad[e0] = g[0];
+        grad[e0 + 1] = g[1];
+        return;
+    }
+    const int64_t nwt = (int64_t)lout(l, nh) * lin(l);
+#pragma unroll
+    for (int u = 0; u < 2; u++) {
+        const int64_t e = e0 + u, i = i0 + u;
+        const float mi = b1 * m[e] + (1.f - b1) * g[u];
+        const float vi = b2 * v[e] + (1.f - b2) * g[u] * g[u];
+        m[e] = mi;
+        v[e] = vi;
+        const float wn = w[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        w[e] = wn;
+        if (i < nwt) put_weight(fused, bwd, l, nh, i, wn);
+        else put_bias(fused, l, (int)(i - nwt), wn);
+    }
+}
+
+// FP32 master -> its bf16 copies (the forward's fused layout with the biases, the
+// backward-data layout), all layers
 __global__ void convert_weights_kernel(const float *master, bf16_t *fused, bf16_t *bwd, int nh)
 {
     const int l = blockIdx.y;
-    const int rows = lout(l, nh), cols = lin(l), rowlen = lrow(l);
-    const int64_t cnt = (int64_t)rows * cols;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x) {
-        const int o = (int)(e / cols), i = (int)(e % cols);
-        const float wv = master[w_off(l) + e];
-        const bf16_t b = to_bf16(wv);
-        if (l >= 1) {
-            // backward-data layout: row i, K slot of output o
-            const int brow = (l == nh) ? IROW : HROW;
-            bwd[bf_off(l, nh) + (int64_t)i * brow + ((l == nh) ? o : kslot(o))] = b;
-        }
-        // layer 0 keeps the natural input order in its one 16-deep K block (inputs >= 16
-        // are padding); later layers take the permutation of the accumulator layout
-        if (l == 0 && i >= FK0) continue;
-        const int slot = (l == 0) ? i : kslot(i);
-        fused[f_off(l) + (int64_t)o * rowlen + slot] = b;
-    }
-    for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < rows; o += gridDim.x * blockDim.x) {
-        const float bv = master[b_off(l, nh) + o];
-        const bf16_t hi = to_bf16(bv);
-        const float r1 = bv - bf16_to_f(hi);
-        const bf16_t mid = to_bf16(r1);
-        const bf16_t lo = to_bf16(r1 - bf16_to_f(mid));
-        bf16_t *dst = fused + f_off(l) + (int64_t)o * rowlen + (l == 0 ? FK0 : HID);
-        dst[0] = hi;
-        dst[1] = mid;
-        dst[2] = lo;
-    }
+    const int rows = lout(l, nh);
+    const int64_t cnt = (int64_t)rows * lin(l);
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += (int64_t)gridDim.x * blockDim.x)
+        put_weight(fused, bwd, l, nh, e, master[w_off(l) + e]);
+    for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < rows; o += gridDim.x * blockDim.x)
+        put_bias(fused, l, o, master[b_off(l, nh) + o]);
 }
 
 __global__ void fill_int_kernel(int *p, int v) { *p = v; }
@@ -1077,8 +1131,7 @@ namespace props {
 // are staged in LDS as bf16 pairs (k even, k odd) per column: a thread reads two k rows of
 // eight columns (two 16-byte loads), interleaves them and stores eight pair-dwords; a
 // fragment is then four 4-byte LDS reads.  Rows of 136 dwords put the two lane halves of a
-// fragment read 32 banks apart.  Double-buffered: the next step's global loads are in
-// flight during the current step's MFMAs, one barrier per step.
+// fragment read 32 banks apart.  Double-buffered in LDS, one barrier per step.
 // A tile of TM x TN outputs per workgroup of 4 waves arranged WAVES_M x (4 / WAVES_M), each
 // wave BM x BN blocks of 32 x 32.  Columns at or beyond M (N) read as zero and are not
 // written, so the 16-row output layer runs on a 32-row tile.  The workgroups of the first
@@ -1109,21 +1162,33 @@ __device__ __forceinline__ uint4 kw_interleave4(uint4 x)
 
 // AT / BT: the operand is in the saved-array layout (tm_idx, width 256) rather than
 // row-major [K][ld].
+//
+// One-dimensional grid of tiles_x * tiles_y * splits workgroups (splits a multiple of 8).
+// Consecutive workgroups are dealt to the eight XCDs in turn, so workgroup b runs on XCD
+// b % 8; the mapping gives every XCD whole batch splits (all tiles of split z on XCD z % 8),
+// so the tiles that share an operand run side by side and read it through one L2.
 template <int TM, int TN, int WAVES_M, bool AT, bool BT>
 __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int lda, int M, const bf16_t *B, int ldb,
-                                                          int N, int K, int kchunk, float *C, int ldc, int64_t strideC,
-                                                          float *Cb)
+                                                          int N, int K, int kchunk, int tiles_x, int tiles_y,
+                                                          float *C, int ldc, int64_t strideC, float *Cb)
 {
     constexpr int WAVES_N = 4 / WAVES_M;
     constexpr int BM = TM / WAVES_M / 32, BN = TN / WAVES_N / 32;
+    static_assert(BM >= 1 && BN >= 1, "each wave holds at least one 32 x 32 block");
     __shared__ __attribute__((aligned(16))) unsigned As[2][16][TM + KW_PAD];
     __shared__ __attribute__((aligned(16))) unsigned Bs[2][16][TN + KW_PAD];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w / WAVES_N, wn = w % WAVES_N;
     const int h = lane >> 5, r = lane & 31;
-    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
-    const int kbeg = blockIdx.z * kchunk;
+    const int ntile = tiles_x * tiles_y;
+    const int bid = blockIdx.x, slot = bid >> 3;
+    const int tile = slot % ntile, split = (slot / ntile) * 8 + (bid & 7);
+    const int bx = tile % tiles_x, by = tile / tiles_x;
+    const int m0 = by * TM, n0 = bx * TN;
+    const int kbeg = split * kchunk;
+    if (split > 0 && kbeg >= K) return;   // grid rounded up to whole splits per XCD
     const int kend = min(K, kbeg + kchunk);
+    const int nsteps = kend > kbeg ? (kend - kbeg + 31) / 32 : 0;
     // loader work items of one 32-deep K step, A then B: a row-major operand has 16 pair rows
     // x width/8 column chunks (two 16-byte row loads each, eight pairs); a saved-array operand
     // 16 pair rows x width/4 feature quads (one 16-byte load each, four pairs)
@@ -1147,40 +1212,41 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
             cc = qq % cw;
         }
     };
+    // Element offset of load e of work item q at step k0, and whether it lies inside the
+    // operand (row below K, column below M or N).  Loads outside are still issued, from the
+    // operand's first element, and their values cleared at the LDS store: a load in a branch
+    // (or one whose value is changed as soon as it returns) makes the compiler wait for it
+    // before issuing the next.
+    auto where = [&](int q, int k0, int e, bool &ok) -> int64_t {
+        bool isA;
+        int kp, cc;
+        item(q, isA, kp, cc);
+        const int k = k0 + 2 * kp;
+        if (isA ? AT : BT) {
+            // the tile's 32 cells x width features are one contiguous run of the saved layout
+            // from tm_idx(k0, first feature); item (kp, cc) is its 16 * cc + kp-th 16-byte piece
+            // (cells 2kp, 2kp + 1, features 4cc .. 4cc + 3); the odd cell is checked at the store
+            ok = q < NA + NB && e == 0 && k < kend && (isA ? m0 : n0) + 4 * cc < (isA ? M : N);
+            return ok ? tm_idx(k0, isA ? m0 : n0) + 8 * (16 * cc + kp) : 0;
+        }
+        const int col = (isA ? m0 : n0) + 8 * cc;
+        ok = q < NA + NB && k + e < kend && col < (isA ? M : N);
+        return ok ? (int64_t)(k + e) * (isA ? lda : ldb) + col : 0;
+    };
     auto load = [&](int k0, uint4 (&rx)[PER][2]) {
 #pragma unroll
         for (int p = 0; p < PER; p++) {
             const int q = t + 256 * p;
-            rx[p][0] = rx[p][1] = make_uint4(0, 0, 0, 0);
-            if (q < NA + NB) {
-                bool isA;
-                int kp, cc;
-                item(q, isA, kp, cc);
-                const bool tm = isA ? AT : BT;
-                const int lim = isA ? M : N;
-                const bf16_t *src = isA ? A : B;
-                const int k = k0 + 2 * kp;
-                if (tm) {
-                    // the tile's 32 cells x width features are one contiguous run of the saved
-                    // layout from tm_idx(k0, first feature); item (kp, cc) is its 16 * cc + kp-th
-                    // 16-byte piece (cells 2kp, 2kp + 1, features 4cc .. 4cc + 3)
-                    const int f = (isA ? m0 : n0) + 4 * cc;
-                    if (k < kend && f < lim) {
-                        const bf16_t *run = src + tm_idx(k0, isA ? m0 : n0);
-                        rx[p][0] = *reinterpret_cast<const uint4 *>(run + 8 * (16 * cc + kp));
-                    }
-                } else {
-                    const int col = (isA ? m0 : n0) + 8 * cc;
-                    const int ld = isA ? lda : ldb;
+            const bool tm = q < NA ? AT : BT;
 #pragma unroll
-                    for (int e = 0; e < 2; e++)
-                        if (k + e < kend && col < lim) rx[p][e] = *reinterpret_cast<const uint4 *>(src + (int64_t)(k + e) * ld + col);
-                }
+            for (int e = 0; e < (AT && BT ? 1 : 2); e++) {
+                if (e == 1 && tm) continue;
+                bool ok;
+                const int64_t off = where(q, k0, e, ok);
+                rx[p][e] = *reinterpret_cast<const uint4 *>((q < NA ? A : B) + off);
             }
         }
     };
-    // the ragged end's odd cell (past n) is cleared here rather than at the load, so that no
-    // load has to complete before the next one is issued
     auto store = [&](int buf, int k0, const uint4 (&rx)[PER][2]) {
 #pragma unroll
         for (int p = 0; p < PER; p++) {
@@ -1189,14 +1255,18 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
                 bool isA;
                 int kp, cc;
                 item(q, isA, kp, cc);
+                bool ok0, ok1;
+                (void)where(q, k0, 0, ok0);
                 if (isA ? AT : BT) {
-                    uint4 v = rx[p][0];
-                    if (k0 + 2 * kp + 1 >= kend) v.z = v.w = 0u;
+                    uint4 v = ok0 ? rx[p][0] : make_uint4(0, 0, 0, 0);
+                    if (k0 + 2 * kp + 1 >= kend) v.z = v.w = 0u;   // the ragged end's odd cell
                     unsigned *dst = isA ? &As[buf][kp][4 * cc] : &Bs[buf][kp][4 * cc];
                     *reinterpret_cast<uint4 *>(dst) = kw_interleave4(v);
                 } else {
+                    (void)where(q, k0, 1, ok1);
                     uint4 lo, hi;
-                    kw_interleave(rx[p][0], rx[p][1], lo, hi);
+                    kw_interleave(ok0 ? rx[p][0] : make_uint4(0, 0, 0, 0), ok1 ? rx[p][1] : make_uint4(0, 0, 0, 0),
+                                  lo, hi);
                     unsigned *dst = isA ? &As[buf][kp][8 * cc] : &Bs[buf][kp][8 * cc];
                     *reinterpret_cast<uint4 *>(dst) = lo;
                     *reinterpret_cast<uint4 *>(dst + 4) = hi;
@@ -1209,17 +1279,9 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
     for (int i = 0; i < BM; i++)
 #pragma unroll
         for (int j = 0; j < BN; j++) acc[i][j] = f32x16{};
-    uint4 rx[PER][2];
     float csum = 0.f;
-    int buf = 0;
-    if (kbeg < kend) {
-        load(kbeg, rx);
-        store(0, kbeg, rx);
-    }
-    __syncthreads();
-    for (int k0 = kbeg; k0 < kend; k0 += 32) {
-        const bool more = k0 + 32 < kend;
-        if (more) load(k0 + 32, rx);
+    const bool colsum = Cb && bx == 0 && t < TM;
+    auto compute = [&](int buf) {
 #pragma unroll
         for (int kb = 0; kb < 2; kb++) {
             bf16x8 af[BM], bfr[BN];
@@ -1244,7 +1306,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
 #pragma unroll
                 for (int j = 0; j < BN; j++) acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
         }
-        if (Cb && blockIdx.x == 0 && t < TM) {
+        if (colsum) {
             // column t of the A tile: 16 (k even, k odd) pairs of this step
 #pragma unroll
             for (int kp = 0; kp < 16; kp++) {
@@ -1253,13 +1315,26 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
                 csum += __builtin_bit_cast(float, v & 0xffff0000u);
             }
         }
-        if (more) store(buf ^ 1, k0 + 32, rx);
+    };
+    // step i sits in LDS buffer i % 2; the loads of step i + 1 are in flight during step i's
+    // MFMAs.  Loads of a step past the range are issued too (they read the operand's first
+    // element and are cleared at the store), so that no load sits in a branch.
+    uint4 rx[PER][2];
+    load(kbeg, rx);
+    store(0, kbeg, rx);
+    __syncthreads();
+    int buf = 0;
+    for (int i = 0; i < nsteps; i++) {
+        const int k1 = kbeg + 32 * (i + 1);
+        load(k1, rx);
+        compute(buf);
+        if (i + 1 < nsteps) store(buf ^ 1, k1, rx);
         __syncthreads();
         buf ^= 1;
     }
-    if (Cb && blockIdx.x == 0 && t < TM && m0 + t < M) Cb[blockIdx.z * strideC + m0 + t] = csum;
+    if (colsum && m0 + t < M) Cb[split * strideC + m0 + t] = csum;
     // C layout of the 32 x 32 blocks: column = lane % 32 (n), rows 8q + 4h + (0..3) (m)
-    float *Cz = C + blockIdx.z * strideC;
+    float *Cz = C + split * strideC;
 #pragma unroll
     for (int i = 0; i < BM; i++)
 #pragma unroll
@@ -1292,6 +1367,7 @@ struct props_dnn_s {
     // forward/backward scratch for one batch
     bf16_t *h0 = nullptr, *zs[MAX_HIDDEN] = {}, *hs[MAX_HIDDEN] = {}, *dzo = nullptr;
     float *part = nullptr, *lpart = nullptr;
+    GradParts gp{};   // where the last fwd_bwd left each layer's partials
     int *fb_idx = nullptr, *fb_count = nullptr;
     int64_t fb_cap = 0;
     size_t params() const { return total_params(nhid); }
@@ -1369,7 +1445,7 @@ static int ensure_train_scratch(props_dnn_s *d)
     const size_t B = MAX_BATCH;
     if ((rc = dalloc(&d->h0, B * IN_PAD)) ||
         (rc = dalloc(&d->dzo, B * OUT_PAD)) ||
-        (rc = dalloc(&d->part, (size_t)SPLITW * (HID * HID + HID))) ||
+        (rc = dalloc(&d->part, part_floats(d->nhid))) ||
         (rc = dalloc(&d->lpart, (size_t)B / CELLS_PER_WAVE + 64)))
         return rc;
     // the forward writes input columns 0..15 of the saved inputs; 16..31 stay zero
@@ -1425,37 +1501,44 @@ static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
 }
 
 // dW = dz^T h (and db = column sums of dz) for the layer shapes of the network: (256, 256) on
-// 128 x 128 tiles, (256, 32) (input layer) on 128 x 32 tiles, (16, 256) (output layer) on
-// 32 x 128 tiles.  Split z writes its W partials at part + z (O I + O) and its bias partials
-// right after them, so one ordered reduction gives W and b, which are adjacent in the master.
+// 128 x 128 tiles in SPLIT_HID batch splits, (256, 32) (input layer) on 128 x 32 tiles and
+// (16, 256) (output layer) on 32 x 128 tiles in SPLIT_IO splits.  Split z writes its W
+// partials at part + z (O I + O) and its bias partials right after them, so one ordered
+// reduction gives W and b, which are adjacent in the master.
+template <int TM, int TN, int WAVES_M, bool AT, bool BT>
+static void launch_wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, int nsplit, float *part,
+                         int &splits, hipStream_t s)
+{
+    const int kchunk = ((n + nsplit - 1) / nsplit + 31) / 32 * 32;
+    splits = (n + kchunk - 1) / kchunk;
+    const int tiles_x = (I + TN - 1) / TN, tiles_y = (O + TM - 1) / TM;
+    const int grid = tiles_x * tiles_y * ((splits + 7) / 8 * 8);
+    const int64_t stride = (int64_t)O * I + O;
+    hipLaunchKernelGGL((gemm_wgrad_kernel<TM, TN, WAVES_M, AT, BT>), dim3(grid), dim3(256), 0, s, dz, O, O, hp, I, I,
+                       n, kchunk, tiles_x, tiles_y, part, I, stride, part + (int64_t)O * I);
+}
+
 static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float *part, int &splits, hipStream_t s)
 {
-    const int kchunk = ((n + SPLITW - 1) / SPLITW + 31) / 32 * 32;
-    splits = (n + kchunk - 1) / kchunk;
-    const int64_t stride = (int64_t)O * I + O;
-    float *pb = part + (int64_t)O * I;
     // hidden layers: both operands in the saved-array layout; layer 0: dz saved, the inputs
     // row-major [n][32]; output layer: dz row-major [n][16], h saved
-    if (O % 128 == 0 && I % 128 == 0) {
-        hipLaunchKernelGGL((gemm_wgrad_kernel<128, 128, 2, true, true>), dim3(I / 128, O / 128, splits), dim3(256), 0, s,
-                           dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
-    } else if (O % 128 == 0 && I == 32) {
-        hipLaunchKernelGGL((gemm_wgrad_kernel<128, 32, 4, true, false>), dim3(1, O / 128, splits), dim3(256), 0, s,
-                           dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
-    } else if (O <= 32 && O % 8 == 0 && I % 128 == 0) {
-        hipLaunchKernelGGL((gemm_wgrad_kernel<32, 128, 1, false, true>), dim3(I / 128, 1, splits), dim3(256), 0, s,
-                           dz, O, O, hp, I, I, n, kchunk, part, I, stride, pb);
-    } else {
+    if (O % 128 == 0 && I % 128 == 0)
+        launch_wgrad<128, 128, 2, true, true>(dz, O, hp, I, n, SPLIT_HID, part, splits, s);
+    else if (O % 128 == 0 && I == 32)
+        launch_wgrad<128, 32, 4, true, false>(dz, O, hp, I, n, SPLIT_IO, part, splits, s);
+    else if (O <= 32 && O % 8 == 0 && I % 128 == 0)
+        launch_wgrad<32, 128, 1, false, true>(dz, O, hp, I, n, SPLIT_IO, part, splits, s);
+    else
         return fail(PROPS_EINVAL, "wgrad: unsupported layer shape %d x %d", O, I);
-    }
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
 }
 
-// One forward + backward pass over rows [row0, row0 + n) of the permuted data; leaves the
-// gradient in d->grad and the loss partials (one per wave of 32 rows) in d->lpart.
+// One forward + backward pass over rows [row0, row0 + n) of the permuted data; leaves each
+// layer's split-K gradient partials (d->gp, reduced by grad_step) and the loss partials (one
+// per wave of 32 rows) in lpart.
 static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, uint64_t pa, uint64_t pc,
-                   int64_t row0, int n, hipStream_t s)
+                   int64_t row0, int n, float *lpart, hipStream_t s)
 {
     int rc;
     const int nh = d->nhid;
@@ -1480,7 +1563,7 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
     a.hs = d->hs[0];
     a.lstride = (int64_t)MAX_BATCH * HID;
     a.dzo = d->dzo;
-    a.lpart = d->lpart;
+    a.lpart = lpart;
     if ((rc = launch_fwd(true, a, s))) return rc;
     // dz of every hidden layer in one fused pass, written over the saved z
     BwdArgs bw{};
@@ -1492,18 +1575,33 @@ static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, u
     bw.nhid = nh;
     if ((rc = launch_bwd(bw, s))) return rc;
     // weight and bias gradients, output layer to input: dW_l = dz_l^T h_{l-1}, db_l = sum dz_l
-    // (M = O, N = I, K = n), split over the batch
+    // (M = O, N = I, K = n), split over the batch; the partials stay for grad_step
+    float *pl = d->part;
+    d->gp.nl = nh + 1;
+    for (int l = 0; l <= nh; l++) d->gp.off[l] = (int64_t)w_off(l);
+    d->gp.off[nh + 1] = (int64_t)total_params(nh);
     for (int l = nh; l >= 0; l--) {
         const int O = lout(l, nh), I = lin(l);
         const bf16_t *dzl = (l == nh) ? d->dzo : d->zs[l];
         const bf16_t *hprev = (l == 0) ? d->h0 : d->hs[l - 1];
         int splits = 0;
-        if ((rc = wgrad(dzl, O, hprev, I, n, d->part, splits, s))) return rc;
-        const int64_t cnt = (int64_t)O * I + O;
-        hipLaunchKernelGGL(reduce_partials_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
-                           d->part, splits, cnt, cnt, d->grad + w_off(l));
-        PROPS_HIP_TRY(hipGetLastError());
+        if ((rc = wgrad(dzl, O, hprev, I, n, pl, splits, s))) return rc;
+        d->gp.part[l] = pl;
+        d->gp.splits[l] = splits;
+        pl += (size_t)splits * ((size_t)O * I + O);
     }
+    return PROPS_OK;
+}
+
+// The reduction of the last fwd_bwd's partials: into d->grad (adam = false), or straight
+// into an Adam step of the master and its bf16 copies.
+static int grad_step(props_dnn_s *d, bool adam, float lr, float b1, float b2, float eps, float bc1, float bc2,
+                     hipStream_t s)
+{
+    const int64_t P = d->gp.off[d->gp.nl];
+    hipLaunchKernelGGL(grad_step_kernel, dim3((unsigned)((P / 2 + 255) / 256)), dim3(256), 0, s, d->gp, d->nhid, d->grad,
+                       d->master, d->m, d->v, d->fused, d->bwd, (int)adam, lr, b1, b2, eps, bc1, bc2);
+    PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
 }
 
@@ -1850,7 +1948,8 @@ int props_dnn_grad(props_dnn_t d, const float *X, const float *Y, int64_t n, flo
     hipStream_t s = (hipStream_t)hip_stream;
     int rc;
     if ((rc = ensure_train_scratch(d))) return rc;
-    if ((rc = fwd_bwd(d, X, Y, n, 1, 0, 0, (int)n, s))) return rc;
+    if ((rc = fwd_bwd(d, X, Y, n, 1, 0, 0, (int)n, d->lpart, s))) return rc;
+    if ((rc = grad_step(d, false, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f, s))) return rc;
     const int nh = d->nhid;
     const size_t nw = (size_t)((n + TILE_CELLS - 1) / TILE_CELLS) * FWD_WAVES;
     std::vector<float> g(d->params()), lp(nw);
@@ -1886,7 +1985,6 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
     const float b1 = cfg->beta1 > 0 ? cfg->beta1 : 0.9f, b2 = cfg->beta2 > 0 ? cfg->beta2 : 0.999f;
     const float eps = cfg->eps > 0 ? cfg->eps : 1e-8f;
     const int64_t steps_per_epoch = (n + batch - 1) / batch;
-    const int64_t P = (int64_t)d->params();
     std::vector<float> lp;
     int64_t steps = 0;
     float *lsum = nullptr;   // per-step loss partials of one epoch (one per wave of 32 rows)
@@ -1902,17 +2000,14 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
         for (int64_t st = 0; st < steps_per_epoch; st++) {
             const int64_t row0 = st * batch;
             const int m = (int)std::min<int64_t>(batch, n - row0);
-            if ((rc = fwd_bwd(d, X, Y, n, pa, pc, row0, m, s))) {
+            // the loss partials go straight to this step's slots of the epoch's array
+            if ((rc = fwd_bwd(d, X, Y, n, pa, pc, row0, m, lsum + st * lslots, s))) {
                 (void)hipFree(lsum);
                 return rc;
             }
-            const size_t nw = (size_t)((m + TILE_CELLS - 1) / TILE_CELLS) * FWD_WAVES;
-            PROPS_HIP_TRY(hipMemcpyAsync(lsum + st * lslots, d->lpart, sizeof(float) * nw, hipMemcpyDeviceToDevice, s));
             d->step++;
             const float bc1 = 1.0f - std::pow(b1, (float)d->step), bc2 = 1.0f - std::pow(b2, (float)d->step);
-            hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, d->master, d->grad,
-                               d->m, d->v, P, lr, b1, b2, eps, bc1, bc2);
-            if ((rc = refresh_weights(d, s))) {
+            if ((rc = grad_step(d, true, lr, b1, b2, eps, bc1, bc2, s))) {
                 (void)hipFree(lsum);
                 return rc;
             }
