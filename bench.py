@@ -880,6 +880,37 @@ def main():
         ms_ng, _ = timed(props.FP64, max(10, args.steps // 2), 2)
         ins = save
         rec["fp64_no_guess"] = {"value": n / (ms_ng * 1e-3), "ms_per_step": ms_ng}
+        # where the headline launch's time goes: the same call without mu and lambda (the
+        # kernel then carries no transport code), from the exact temperature (one evaluation
+        # of e(T) instead of ~2.9), and both; the last is close to the launch's HBM time
+        def timed_fn(fn, steps, warmup):
+            for i in range(warmup):
+                fn(i)
+            torch.cuda.synchronize()
+            a_, b_ = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a_.record(stream)
+            for i in range(steps):
+                fn(i)
+            b_.record(stream)
+            torch.cuda.synchronize()
+            return a_.elapsed_time(b_) / steps
+
+        thermo_keys = [k for k in outs[0] if k not in ("mu", "lambda")]
+        outs_nt = [{k: o[k] for k in thermo_keys} for o in outs]
+        ins_ex = [dict(d, T_guess=dt(T)) for d in ins]
+        nb = max(10, args.steps // 2)
+        bd = {"full": ms,
+              "no_transport": timed_fn(lambda i: props.pr(mech, props.RHOEY, props.FP64, ins[i % NCOPY],
+                                                          outs_nt[i % NCOPY], n, stream=stream), nb, 2),
+              "exact_guess": timed_fn(lambda i: props.pr(mech, props.RHOEY, props.FP64, ins_ex[i % NCOPY],
+                                                         outs[i % NCOPY], n, stream=stream), nb, 2),
+              "exact_guess_no_transport": timed_fn(lambda i: props.pr(mech, props.RHOEY, props.FP64,
+                                                                      ins_ex[i % NCOPY], outs_nt[i % NCOPY], n,
+                                                                      stream=stream), nb, 2)}
+        del ins_ex
+        rec["breakdown_ms"] = bd
+        rec["breakdown_ms"]["hbm_time_at_copy_rate"] = None   # filled in below, once the copy rate is known
+        log("breakdown (ms): " + ", ".join(f"{k} {v:.4f}" for k, v in bd.items() if v is not None))
         rec["shard_1_of_8"] = shard_section(props, mech, ins[0], n, stream, args.steps)
         log(f"1/8 shard: {rec['shard_1_of_8']['ms_per_step']:.4f} ms, {rec['shard_1_of_8']['value']:.3e} cells/s")
         rec["pty"] = pty_section(props, mech, n, Pd, dt(T), Yd, stream, max(10, args.steps // 2))
@@ -896,6 +927,7 @@ def main():
         rec["roofline"]["copy_kernel"] = "props_stream_copy (16-byte non-temporal vectors, 1 GiB)"
         rec["roofline"]["torch_copy_GBs"] = tbw
         rec["roofline"]["hbm_frac_of_copy"] = hbm / cbw
+        rec["breakdown_ms"]["hbm_time_at_copy_rate"] = bpc * n / (cbw * 1e9) * 1e3
         for sec in ("pty", "diffusion", "hpy"):
             for prec in ("fp64", "mixed"):
                 r = rec.get(sec, {}).get(prec, {})
