@@ -448,3 +448,72 @@ def test_constant_training_feature_still_bounds_the_hull(props, sp8):
     s = st.cpu().numpy()
     assert np.all(s[0::2] == 0), s[0::2]
     assert np.all(s[1::2] & 64) and np.all(s[1::2] & 128), s[1::2]
+
+
+def test_trained_network_gain(props, sp8):
+    """What the trained network gains: the same network before training (initial weights,
+    fitted scalers) and after 60 epochs on 2^18 states labelled by the library's FP64 PR
+    path, each against that path on a 64^3 flame field (the judge of the surrogate's error,
+    itself checked against the oracle by the parity tests); the surrogate's throughput on
+    the field is recorded beside the FP64 and mixed PR paths' (printed, not asserted: on
+    this GPU the PR path is the faster)."""
+    import time
+    import torch
+    keys = ("rho", "h", "cp", "c", "mu", "lambda")
+    mech = props.Mechanism(sp8, synth.synthetic_kij(8))
+    n_train = 1 << 18
+    P, T, Y = synth.training_states(n_train, seed=21)
+    Pd, Td, Yd = dev(P), dev(T), dev(Y)
+    lab = {k: torch.empty(n_train, dtype=torch.float64, device="cuda:0") for k in keys}
+    props.pr(mech, props.PTY, props.FP64, {"P": Pd, "T": Td, "Y": Yd}, lab, n_train)
+    X = torch.cat([Pd[None], Td[None], Yd]).float().contiguous()
+    L = torch.stack([lab[k] for k in keys]).float().contiguous()
+    Pf, Tf, Yf = synth.flame_field(64, seed=22)
+    n = Tf.size
+    ins = {"P": dev(Pf), "T": dev(Tf), "Y": dev(Yf)}
+    ref = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in keys}
+    props.pr(mech, props.PTY, props.FP64, ins, ref, n)
+
+    def errors(net):
+        out = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in keys}
+        st = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+        net(ins, out, n, status=st)
+        torch.cuda.synchronize()
+        inside = (st == 0)
+        assert int(inside.sum()) > 0.95 * n
+        e = {}
+        for k in keys:
+            r = ref[k][inside]
+            scale = r.abs() + (1e5 if k == "h" else 0.0)
+            rel = ((out[k][inside] - r).abs() / scale)
+            e[k] = (float(rel.max()), float(rel.pow(2).mean().sqrt()))
+        return e
+
+    net = props.Network(seed=31)
+    net.train(X, L, n_train, epochs=0, batch=8192, fit_scalers=True)
+    before = errors(net)
+    _, losses = net.train(X, L, n_train, epochs=60, batch=8192, lr=2e-3, lr_min=2e-5, seed=5, fit_scalers=False)
+    after = errors(net)
+    assert losses[-1] < 0.2 * losses[0]
+    for k in keys:
+        # the trained network is at least ten times better in RMS and within 5 % RMS
+        assert after[k][1] < 0.1 * before[k][1], (k, before[k], after[k])
+        assert after[k][1] < 5e-2, (k, after[k])
+
+    def rate(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return n * reps / (time.perf_counter() - t0)
+
+    out = {k: torch.empty(n, dtype=torch.float64, device="cuda:0") for k in keys}
+    r_dnn = rate(lambda: net(ins, out, n))
+    r_fp64 = rate(lambda: props.pr(mech, props.PTY, props.FP64, ins, out, n))
+    r_mix = rate(lambda: props.pr(mech, props.PTY, props.MIXED, ins, out, n))
+    print("[surrogate gain] RMS rel. error untrained -> trained: " +
+          ", ".join(f"{k} {before[k][1]:.2e} -> {after[k][1]:.2e}" for k in keys) +
+          f"; cells/s DNN {r_dnn:.3e}, PR FP64 {r_fp64:.3e}, PR mixed {r_mix:.3e}", flush=True)
+    net.close()
