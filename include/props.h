@@ -90,7 +90,9 @@ int props_mech_num_species(props_mech_t m);
  * step at most this small is the last one (convergence is cubic for (rho, e, Y), which
  * takes Chebyshev's third-order step, and quadratic for (h, P, Y)); after a bisection step
  * that small, one more step is taken.  (h, P, Y) also ends after three Newton steps of
- * consistent quadratic contraction once the error they predict is below 1e-5 rtol T.
+ * consistent quadratic contraction once the error they predict is below 1e-5 rtol T, and
+ * (rho, e, Y) after two Chebyshev steps d1, d once the error cubic convergence predicts,
+ * d^4/d1^3, is below 1e-8 rtol T.
  * max_iter and rtol outside [1, 10000] and (0, 1) return PROPS_EINVAL. */
 int props_mech_set_newton(props_mech_t m, int max_iter, double rtol);
 

@@ -490,6 +490,12 @@ __device__ __forceinline__ double stable_root(double A, double B, uint8_t &st)
 // quadratic convergence predicts after the last step is below kStopAhead rtol T (with
 // rtol = 1e-10, 1e-15 relative: rounding level).
 constexpr double kStopAhead = 1e-5;
+// Look-ahead stop of the (rho, e, Y) inversion: after two consecutive Chebyshev steps d1, d,
+// cubic convergence (error e' ~ M e^3, with M ~ d / d1^3 from the two steps) predicts the error
+// left after the last step as d^4 / d1^3; the iteration ends once that is below
+// kStopAheadCubic rtol T, three orders of magnitude inside the (h, P, Y) bound, so that an
+// estimate of M a thousand times too small still leaves the result at rounding level.
+constexpr double kStopAheadCubic = 1e-8;
 // Minimum waves per SIMD the register allocation must allow (1: the compiler's choice;
 // forcing 4 or 5 for the 8-species FP64 kernel spills and measured slower).  The (h, P, Y)
 // kernels, left to themselves at 185-213 VGPRs (2 waves), are held to 3 waves: a spill of
@@ -706,7 +712,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
                 const double g = a.Tg[k];
                 if (g > kTlo && g < kThi) T = g;
             }
-            bool fin = false, conv = false;
+            bool fin = false, conv = false, lastN = false;
             double dT1 = __builtin_inf(), dT2 = __builtin_inf();   // sizes of the last two steps
             int it = 0;
             // With single-precision departures the residual carries ~1e-7 relative noise,
@@ -739,7 +745,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
                 // rtol ends the iteration: convergence is cubic, so the updated T is exact to
                 // rounding.  After a small bisection step one more (polishing) step is taken,
                 // which never bisects: a converged T whose step rounds to nothing sits on a
-                // bracket end, and bisecting there would throw it away.
+                // bracket end, and bisecting there would throw it away.  So does the second of two
+                // Chebyshev steps once the error it predicts, d^4 / d1^3, is below kStopAheadCubic
+                // rtol T.
                 const double irp = fm::rcp(rp);
                 const double dN = r * irp;
                 const double q = 0.5 * dN * rpp * irp;
@@ -747,11 +755,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == PRO
                 const bool newton = (rp > 0.0) && (Tn >= lo && Tn <= hi) && (fabs(Tn - T) <= 0.5 * dT2);
                 if (!newton) Tn = fin ? T : 0.5 * (lo + hi);
                 const double dT = Tn - T, adT = fabs(dT);
+                const double a2 = adT * adT;
+                const bool ahead = newton && lastN && a2 * a2 <= kStopAheadCubic * rtol * Tn * dT1 * dT1 * dT1;
+                lastN = newton;
                 dT2 = dT1;
                 dT1 = adT;
                 T = Tn;
                 if (fin) { conv = true; break; }
-                if (adT <= rtol * T) {
+                if (adT <= rtol * T || ahead) {
                     if (newton) { conv = true; break; }
                     fin = true;
                 }
