@@ -730,7 +730,7 @@ def main():
     ap.add_argument("--no-dnn", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--dnn-epochs", type=int, default=1000)
-    ap.add_argument("--hpz-epochs", type=int, default=30)
+    ap.add_argument("--hpz-epochs", type=int, default=300)
     ap.add_argument("--dnn-train", type=int, default=8_388_608)
     ap.add_argument("--dnn-res", type=int, default=256)
     ap.add_argument("--copy-calibration", action="store_true",
