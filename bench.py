@@ -740,7 +740,7 @@ def main():
                          "for profiling the MLP kernels")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (--gpus {args.gpus} requested); "
+        print(f"bench.py: this benchmark runs on one GPU only (--gpus {args.gpus} requested); "
               "cells are independent, so N GPUs would each evaluate their own field slab.",
               file=sys.stderr)
         sys.exit(2)

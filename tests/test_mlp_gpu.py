@@ -453,7 +453,7 @@ def test_constant_training_feature_still_bounds_the_hull(props, sp8):
 def test_trained_network_gain(props, sp8):
     """What the trained network gains: the same network before training (initial weights,
     fitted scalers) and after 60 epochs on 2^18 states labelled by the library's FP64 PR
-    path, each against that path on a 64^3 flame field (the judge of the surrogate's error,
+    path, each against that path on a 64^3 flame field (the reference for the surrogate's error,
     itself checked against the oracle by the parity tests); the surrogate's throughput on
     the field is recorded beside the FP64 and mixed PR paths' (printed, not asserted: on
     this GPU the PR path is the faster)."""
