@@ -436,6 +436,10 @@ __device__ __forceinline__ f32x16 hid_block(const unsigned char *lds, BlkAddr cu
         for (int w = 0; w < nv; w++) {
             const int v = v0 + w;
             gv[v] = gelu_f(pz[v]);
+            // pinned to this step: the activations are needed only by the next layer, and
+            // without the pin the compiler sinks the GELUs of whole blocks out of the
+            // matrix-core steps into one run of vector work
+            asm volatile("" : "+v"(gv[v]));
             if (v & 1) pg[v >> 1] = pack_bf16x2(gv[v - 1], gv[v]);
         }
         __builtin_amdgcn_sched_barrier(0);
