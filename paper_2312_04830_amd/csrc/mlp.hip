@@ -159,6 +159,9 @@ __device__ __forceinline__ float gelu_f(float x)
     float e = __builtin_amdgcn_exp2f(t);
     return x * __builtin_amdgcn_rcpf(1.0f + e);
 }
+// gelu_f in two halves, the same operations in the same order: the exponential, then the rest
+__device__ __forceinline__ float gelu_exp_f(float x) { return __builtin_amdgcn_exp2f(x * __builtin_fmaf(kG1, x * x, kG0)); }
+__device__ __forceinline__ float gelu_fin_f(float x, float e) { return x * __builtin_amdgcn_rcpf(1.0f + e); }
 
 // d/dx of gelu_f
 __device__ __forceinline__ float gelu_grad_f(float x)
@@ -407,40 +410,51 @@ __device__ __forceinline__ f32x16 l0_block(const unsigned char *lds, BlkAddr cur
 // One 32-row output block of a 256-input layer at `cur`: returns bias + W act in 17
 // matrix-core steps (the bias block, then K blocks 0..15), while the GELU of the pending
 // block's accumulator pz is formed one value per step into the packed bf16 pairs pg.  Each
-// step is a scheduling region of its own (the LDS read FPF steps ahead, one MFMA, one or two
-// GELU values), so that the vector work of a step runs in the shadow of its MFMA.  The stream
-// continues into the next block at `nx`, a 256-input block or (NEXT_L0) the next tile's
-// layer 0.  FIRST: pz is the previous layer's last block, i.e. act[14], act[15]; its 16
-// values are done by step 14 (two at step 0), and act[14], act[15] are filled before steps
-// 15 and 16.
+// step is a scheduling region of its own (the LDS read FPF steps ahead, one MFMA, the first
+// part of one or two GELU values and the rest of the previous step's), so that the vector
+// work of a step runs in the shadow of its MFMA.  The stream continues into the next block
+// at `nx`, a 256-input block or (NEXT_L0) the next tile's layer 0.  FIRST: pz is the previous
+// layer's last block, i.e. act[14], act[15]; its 16 values are started by step 14 (two at
+// step 0) and finished a step later, act[14] (values 0..7) is filled before step 15 and
+// act[15] (values 8..15) before step 16, the steps that read them.
 template <bool FIRST, bool NEXT_L0>
 __device__ __forceinline__ f32x16 hid_block(const unsigned char *lds, BlkAddr cur, BlkAddr nx, Ring &ring,
                                             bf16x8 (&act)[16], const f32x16 &pz, unsigned (&pg)[8], bf16x8 ones)
 {
     constexpr int NS = 17;
     f32x16 acc = {};
-    float gv[16];
+    float ex[16], gv[16];
+    // values whose GELU starts at step s (FIRST: two at step 0, one at steps 1..14; else one
+    // at steps 0..15); each is finished one step later
+    const auto v0 = [](int s) { return FIRST ? (s == 0 ? 0 : s + 1) : s; };
+    const auto nv = [](int s) { return FIRST ? (s == 0 ? 2 : (s < 15 ? 1 : 0)) : (s < 16 ? 1 : 0); };
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-        if (FIRST && s == 15) {
-            act[14] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
-            act[15] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
-        }
+        if (FIRST && s == 15) act[14] = __builtin_bit_cast(bf16x8, make_uint4(pg[0], pg[1], pg[2], pg[3]));
+        if (FIRST && s == 16) act[15] = __builtin_bit_cast(bf16x8, make_uint4(pg[4], pg[5], pg[6], pg[7]));
         const int u = s + FPF;
         const bf16x8 af = ring_step(ring, u < NS ? hid_frag(lds, cur, u)
                                                  : (NEXT_L0 ? l0_frag(lds, nx, u - NS) : hid_frag(lds, nx, u - NS)));
         acc = (s == 0) ? mfma32(af, ones, f32x16{}) : mfma32(af, act[s - 1], acc);
-        const int v0 = FIRST ? (s == 0 ? 0 : s + 1) : s;
-        const int nv = FIRST ? (s == 0 ? 2 : (s < 15 ? 1 : 0)) : (s < 16 ? 1 : 0);
+        // Each part of a GELU is pinned to its step: the activations are needed only by the
+        // next layer, and without the pin the compiler sinks the GELUs of whole blocks out of
+        // the matrix-core steps into one run of vector work.  The chain of one value (seven
+        // dependent operations) is split over two steps: this step's exponentials, then the
+        // rest of the previous step's values.
 #pragma unroll
-        for (int w = 0; w < nv; w++) {
-            const int v = v0 + w;
-            gv[v] = gelu_f(pz[v]);
-            // pinned to this step: the activations are needed only by the next layer, and
-            // without the pin the compiler sinks the GELUs of whole blocks out of the
-            // matrix-core steps into one run of vector work
-            asm volatile("" : "+v"(gv[v]));
-            if (v & 1) pg[v >> 1] = pack_bf16x2(gv[v - 1], gv[v]);
+        for (int w = 0; w < nv(s); w++) {
+            const int v = v0(s) + w;
+            ex[v] = gelu_exp_f(pz[v]);
+            asm volatile("" : "+v"(ex[v]));
+        }
+        if (s > 0) {
+#pragma unroll
+            for (int w = 0; w < nv(s - 1); w++) {
+                const int v = v0(s - 1) + w;
+                gv[v] = gelu_fin_f(pz[v], ex[v]);
+                asm volatile("" : "+v"(gv[v]));
+                if (v & 1) pg[v >> 1] = pack_bf16x2(gv[v - 1], gv[v]);
+            }
         }
         __builtin_amdgcn_sched_barrier(0);
     }
