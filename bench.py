@@ -858,9 +858,9 @@ def main():
     }
 
     if not args.no_extras:
-        # clock under sustained load: 200 launches back to back, timed in groups of ten; the
-        # shader clock falls as the FP64 load heats the part, so the first group runs faster
-        # than the steady state the timed region above is partly made of
+        # clock under sustained load: 200 more launches back to back, timed in groups of ten;
+        # the shader clock moves under this FP64 load for the first ~50 ms of a run, and a flat
+        # series here shows that the timed region above ran at the settled clock
         torch.cuda.synchronize()
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(21)]
         evs[0].record(stream)
