@@ -68,12 +68,14 @@ constexpr int LDS_BYTES = NRING * 2 * SLOT_BYTES;         // 101,376 B per workg
 constexpr int L0_BYTES = HID * IROW * 2;                  // layer 0 whole: 12,288 B, one slot
 static_assert(L0_BYTES <= SLOT_BYTES, "layer 0 fits one slot");
 constexpr int MAX_BATCH = 65536;
-// batch splits of the weight-gradient GEMMs (multiples of 8).  Each workgroup walks its
-// split's K range one 32-cell step at a time with one step in flight, so the time follows the
-// split length: on a 65,536 batch 32 / 64 / 128 splits of the 256 x 256 layers take 85 / 52
-// / 36 us, and 128 / 256 splits of the input layer 27 / 21 us.
-constexpr int SPLIT_HID = 128;
-constexpr int SPLIT_IO = 256;
+// Batch splits of the weight-gradient GEMMs (multiples of 8) and the prefetch depth of their
+// loaders, in 32-cell steps.  Fewer splits write and reduce fewer FP32 partials but give each
+// workgroup a longer serial walk; on a 65,536 batch 64 splits of the 256 x 256 layers (256
+// workgroups, 32 steps each) take 24 us, and 128 splits of the input and output layers 13 us.
+constexpr int SPLIT_HID = 64;
+constexpr int SPLIT_IO = 128;
+constexpr int WG_DEPTH = 4;
+
 // LDS fragment prefetch distance of the A-fragment stream, in matrix-core steps
 constexpr int FPF = 3;
 // Outputs of the (P, T, Y) surrogate trained on their logarithm: rho, cp, mu, lambda
@@ -353,16 +355,20 @@ __device__ __forceinline__ bf16x8 ring_step(Ring &r, bf16x8 incoming)
 }
 
 // Training saves of one 32-feature block of a hidden layer: bf16 pre-activations z into zl and
-// the packed bf16 activations p (8 pairs) into hl, in the saved-array layout (tm_idx).
+// the packed bf16 activations p (8 pairs) into hl, in the saved-array layout (tm_idx).  The
+// stores are non-temporal: the saves are read back only by later kernels, and kept out of
+// the cache they leave room there for the weights that every tile re-stages.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void save_block(bf16_t *zl, bf16_t *hl, int64_t cell, int ob, int h, const f32x16 &z,
                                            const unsigned *p)
 {
 #pragma unroll
     for (int q = 0; q < 4; q++) {
         const int64_t off = tm_idx(cell, 32 * ob + 8 * q + 4 * h);
-        *reinterpret_cast<uint2 *>(zl + off) =
-            make_uint2(pack_bf16x2(z[4 * q], z[4 * q + 1]), pack_bf16x2(z[4 * q + 2], z[4 * q + 3]));
-        *reinterpret_cast<uint2 *>(hl + off) = make_uint2(p[2 * q], p[2 * q + 1]);
+        const u32x2 zv = {pack_bf16x2(z[4 * q], z[4 * q + 1]), pack_bf16x2(z[4 * q + 2], z[4 * q + 3])};
+        const u32x2 hv = {p[2 * q], p[2 * q + 1]};
+        __builtin_nontemporal_store(zv, reinterpret_cast<u32x2 *>(zl + off));
+        __builtin_nontemporal_store(hv, reinterpret_cast<u32x2 *>(hl + off));
     }
 }
 
@@ -819,8 +825,10 @@ __device__ __forceinline__ float zval(const ZBlk &z, int v)
 __device__ __forceinline__ void store_dzblk(bf16_t *zl, int64_t cell, int ob, int h, const unsigned (&pg)[8])
 {
 #pragma unroll
-    for (int q = 0; q < 4; q++)
-        *reinterpret_cast<uint2 *>(zl + tm_idx(cell, 32 * ob + 8 * q + 4 * h)) = make_uint2(pg[2 * q], pg[2 * q + 1]);
+    for (int q = 0; q < 4; q++) {
+        const u32x2 v = {pg[2 * q], pg[2 * q + 1]};
+        __builtin_nontemporal_store(v, reinterpret_cast<u32x2 *>(zl + tm_idx(cell, 32 * ob + 8 * q + 4 * h)));
+    }
 }
 
 // One 32-row block of a hidden layer's transpose (16 K blocks, no bias) at `cur`, with the
@@ -1159,37 +1167,129 @@ namespace props {
 // Weight gradient C_z[m][n] = sum_{k in split z} A[k][m] B[k][n], with both operands stored
 // k-major ([batch][feature] activations and output gradients), on v_mfma_f32_32x32x16_bf16,
 // K in steps of 32.  The matrix cores want each lane's eight bf16 consecutive along K, so tiles
-// are staged in LDS as bf16 pairs (k even, k odd) per column: a thread reads two k rows of
-// eight columns (two 16-byte loads), interleaves them and stores eight pair-dwords; a
-// fragment is then four 4-byte LDS reads.  Rows of 136 dwords put the two lane halves of a
-// fragment read 32 banks apart.  Double-buffered in LDS, one barrier per step.
+// are staged in LDS as bf16 pairs (k even, k odd), four pairs (k .. k + 7) side by side per
+// column: a fragment is then one 16-byte LDS read straight into the operand's registers.
+// Double-buffered in LDS, one barrier per step.
 // A tile of TM x TN outputs per workgroup of 4 waves arranged WAVES_M x (4 / WAVES_M), each
-// wave BM x BN blocks of 32 x 32.  Columns at or beyond M (N) read as zero and are not
-// written, so the 16-row output layer runs on a 32-row tile.  The workgroups of the first
-// column tile also sum the staged A columns over their K range (Cb: the bias gradient's
-// partials, the column sums of dz), in the same fixed order on every run.
-constexpr int KW_PAD = 8;          // extra pair-dwords per LDS row
+// wave BM x BN blocks of 32 x 32.  Columns at or beyond M (N) are loaded from the operand's
+// first columns and not written (a column of A only reaches row m of C), so the 16-row output
+// layer runs on a 32-row tile.  The workgroups of the first column tile also sum the A columns
+// over their K range (Cb: the bias gradient's partials, the column sums of dz) on the matrix
+// cores, as A^T times a ones operand, in the same fixed order on every run.
+// LDS rows of (W + 1) columns x 4 dwords: 4 banks apart modulo 64, so that the 8-byte writes of
+// a wave's row-pair x column-group items and the 16-byte fragment reads meet no bank twice
+constexpr int KW_PAD = 1;
+// bf16 pairs from two dwords, one v_perm_b32 each: low halves (lo.lo, hi.lo) and high halves
+// (lo.hi, hi.hi)
+__device__ __forceinline__ unsigned pair_lo(unsigned lo, unsigned hi) { return __builtin_amdgcn_perm(hi, lo, 0x05040100u); }
+__device__ __forceinline__ unsigned pair_hi(unsigned lo, unsigned hi) { return __builtin_amdgcn_perm(hi, lo, 0x07060302u); }
+
 __device__ __forceinline__ void kw_interleave(uint4 x, uint4 y, uint4 &lo, uint4 &hi)
 {
     // x: row 2kp, y: row 2kp + 1, eight bf16 columns each -> eight (x_j, y_j) pairs
-    const unsigned xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {y.x, y.y, y.z, y.w};
-    unsigned d[8];
-#pragma unroll
-    for (int w = 0; w < 4; w++) {
-        d[2 * w] = (xs[w] & 0xffffu) | (ys[w] << 16);
-        d[2 * w + 1] = (xs[w] >> 16) | (ys[w] & 0xffff0000u);
-    }
-    lo = make_uint4(d[0], d[1], d[2], d[3]);
-    hi = make_uint4(d[4], d[5], d[6], d[7]);
+    lo = make_uint4(pair_lo(x.x, y.x), pair_hi(x.x, y.x), pair_lo(x.y, y.y), pair_hi(x.y, y.y));
+    hi = make_uint4(pair_lo(x.z, y.z), pair_hi(x.z, y.z), pair_lo(x.w, y.w), pair_hi(x.w, y.w));
 }
 
 // (cells 2kp, 2kp + 1) x four features, as one 16-byte load from the saved-array layout
 // (tm_idx): {c f0 f1, c f2 f3, c+1 f0 f1, c+1 f2 f3} -> the four (c, c+1) pairs
 __device__ __forceinline__ uint4 kw_interleave4(uint4 x)
 {
-    return make_uint4((x.x & 0xffffu) | (x.z << 16), (x.x >> 16) | (x.z & 0xffff0000u), (x.y & 0xffffu) | (x.w << 16),
-                      (x.y >> 16) | (x.w & 0xffff0000u));
+    return make_uint4(pair_lo(x.x, x.z), pair_hi(x.x, x.z), pair_lo(x.y, x.w), pair_hi(x.y, x.w));
 }
+
+// One operand of the weight-gradient GEMM: W (TM or TN) columns starting at c0, K rows.  SAVED:
+// the saved-array layout (tm_idx, 256 features); otherwise row-major [K][ld].  A work item is
+// one row pair rp (K rows 4 rp .. 4 rp + 3 of the step) times a column group: four features
+// (two 16-byte pieces of the saved layout, 32 contiguous bytes: cells 4 rp .. 4 rp + 1 and
+// 4 rp + 2 .. 4 rp + 3) or eight columns (four 16-byte row loads).  Items run along the
+// operand's contiguous direction, so consecutive lanes read consecutive memory.
+template <int W, bool SAVED>
+struct WgOperand {
+    static constexpr int CG = SAVED ? W / 4 : W / 8;   // column groups
+    static constexpr int NITEM = 8 * CG;
+    static constexpr int NLOAD = SAVED ? 2 : 4;
+    static_assert(NITEM <= 256, "one item per thread");
+    const bf16_t *base;   // item's first load at step 0 (saved) or its column (row-major)
+    int rp, cg;
+    bool live;            // item index below NITEM
+    __device__ WgOperand(const bf16_t *X, int ld, int c0, int ncol, int kbeg, int t)
+    {
+        live = t < NITEM;
+        const int q = live ? t : 0;
+        if (SAVED) {
+            rp = q & 7;
+            cg = q >> 3;
+            // the step's 32 cells x W features are one run of the saved layout from
+            // tm_idx(k, c0); item (rp, cg) is its 16-byte pieces 16 cg + 2 rp and + 1
+            base = X + tm_idx(kbeg, c0) + 128 * cg + 16 * rp;
+        } else {
+            cg = q % CG;
+            rp = q / CG;
+            const int col = c0 + 8 * cg;
+            base = X + (col < ncol ? col : 0);   // columns past the operand read its first ones
+        }
+        (void)ld;
+    }
+    // loads of step j (clamped to the last step je); rows past kend of a row-major operand
+    // read row kend - 1
+    __device__ __forceinline__ void load(int je, int kbeg, int kend, int ld, uint4 (&r)[4]) const
+    {
+        if (SAVED) {
+            const bf16_t *p = base + (int64_t)je * 8192;   // 8192 elements per 32-cell group
+            r[0] = *reinterpret_cast<const uint4 *>(p);
+            r[1] = *reinterpret_cast<const uint4 *>(p + 8);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int k = min(kbeg + 32 * je + 4 * rp + e, max(kend - 1, 0));
+                r[e] = *reinterpret_cast<const uint4 *>(base + (int64_t)k * ld);
+            }
+        }
+    }
+    // clear rows at or past nvalid (relative to the step), then write the item's pair-dwords to
+    // S[kp / 4][column][kp % 4] (STRIDE dwords per row)
+    template <int STRIDE>
+    __device__ __forceinline__ void store(unsigned *S, int nvalid, uint4 (&r)[4]) const
+    {
+        if (!live) return;
+        if (nvalid < 32) {
+            const int k0 = 4 * rp;
+            if (SAVED) {
+                if (k0 >= nvalid) r[0].x = r[0].y = 0u;
+                if (k0 + 1 >= nvalid) r[0].z = r[0].w = 0u;
+                if (k0 + 2 >= nvalid) r[1].x = r[1].y = 0u;
+                if (k0 + 3 >= nvalid) r[1].z = r[1].w = 0u;
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; e++)
+                    if (k0 + e >= nvalid) r[e] = make_uint4(0, 0, 0, 0);
+            }
+        }
+        unsigned *row = S + (rp >> 1) * STRIDE + 2 * (rp & 1);   // k pairs 2 rp, 2 rp + 1
+        if (SAVED) {
+            const uint4 a = kw_interleave4(r[0]), b = kw_interleave4(r[1]);
+            uint2 *d = reinterpret_cast<uint2 *>(row + 4 * (4 * cg));
+            d[0] = make_uint2(a.x, b.x);
+            d[2] = make_uint2(a.y, b.y);
+            d[4] = make_uint2(a.z, b.z);
+            d[6] = make_uint2(a.w, b.w);
+        } else {
+            uint4 e0, e1, o0, o1;
+            kw_interleave(r[0], r[1], e0, e1);   // k pair 2 rp, columns 0..3 and 4..7
+            kw_interleave(r[2], r[3], o0, o1);   // k pair 2 rp + 1
+            uint2 *d = reinterpret_cast<uint2 *>(row + 4 * (8 * cg));
+            d[0] = make_uint2(e0.x, o0.x);
+            d[2] = make_uint2(e0.y, o0.y);
+            d[4] = make_uint2(e0.z, o0.z);
+            d[6] = make_uint2(e0.w, o0.w);
+            d[8] = make_uint2(e1.x, o1.x);
+            d[10] = make_uint2(e1.y, o1.y);
+            d[12] = make_uint2(e1.z, o1.z);
+            d[14] = make_uint2(e1.w, o1.w);
+        }
+    }
+};
 
 // AT / BT: the operand is in the saved-array layout (tm_idx, width 256) rather than
 // row-major [K][ld].
@@ -1198,7 +1298,7 @@ __device__ __forceinline__ uint4 kw_interleave4(uint4 x)
 // Consecutive workgroups are dealt to the eight XCDs in turn, so workgroup b runs on XCD
 // b % 8; the mapping gives every XCD whole batch splits (all tiles of split z on XCD z % 8),
 // so the tiles that share an operand run side by side and read it through one L2.
-template <int TM, int TN, int WAVES_M, bool AT, bool BT>
+template <int TM, int TN, int WAVES_M, bool AT, bool BT, int DEPTH>
 __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int lda, int M, const bf16_t *B, int ldb,
                                                           int N, int K, int kchunk, int tiles_x, int tiles_y,
                                                           float *C, int ldc, int64_t strideC, float *Cb)
@@ -1206,8 +1306,9 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
     constexpr int WAVES_N = 4 / WAVES_M;
     constexpr int BM = TM / WAVES_M / 32, BN = TN / WAVES_N / 32;
     static_assert(BM >= 1 && BN >= 1, "each wave holds at least one 32 x 32 block");
-    __shared__ __attribute__((aligned(16))) unsigned As[2][16][TM + KW_PAD];
-    __shared__ __attribute__((aligned(16))) unsigned Bs[2][16][TN + KW_PAD];
+    constexpr int SA = 4 * (TM + KW_PAD), SB = 4 * (TN + KW_PAD);   // dwords per LDS row (8 k)
+    __shared__ __attribute__((aligned(16))) unsigned As[2][4 * SA];
+    __shared__ __attribute__((aligned(16))) unsigned Bs[2][4 * SB];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w / WAVES_N, wn = w % WAVES_N;
     const int h = lane >> 5, r = lane & 31;
@@ -1220,151 +1321,96 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
     if (split > 0 && kbeg >= K) return;   // grid rounded up to whole splits per XCD
     const int kend = min(K, kbeg + kchunk);
     const int nsteps = kend > kbeg ? (kend - kbeg + 31) / 32 : 0;
-    // loader work items of one 32-deep K step, A then B: a row-major operand has 16 pair rows
-    // x width/8 column chunks (two 16-byte row loads each, eight pairs); a saved-array operand
-    // 16 pair rows x width/4 feature quads (one 16-byte load each, four pairs)
-    constexpr int CA = AT ? TM / 4 : TM / 8, CB = BT ? TN / 4 : TN / 8;
-    constexpr int NA = 16 * CA, NB = 16 * CB;
-    constexpr int PER = (NA + NB + 255) / 256;
-    // A saved-array operand's piece (kp, cc) is the (16 cc + kp)-th 16 bytes of a contiguous
-    // run; each wave takes 64 pieces (1 KB) of it, four cc by sixteen kp, and its lanes are
-    // ordered so that eight (and sixteen) neighbouring lanes write LDS rows kp, columns 4cc
-    // on distinct banks: lane 16 g + e takes kp = 8 (g & 1) + e / 2, cc = 4 G + 2 (g >> 1) + e % 2.
-    auto item = [&](int q, bool &isA, int &kp, int &cc) {
-        isA = q < NA;
-        const int qq = isA ? q : q - NA;
-        const int cw = isA ? CA : CB;
-        if (isA ? AT : BT) {
-            const int G = qq >> 6, l = qq & 63, e = l & 15, g = l >> 4;
-            kp = 8 * (g & 1) + (e >> 1);
-            cc = 4 * G + 2 * (g >> 1) + (e & 1);
-        } else {
-            kp = qq / cw;
-            cc = qq % cw;
-        }
-    };
-    // Element offset of load e of work item q at step k0, and whether it lies inside the
-    // operand (row below K, column below M or N).  Loads outside are still issued, from the
-    // operand's first element, and their values cleared at the LDS store: a load in a branch
-    // (or one whose value is changed as soon as it returns) makes the compiler wait for it
-    // before issuing the next.
-    auto where = [&](int q, int k0, int e, bool &ok) -> int64_t {
-        bool isA;
-        int kp, cc;
-        item(q, isA, kp, cc);
-        const int k = k0 + 2 * kp;
-        if (isA ? AT : BT) {
-            // the tile's 32 cells x width features are one contiguous run of the saved layout
-            // from tm_idx(k0, first feature); item (kp, cc) is its 16 * cc + kp-th 16-byte piece
-            // (cells 2kp, 2kp + 1, features 4cc .. 4cc + 3); the odd cell is checked at the store
-            ok = q < NA + NB && e == 0 && k < kend && (isA ? m0 : n0) + 4 * cc < (isA ? M : N);
-            return ok ? tm_idx(k0, isA ? m0 : n0) + 8 * (16 * cc + kp) : 0;
-        }
-        const int col = (isA ? m0 : n0) + 8 * cc;
-        ok = q < NA + NB && k + e < kend && col < (isA ? M : N);
-        return ok ? (int64_t)(k + e) * (isA ? lda : ldb) + col : 0;
-    };
-    auto load = [&](int k0, uint4 (&rx)[PER][2]) {
-#pragma unroll
-        for (int p = 0; p < PER; p++) {
-            const int q = t + 256 * p;
-            const bool tm = q < NA ? AT : BT;
-#pragma unroll
-            for (int e = 0; e < (AT && BT ? 1 : 2); e++) {
-                if (e == 1 && tm) continue;
-                bool ok;
-                const int64_t off = where(q, k0, e, ok);
-                rx[p][e] = *reinterpret_cast<const uint4 *>((q < NA ? A : B) + off);
-            }
-        }
-    };
-    auto store = [&](int buf, int k0, const uint4 (&rx)[PER][2]) {
-#pragma unroll
-        for (int p = 0; p < PER; p++) {
-            const int q = t + 256 * p;
-            if (q < NA + NB) {
-                bool isA;
-                int kp, cc;
-                item(q, isA, kp, cc);
-                bool ok0, ok1;
-                (void)where(q, k0, 0, ok0);
-                if (isA ? AT : BT) {
-                    uint4 v = ok0 ? rx[p][0] : make_uint4(0, 0, 0, 0);
-                    if (k0 + 2 * kp + 1 >= kend) v.z = v.w = 0u;   // the ragged end's odd cell
-                    unsigned *dst = isA ? &As[buf][kp][4 * cc] : &Bs[buf][kp][4 * cc];
-                    *reinterpret_cast<uint4 *>(dst) = kw_interleave4(v);
-                } else {
-                    (void)where(q, k0, 1, ok1);
-                    uint4 lo, hi;
-                    kw_interleave(ok0 ? rx[p][0] : make_uint4(0, 0, 0, 0), ok1 ? rx[p][1] : make_uint4(0, 0, 0, 0),
-                                  lo, hi);
-                    unsigned *dst = isA ? &As[buf][kp][8 * cc] : &Bs[buf][kp][8 * cc];
-                    *reinterpret_cast<uint4 *>(dst) = lo;
-                    *reinterpret_cast<uint4 *>(dst + 4) = hi;
-                }
-            }
-        }
-    };
+    const int jlast = max(nsteps - 1, 0);
+    const WgOperand<TM, AT> opA(A, lda, m0, M, kbeg, t);
+    const WgOperand<TN, BT> opB(B, ldb, n0, N, kbeg, t);
+
     f32x16 acc[BM][BN];
 #pragma unroll
     for (int i = 0; i < BM; i++)
 #pragma unroll
         for (int j = 0; j < BN; j++) acc[i][j] = f32x16{};
-    float csum = 0.f;
-    const bool colsum = Cb && bx == 0 && t < TM;
+    // bias gradient: the waves of the first column of the first column tile multiply their A
+    // fragments by ones
+    const bool colsum = Cb && bx == 0 && wn == 0;
+    f32x16 accb[BM];
+#pragma unroll
+    for (int i = 0; i < BM; i++) accb[i] = f32x16{};
+    const bf16x8 ones = __builtin_bit_cast(bf16x8, make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u));
     auto compute = [&](int buf) {
 #pragma unroll
         for (int kb = 0; kb < 2; kb++) {
+            const int kq = 2 * kb + h;   // this lane's k = 16 kb + 8 h .. + 7: LDS row kq
             bf16x8 af[BM], bfr[BN];
 #pragma unroll
-            for (int i = 0; i < BM; i++) {
-                const int col = (wm * BM + i) * 32 + r;
-                unsigned p[4];
+            for (int i = 0; i < BM; i++)
+                af[i] = *reinterpret_cast<const bf16x8 *>(&As[buf][kq * SA + 4 * ((wm * BM + i) * 32 + r)]);
 #pragma unroll
-                for (int j = 0; j < 4; j++) p[j] = As[buf][8 * kb + 4 * h + j][col];
-                af[i] = __builtin_bit_cast(bf16x8, make_uint4(p[0], p[1], p[2], p[3]));
-            }
-#pragma unroll
-            for (int i = 0; i < BN; i++) {
-                const int col = (wn * BN + i) * 32 + r;
-                unsigned p[4];
-#pragma unroll
-                for (int j = 0; j < 4; j++) p[j] = Bs[buf][8 * kb + 4 * h + j][col];
-                bfr[i] = __builtin_bit_cast(bf16x8, make_uint4(p[0], p[1], p[2], p[3]));
-            }
+            for (int i = 0; i < BN; i++)
+                bfr[i] = *reinterpret_cast<const bf16x8 *>(&Bs[buf][kq * SB + 4 * ((wn * BN + i) * 32 + r)]);
 #pragma unroll
             for (int i = 0; i < BM; i++)
 #pragma unroll
                 for (int j = 0; j < BN; j++) acc[i][j] = mfma32(af[i], bfr[j], acc[i][j]);
-        }
-        if (colsum) {
-            // column t of the A tile: 16 (k even, k odd) pairs of this step
+            if (colsum) {
 #pragma unroll
-            for (int kp = 0; kp < 16; kp++) {
-                const unsigned v = As[buf][kp][t];
-                csum += __builtin_bit_cast(float, v << 16);
-                csum += __builtin_bit_cast(float, v & 0xffff0000u);
+                for (int i = 0; i < BM; i++) accb[i] = mfma32(af[i], ones, accb[i]);
             }
         }
     };
-    // step i sits in LDS buffer i % 2; the loads of step i + 1 are in flight during step i's
-    // MFMAs.  Loads of a step past the range are issued too (they read the operand's first
-    // element and are cleared at the store), so that no load sits in a branch.
-    uint4 rx[PER][2];
-    load(kbeg, rx);
-    store(0, kbeg, rx);
-    __syncthreads();
-    int buf = 0;
-    for (int i = 0; i < nsteps; i++) {
-        const int k1 = kbeg + 32 * (i + 1);
-        load(k1, rx);
-        compute(buf);
-        if (i + 1 < nsteps) store(buf ^ 1, k1, rx);
-        __syncthreads();
-        buf ^= 1;
+    // Step j sits in LDS buffer j % 2 and, before that, in register set j % DEPTH: while step
+    // j's MFMAs run, the loads of steps j + 1 .. j + DEPTH are in flight (each step waits for
+    // its own loads only, which the in-order vmcnt allows), since one step's work is far
+    // shorter than a load's latency.  Steps past the range load the last step again and clear
+    // it at the store, so that no load sits in a branch.  The barrier waits for this wave's LDS
+    // accesses only; a fenced __syncthreads would also drain the loads in flight.
+    auto lds_barrier = [] {
+        __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0); vmcnt and expcnt left alone
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    };
+    auto load = [&](int j, uint4 (&ra)[4], uint4 (&rb)[4]) {
+        const int je = min(j, jlast);
+        opA.load(je, kbeg, kend, lda, ra);
+        opB.load(je, kbeg, kend, ldb, rb);
+    };
+    auto store = [&](int buf, int j, uint4 (&ra)[4], uint4 (&rb)[4]) {
+        const int nvalid = kend - (kbeg + 32 * j);
+        opA.template store<SA>(As[buf], nvalid, ra);
+        opB.template store<SB>(Bs[buf], nvalid, rb);
+    };
+    // The loop is unrolled DEPTH times, so that the register set (j % DEPTH) and the LDS buffer
+    // (j % 2) are constants, and runs whole rounds: the steps added at the end are cleared
+    // (both operands zero) and add exact zeros.  A branch inside the round would make the
+    // compiler move the accumulators at every iteration and drain the loads.
+    static_assert(DEPTH % 2 == 0, "an even prefetch depth keeps the LDS buffer of a step constant");
+    uint4 ra[DEPTH][4], rb[DEPTH][4];
+#pragma unroll
+    for (int d = 0; d < DEPTH; d++) load(d, ra[d], rb[d]);
+    store(0, 0, ra[0], rb[0]);
+    lds_barrier();
+    for (int j0 = 0; j0 < nsteps; j0 += DEPTH) {
+#pragma unroll
+        for (int d = 0; d < DEPTH; d++) {
+            const int j = j0 + d;
+            load(j + DEPTH, ra[d], rb[d]);
+            compute(d & 1);
+            store((d + 1) & 1, j + 1, ra[(d + 1) % DEPTH], rb[(d + 1) % DEPTH]);
+            lds_barrier();
+        }
     }
-    if (colsum && m0 + t < M) Cb[split * strideC + m0 + t] = csum;
-    // C layout of the 32 x 32 blocks: column = lane % 32 (n), rows 8q + 4h + (0..3) (m)
+    // C layout of the 32 x 32 blocks: column = lane % 32 (n), rows 8q + 4h + (0..3) (m); every
+    // column of a ones product holds the same sums
+    if (colsum && r == 0) {
+#pragma unroll
+        for (int i = 0; i < BM; i++)
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int m = m0 + (wm * BM + i) * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+                if (m < M) Cb[split * strideC + m] = accb[i][v];
+            }
+    }
     float *Cz = C + split * strideC;
 #pragma unroll
     for (int i = 0; i < BM; i++)
@@ -1536,7 +1582,7 @@ static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
 // (16, 256) (output layer) on 32 x 128 tiles in SPLIT_IO splits.  Split z writes its W
 // partials at part + z (O I + O) and its bias partials right after them, so one ordered
 // reduction gives W and b, which are adjacent in the master.
-template <int TM, int TN, int WAVES_M, bool AT, bool BT>
+template <int TM, int TN, int WAVES_M, bool AT, bool BT, int DEPTH>
 static void launch_wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, int nsplit, float *part,
                          int &splits, hipStream_t s)
 {
@@ -1545,7 +1591,7 @@ static void launch_wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n
     const int tiles_x = (I + TN - 1) / TN, tiles_y = (O + TM - 1) / TM;
     const int grid = tiles_x * tiles_y * ((splits + 7) / 8 * 8);
     const int64_t stride = (int64_t)O * I + O;
-    hipLaunchKernelGGL((gemm_wgrad_kernel<TM, TN, WAVES_M, AT, BT>), dim3(grid), dim3(256), 0, s, dz, O, O, hp, I, I,
+    hipLaunchKernelGGL((gemm_wgrad_kernel<TM, TN, WAVES_M, AT, BT, DEPTH>), dim3(grid), dim3(256), 0, s, dz, O, O, hp, I, I,
                        n, kchunk, tiles_x, tiles_y, part, I, stride, part + (int64_t)O * I);
 }
 
@@ -1554,11 +1600,11 @@ static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float 
     // hidden layers: both operands in the saved-array layout; layer 0: dz saved, the inputs
     // row-major [n][32]; output layer: dz row-major [n][16], h saved
     if (O % 128 == 0 && I % 128 == 0)
-        launch_wgrad<128, 128, 2, true, true>(dz, O, hp, I, n, SPLIT_HID, part, splits, s);
+        launch_wgrad<128, 128, 2, true, true, WG_DEPTH>(dz, O, hp, I, n, SPLIT_HID, part, splits, s);
     else if (O % 128 == 0 && I == 32)
-        launch_wgrad<128, 32, 4, true, false>(dz, O, hp, I, n, SPLIT_IO, part, splits, s);
+        launch_wgrad<128, 32, 4, true, false, WG_DEPTH>(dz, O, hp, I, n, SPLIT_IO, part, splits, s);
     else if (O <= 32 && O % 8 == 0 && I % 128 == 0)
-        launch_wgrad<32, 128, 1, false, true>(dz, O, hp, I, n, SPLIT_IO, part, splits, s);
+        launch_wgrad<32, 128, 1, false, true, WG_DEPTH>(dz, O, hp, I, n, SPLIT_IO, part, splits, s);
     else
         return fail(PROPS_EINVAL, "wgrad: unsupported layer shape %d x %d", O, I);
     PROPS_HIP_TRY(hipGetLastError());

@@ -73,16 +73,17 @@ FWD_MAX, FWD_RMS = 5e-4, 1e-5
 # Gradients, element by element.  Each gradient element is a sum of n terms dz[r, j] h[r, i]
 # accumulated in FP32 on the matrix cores (and split over the batch); against the exact sum
 # its rounding is bounded by about K' u S, S the sum of the terms' magnitudes, u = 2^-24 and
-# K' the depth of the summation (<= 2^7 here: 16-term matrix-core steps, 32-row K steps,
-# 128 splits summed in order): 2^-16 S covers it with room.  Besides, both factors of a term
-# are bf16 values rounded from FP32 results (the back-propagated dz from FP32 sums, the
-# activation h from the FP32 pre-activation) that the oracle computes exactly, so either can
-# land on the other side of a bf16 rounding boundary: a flip of one bf16 step, at most 2^-7
-# relative, so a term moves by at most 2^-6 of itself.  Near the output flips are rare, but
-# a flip moves its whole row of the next dz by about 2^-12 relative, so further down they
-# multiply; bounding the flip probability by 1, with independent signs, the flips of a sum
-# have a standard deviation of at most 2^-6 sqrt(Q), Q = sum_r (dz[r, j] h[r, i])^2; the
-# bar takes six of them.
+# K' the depth of the summation: the 16-term matrix-core steps of one batch split, then the
+# splits summed in order, at most 64 + 64 (hidden layers) or 32 + 128 (input and output
+# layers) = 160 at the batch of 65,536, so K' u < 2^-16.6 and 2^-16 S covers it.  Besides,
+# both factors of a term are bf16 values rounded from FP32 results (the back-propagated dz
+# from FP32 sums, the activation h from the FP32 pre-activation) that the oracle computes
+# exactly, so either can land on the other side of a bf16 rounding boundary: a flip of one
+# bf16 step, at most 2^-7 relative, so a term moves by at most 2^-6 of itself.  Near the
+# output flips are rare, but a flip moves its whole row of the next dz by about 2^-12
+# relative, so further down they multiply; bounding the flip probability by 1, with
+# independent signs, the flips of a sum have a standard deviation of at most 2^-6 sqrt(Q), Q =
+# sum_r (dz[r, j] h[r, i])^2; the bar takes six of them.
 GRAD_REL_S = 2.0 ** -16
 
 
@@ -141,8 +142,8 @@ def test_forward_matches_bf16_oracle_several_tiles_with_fallback(props, orc, sp8
 @pytest.mark.parametrize("mask,n", [(0x35, 65536), (0x3F, 8192), (0x00, 8192)])
 def test_gradient_matches_bf16_oracle_elementwise(props, orc, sp8, mask, n):
     """The L1 gradient on the scaled targets, every weight and bias element against the
-    bf16-emulating oracle, at the training batch of 65,536 (the 128-way split of the
-    weight-gradient GEMMs at full depth) for the default log outputs (rho, cp, mu, lambda),
+    bf16-emulating oracle, at the training batch of 65,536 (every weight-gradient GEMM at its
+    full split count and depth) for the default log outputs (rho, cp, mu, lambda),
     and for networks that log-transform all or none of their outputs."""
     X, L = labelled_states(orc, sp8, n, seed=32)
     if mask == 0x3F:
