@@ -1041,23 +1041,27 @@ __device__ __forceinline__ void put_bias(bf16_t *fused, int l, int o, float bv)
     dst[2] = lo;
 }
 
-// One thread per four master parameters e .. e + 3 (layer sizes and offsets are multiples of
-// four): the gradient g = sum_z part_z[e] over the splits in order z = 0, 1, ... (a
-// deterministic split-K reduction).  Without Adam, g is written to grad.  With Adam: the moments and the
-// FP32 master take the step
+// Four lanes per four master parameters e .. e + 3 (layer sizes and offsets are multiples of
+// four): lane r of the group sums the splits z = r, r + 4, r + 8, ... in order (16-byte
+// loads, sixteen in flight), and the four lane sums are added as (s0 + s1) + (s2 + s3), the
+// same expression in every lane of the group, so the gradient g = sum_z part_z[e] is one
+// fixed-order, deterministic split-K reduction.  Then lane r takes parameter e + r.  Without
+// Adam, g is written to grad.  With Adam: the moments and the FP32 master take the step
 //   m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,  w -= lr (m / bc1) / (sqrt(v / bc2) + eps)
 // (bc1, bc2: the bias corrections 1 - b^t), and the new weight goes straight to its bf16 copies.
-// Parameters per thread and partials in flight: four and sixteen measured 35 us per training
-// step, against 40 us for two and sixteen, 39 us for two and thirty-two.
-constexpr int GS_VEC = 4, GS_BATCH = 16, GS_THREADS = 256;
+// One lane per four parameters, summing every split, took 23 us per training step (about
+// 800 waves on the 1024 SIMDs, each with a long serial chain of loads).
+constexpr int GS_VEC = 4, GS_BATCH = 16, GS_THREADS = 256, GS_LANES = 4;
 typedef float gs_vec_t __attribute__((ext_vector_type(GS_VEC)));
 __global__ __launch_bounds__(GS_THREADS) void grad_step_kernel(GradParts L, int nh, float *grad, float *w, float *m,
                                                         float *v, bf16_t *fused, bf16_t *bwd, int adam, float lr,
                                                         float b1, float b2, float eps, float bc1, float bc2)
 {
-    constexpr int VEC = GS_VEC, NB = GS_BATCH;
-    const int64_t e0 = VEC * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
-    if (e0 >= L.off[L.nl]) return;
+    constexpr int VEC = GS_VEC, NB = GS_BATCH, R = GS_LANES;
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = (int)(tid % R);
+    const int64_t e0 = VEC * (tid / R);
+    if (e0 >= L.off[L.nl]) return;   // whole groups of R lanes leave together
     int l = 0;
     while (l + 1 < L.nl && e0 >= L.off[l + 1]) l++;
     const int64_t i0 = e0 - L.off[l], cnt = L.off[l + 1] - L.off[l];
@@ -1065,39 +1069,44 @@ __global__ __launch_bounds__(GS_THREADS) void grad_step_kernel(GradParts L, int 
     const int64_t zs = cnt / VEC;
     const int S = L.splits[l];
     float g[VEC] = {};
-    int z = 0;
-    for (; z + NB <= S; z += NB) {   // NB partials in flight, summed in order
+    int z = r;
+    for (; z + R * (NB - 1) < S; z += R * NB) {   // NB partials in flight, summed in order
         gs_vec_t pv[NB];
 #pragma unroll
-        for (int j = 0; j < NB; j++) pv[j] = __builtin_nontemporal_load(src + (z + j) * zs);
+        for (int j = 0; j < NB; j++) pv[j] = __builtin_nontemporal_load(src + (z + R * j) * zs);
 #pragma unroll
         for (int j = 0; j < NB; j++)
 #pragma unroll
             for (int u = 0; u < VEC; u++) g[u] += pv[j][u];
     }
-    for (; z < S; z++) {
-        const gs_vec_t pv = src[z * zs];
+    for (; z < S; z += R) {
+        const gs_vec_t pv = __builtin_nontemporal_load(src + z * zs);
 #pragma unroll
         for (int u = 0; u < VEC; u++) g[u] += pv[u];
     }
-    if (!adam) {
+    // (s0 + s1) + (s2 + s3) in every lane: the xor-1 partner's sum first, then the xor-2
+    // partner's pair sum (addition commutes exactly, so the four lanes agree bit for bit)
+    static_assert(R == 4, "the butterfly below adds four lanes");
 #pragma unroll
-        for (int u = 0; u < VEC; u++) grad[e0 + u] = g[u];
+    for (int u = 0; u < VEC; u++) {
+        g[u] += __shfl_xor(g[u], 1);
+        g[u] += __shfl_xor(g[u], 2);
+    }
+    const float gr = r == 0 ? g[0] : r == 1 ? g[1] : r == 2 ? g[2] : g[3];
+    const int64_t e = e0 + r, i = i0 + r;
+    if (!adam) {
+        grad[e] = gr;
         return;
     }
     const int64_t nwt = (int64_t)lout(l, nh) * lin(l);
-#pragma unroll
-    for (int u = 0; u < VEC; u++) {
-        const int64_t e = e0 + u, i = i0 + u;
-        const float mi = b1 * m[e] + (1.f - b1) * g[u];
-        const float vi = b2 * v[e] + (1.f - b2) * g[u] * g[u];
-        m[e] = mi;
-        v[e] = vi;
-        const float wn = w[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-        w[e] = wn;
-        if (i < nwt) put_weight(fused, bwd, l, nh, i, wn);
-        else put_bias(fused, l, (int)(i - nwt), wn);
-    }
+    const float mi = b1 * m[e] + (1.f - b1) * gr;
+    const float vi = b2 * v[e] + (1.f - b2) * gr * gr;
+    m[e] = mi;
+    v[e] = vi;
+    const float wn = w[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[e] = wn;
+    if (i < nwt) put_weight(fused, bwd, l, nh, i, wn);
+    else put_bias(fused, l, (int)(i - nwt), wn);
 }
 
 // FP32 master -> its bf16 copies (the forward's fused layout with the biases, the
@@ -1676,7 +1685,8 @@ static int grad_step(props_dnn_s *d, bool adam, float lr, float b1, float b2, fl
                      hipStream_t s)
 {
     const int64_t P = d->gp.off[d->gp.nl];
-    hipLaunchKernelGGL(grad_step_kernel, dim3((unsigned)((P / GS_VEC + GS_THREADS - 1) / GS_THREADS)), dim3(GS_THREADS), 0, s, d->gp, d->nhid, d->grad,
+    const int64_t threads = P / GS_VEC * GS_LANES;
+    hipLaunchKernelGGL(grad_step_kernel, dim3((unsigned)((threads + GS_THREADS - 1) / GS_THREADS)), dim3(GS_THREADS), 0, s, d->gp, d->nhid, d->grad,
                        d->master, d->m, d->v, d->fused, d->bwd, (int)adam, lr, b1, b2, eps, bc1, bc2);
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
