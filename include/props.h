@@ -295,7 +295,8 @@ typedef struct {
 /* Train with the L1 loss of Section 4.3 (the mean absolute error over the network's outputs)
  * and Adam.  X: device float [10][n] raw inputs (P, T, Y_1..8 for the default network),
  * feature-major; Y: device float [outputs][n] raw targets (rho, h, cp, c, mu, lambda for the
- * default network).
+ * default network).  The call allocates a device copy of the set as 64-byte sample rows (n x 64
+ * bytes, freed before it returns), from which the per-epoch permutation reads.
  * Blocking: returns when training is done (synchronises hip_stream once per epoch). */
 int train_dnn(props_dnn_t net, const float *X, const float *Y, int64_t n,
               const props_train_cfg *cfg, props_train_report *rep, void *hip_stream);

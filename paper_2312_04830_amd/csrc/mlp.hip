@@ -68,6 +68,9 @@ constexpr int LDS_BYTES = NRING * 2 * SLOT_BYTES;         // 101,376 B per workg
 constexpr int L0_BYTES = HID * IROW * 2;                  // layer 0 whole: 12,288 B, one slot
 static_assert(L0_BYTES <= SLOT_BYTES, "layer 0 fits one slot");
 constexpr int MAX_BATCH = 65536;
+// floats per training sample row: the inputs, the targets, padding to 64 bytes
+constexpr int SAMPLE_FLOATS = 16;
+static_assert(NIN + NOUT <= SAMPLE_FLOATS, "a sample row holds the inputs and the targets");
 // Batch splits of the weight-gradient GEMMs (multiples of 8) and the prefetch depth of their
 // loaders, in 32-cell steps.  Fewer splits write and reduce fewer FP32 partials but give each
 // workgroup a longer serial walk; on a 65,536 batch 64 splits of the 256 x 256 layers (256
@@ -192,9 +195,9 @@ struct FwdArgs {
     // inference inputs (SoA doubles, species rows ldy apart) ...
     const double *P, *T, *Y;
     int64_t ldy;
-    // ... or training inputs (feature-major float [10][nx]) and raw targets ([6][nx]) with
-    // the epoch permutation
-    const float *X, *Yt;
+    // ... or the training set, one 64-byte sample per row ([nx][16] float: the 10 inputs, the
+    // raw targets, zeros), read in the order of the epoch permutation
+    const float *XY;
     int64_t nx;
     uint64_t pa, pc;
     int64_t row0;        // first permuted row of this batch
@@ -481,8 +484,12 @@ template <bool TRAIN>
 __device__ __forceinline__ void load_inputs(const FwdArgs &a, int64_t cell, int64_t sidx, RawIn<TRAIN> &r)
 {
     if (TRAIN) {
-#pragma unroll
-        for (int f = 0; f < NIN; f++) r.x[f] = a.X[(int64_t)f * a.nx + sidx];
+        // a permuted sample is one 64-byte row: its inputs are three 16-byte loads
+        const float4 *p = reinterpret_cast<const float4 *>(a.XY + SAMPLE_FLOATS * sidx);
+        const float4 v0 = p[0], v1 = p[1], v2 = p[2];
+        r.x[0] = v0.x, r.x[1] = v0.y, r.x[2] = v0.z, r.x[3] = v0.w;
+        r.x[4] = v1.x, r.x[5] = v1.y, r.x[6] = v1.z, r.x[7] = v1.w;
+        r.x[8] = v2.x, r.x[9] = v2.y;
     } else if (a.Xd) {
 #pragma unroll
         for (int f = 0; f < NIN; f++) r.x[f] = a.Xd[(int64_t)f * a.n + cell];
@@ -501,7 +508,7 @@ __device__ __forceinline__ void load_targets(const FwdArgs &a, int64_t sidx, int
 #pragma unroll
     for (int r = 0; r < 4; r++) {
         const int j = 4 * h + r;
-        t[r] = j < a.nout ? a.Yt[(int64_t)j * a.nx + sidx] : 0.0f;
+        t[r] = j < a.nout ? a.XY[SAMPLE_FLOATS * sidx + NIN + j] : 0.0f;
     }
 }
 
@@ -1620,17 +1627,57 @@ static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float 
     return PROPS_OK;
 }
 
+// The training set as rows of SAMPLE_FLOATS floats (inputs, targets, zeros): the epoch
+// permutation then reads one 64-byte row per sample instead of a 4-byte value from each of the
+// sixteen feature-major rows (sixteen cache lines).
+__global__ void pack_samples_kernel(const float *X, const float *Y, int64_t n, int nout, float *XY)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v[SAMPLE_FLOATS];
+#pragma unroll
+    for (int f = 0; f < SAMPLE_FLOATS; f++) {
+        const int j = f - NIN;
+        v[f] = f < NIN ? X[(int64_t)f * n + i] : j < nout ? Y[(int64_t)j * n + i] : 0.0f;
+    }
+    float4 *dst = reinterpret_cast<float4 *>(XY + SAMPLE_FLOATS * i);
+#pragma unroll
+    for (int q = 0; q < SAMPLE_FLOATS / 4; q++) dst[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+
+// frees a device allocation when the entry point returns (hipFree waits for the device)
+struct DevFree {
+    void *p;
+    ~DevFree()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+static int pack_samples(const float *X, const float *Y, int64_t n, int nout, float **xy, hipStream_t s)
+{
+    int rc;
+    if ((rc = dalloc(xy, (size_t)n * SAMPLE_FLOATS))) return rc;
+    hipLaunchKernelGGL(pack_samples_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, Y, n, nout, *xy);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        (void)hipFree(*xy);
+        *xy = nullptr;
+        return fail(PROPS_EHIP, "pack_samples: %s", hipGetErrorString(e));
+    }
+    return PROPS_OK;
+}
+
 // One forward + backward pass over rows [row0, row0 + n) of the permuted data; leaves each
 // layer's split-K gradient partials (d->gp, reduced by grad_step) and the loss partials (one
 // per wave of 32 rows) in lpart.
-static int fwd_bwd(props_dnn_s *d, const float *X, const float *Y, int64_t nx, uint64_t pa, uint64_t pc,
-                   int64_t row0, int n, float *lpart, hipStream_t s)
+static int fwd_bwd(props_dnn_s *d, const float *XY, int64_t nx, uint64_t pa, uint64_t pc, int64_t row0, int n,
+                   float *lpart, hipStream_t s)
 {
     int rc;
     const int nh = d->nhid;
     FwdArgs a{};
-    a.X = X;
-    a.Yt = Y;
+    a.XY = XY;
     a.nx = nx;
     a.pa = pa;
     a.pc = pc;
@@ -2035,7 +2082,10 @@ int props_dnn_grad(props_dnn_t d, const float *X, const float *Y, int64_t n, flo
     hipStream_t s = (hipStream_t)hip_stream;
     int rc;
     if ((rc = ensure_train_scratch(d))) return rc;
-    if ((rc = fwd_bwd(d, X, Y, n, 1, 0, 0, (int)n, d->lpart, s))) return rc;
+    float *xy = nullptr;
+    if ((rc = pack_samples(X, Y, n, d->nout, &xy, s))) return rc;
+    const DevFree xy_free{xy};
+    if ((rc = fwd_bwd(d, xy, n, 1, 0, 0, (int)n, d->lpart, s))) return rc;
     if ((rc = grad_step(d, false, 0.f, 0.f, 0.f, 0.f, 1.f, 1.f, s))) return rc;
     const int nh = d->nhid;
     const size_t nw = (size_t)((n + TILE_CELLS - 1) / TILE_CELLS) * FWD_WAVES;
@@ -2068,6 +2118,9 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
     auto t0 = std::chrono::steady_clock::now();
     if ((rc = ensure_train_scratch(d))) return rc;
     if (cfg->fit_scalers && (rc = fit_scalers_dev(d, X, Y, n, s))) return rc;
+    float *xy = nullptr;
+    if ((rc = pack_samples(X, Y, n, d->nout, &xy, s))) return rc;
+    const DevFree xy_free{xy};
     const int total = cfg->total_epochs > 0 ? cfg->total_epochs : std::max(1, d->epoch + cfg->epochs);
     const float b1 = cfg->beta1 > 0 ? cfg->beta1 : 0.9f, b2 = cfg->beta2 > 0 ? cfg->beta2 : 0.999f;
     const float eps = cfg->eps > 0 ? cfg->eps : 1e-8f;
@@ -2088,7 +2141,7 @@ int train_dnn(props_dnn_t d, const float *X, const float *Y, int64_t n, const pr
             const int64_t row0 = st * batch;
             const int m = (int)std::min<int64_t>(batch, n - row0);
             // the loss partials go straight to this step's slots of the epoch's array
-            if ((rc = fwd_bwd(d, X, Y, n, pa, pc, row0, m, lsum + st * lslots, s))) {
+            if ((rc = fwd_bwd(d, xy, n, pa, pc, row0, m, lsum + st * lslots, s))) {
                 (void)hipFree(lsum);
                 return rc;
             }
