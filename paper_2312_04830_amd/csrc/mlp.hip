@@ -73,9 +73,10 @@ constexpr int SAMPLE_FLOATS = 16;
 static_assert(NIN + NOUT <= SAMPLE_FLOATS, "a sample row holds the inputs and the targets");
 // Batch splits of the weight-gradient GEMMs (multiples of 8) and the prefetch depth of their
 // loaders, in 32-cell steps.  Fewer splits write and reduce fewer FP32 partials but give each
-// workgroup a longer serial walk; on a 65,536 batch 64 splits of the 256 x 256 layers (256
-// workgroups, 32 steps each) take 24 us, and 128 splits of the input and output layers 13 us.
-constexpr int SPLIT_HID = 64;
+// workgroup a longer serial walk; on a 65,536 batch the three 256 x 256 layers in one launch
+// take 63 us with 64 splits each (768 workgroups of 32 steps) and training runs 2.5 % faster
+// with 32, 7 % slower with 128; 128 splits of the input and output layers take 13-14 us each.
+constexpr int SPLIT_HID = 32;
 constexpr int SPLIT_IO = 128;
 constexpr int WG_DEPTH = 4;
 
@@ -1314,11 +1315,24 @@ struct WgOperand {
 // Consecutive workgroups are dealt to the eight XCDs in turn, so workgroup b runs on XCD
 // b % 8; the mapping gives every XCD whole batch splits (all tiles of split z on XCD z % 8),
 // so the tiles that share an operand run side by side and read it through one L2.
+//
+// Layers of one shape share a launch: workgroup b works on layer b / per_layer (per_layer a
+// multiple of 8, so the XCD mapping within each layer is unchanged), and the three hidden
+// layers' GEMMs fill the machine together instead of each ending on its own tail.
+struct WgLayers {
+    const bf16_t *A[MAX_HIDDEN];
+    const bf16_t *B[MAX_HIDDEN];
+    float *C[MAX_HIDDEN];   // partials of split z at C + z strideC, the bias row right after
+};
+
 template <int TM, int TN, int WAVES_M, bool AT, bool BT, int DEPTH>
-__global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int lda, int M, const bf16_t *B, int ldb,
-                                                          int N, int K, int kchunk, int tiles_x, int tiles_y,
-                                                          float *C, int ldc, int64_t strideC, float *Cb)
+__global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgLayers L, int per_layer, int lda, int M, int ldb, int N,
+                                                          int K, int kchunk, int tiles_x, int tiles_y, int ldc,
+                                                          int64_t strideC)
 {
+    const int layer = blockIdx.x / per_layer;
+    const bf16_t *A = L.A[layer], *B = L.B[layer];
+    float *C = L.C[layer], *Cb = C + (int64_t)M * ldc;
     constexpr int WAVES_N = 4 / WAVES_M;
     constexpr int BM = TM / WAVES_M / 32, BN = TN / WAVES_N / 32;
     static_assert(BM >= 1 && BN >= 1, "each wave holds at least one 32 x 32 block");
@@ -1329,7 +1343,7 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(const bf16_t *A, int ld
     const int wm = w / WAVES_N, wn = w % WAVES_N;
     const int h = lane >> 5, r = lane & 31;
     const int ntile = tiles_x * tiles_y;
-    const int bid = blockIdx.x, slot = bid >> 3;
+    const int bid = blockIdx.x - layer * per_layer, slot = bid >> 3;
     const int tile = slot % ntile, split = (slot / ntile) * 8 + (bid & 7);
     const int bx = tile % tiles_x, by = tile / tiles_x;
     const int m0 = by * TM, n0 = bx * TN;
@@ -1599,32 +1613,41 @@ static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
 // partials at part + z (O I + O) and its bias partials right after them, so one ordered
 // reduction gives W and b, which are adjacent in the master.
 template <int TM, int TN, int WAVES_M, bool AT, bool BT, int DEPTH>
-static void launch_wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, int nsplit, float *part,
-                         int &splits, hipStream_t s)
+static void launch_wgrad(const WgLayers &L, int nl, int O, int I, int n, int nsplit, int &splits, hipStream_t s)
 {
     const int kchunk = ((n + nsplit - 1) / nsplit + 31) / 32 * 32;
     splits = (n + kchunk - 1) / kchunk;
     const int tiles_x = (I + TN - 1) / TN, tiles_y = (O + TM - 1) / TM;
-    const int grid = tiles_x * tiles_y * ((splits + 7) / 8 * 8);
+    const int per_layer = tiles_x * tiles_y * ((splits + 7) / 8 * 8);
     const int64_t stride = (int64_t)O * I + O;
-    hipLaunchKernelGGL((gemm_wgrad_kernel<TM, TN, WAVES_M, AT, BT, DEPTH>), dim3(grid), dim3(256), 0, s, dz, O, O, hp, I, I,
-                       n, kchunk, tiles_x, tiles_y, part, I, stride, part + (int64_t)O * I);
+    hipLaunchKernelGGL((gemm_wgrad_kernel<TM, TN, WAVES_M, AT, BT, DEPTH>), dim3(per_layer * nl), dim3(256), 0, s, L,
+                       per_layer, O, O, I, I, n, kchunk, tiles_x, tiles_y, I, stride);
 }
 
-static int wgrad(const bf16_t *dz, int O, const bf16_t *hp, int I, int n, float *part, int &splits, hipStream_t s)
+// nl layers of one shape O x I in one launch (dz of layer j in L.A[j], its inputs in L.B[j],
+// its partials at L.C[j])
+static int wgrad(const WgLayers &L, int nl, int O, int I, int n, int &splits, hipStream_t s)
 {
     // hidden layers: both operands in the saved-array layout; layer 0: dz saved, the inputs
     // row-major [n][32]; output layer: dz row-major [n][16], h saved
     if (O % 128 == 0 && I % 128 == 0)
-        launch_wgrad<128, 128, 2, true, true, WG_DEPTH>(dz, O, hp, I, n, SPLIT_HID, part, splits, s);
+        launch_wgrad<128, 128, 2, true, true, WG_DEPTH>(L, nl, O, I, n, SPLIT_HID, splits, s);
     else if (O % 128 == 0 && I == 32)
-        launch_wgrad<128, 32, 4, true, false, WG_DEPTH>(dz, O, hp, I, n, SPLIT_IO, part, splits, s);
+        launch_wgrad<128, 32, 4, true, false, WG_DEPTH>(L, nl, O, I, n, SPLIT_IO, splits, s);
     else if (O <= 32 && O % 8 == 0 && I % 128 == 0)
-        launch_wgrad<32, 128, 1, false, true, WG_DEPTH>(dz, O, hp, I, n, SPLIT_IO, part, splits, s);
+        launch_wgrad<32, 128, 1, false, true, WG_DEPTH>(L, nl, O, I, n, SPLIT_IO, splits, s);
     else
         return fail(PROPS_EINVAL, "wgrad: unsupported layer shape %d x %d", O, I);
     PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
+}
+
+// the number of batch splits wgrad uses for a layer of O x I on n rows
+static int wgrad_splits(int O, int I, int n)
+{
+    const int nsplit = (O % 128 == 0 && I % 128 == 0) ? SPLIT_HID : SPLIT_IO;
+    const int kchunk = ((n + nsplit - 1) / nsplit + 31) / 32 * 32;
+    return (n + kchunk - 1) / kchunk;
 }
 
 // The training set as rows of SAMPLE_FLOATS floats (inputs, targets, zeros): the epoch
@@ -1708,20 +1731,31 @@ static int fwd_bwd(props_dnn_s *d, const float *XY, int64_t nx, uint64_t pa, uin
     bw.nhid = nh;
     if ((rc = launch_bwd(bw, s))) return rc;
     // weight and bias gradients, output layer to input: dW_l = dz_l^T h_{l-1}, db_l = sum dz_l
-    // (M = O, N = I, K = n), split over the batch; the partials stay for grad_step
-    float *pl = d->part;
+    // (M = O, N = I, K = n), split over the batch; the partials stay for grad_step, laid out
+    // output layer first
+    float *pl = d->part, *lpart_of[MAX_HIDDEN + 1];
     d->gp.nl = nh + 1;
     for (int l = 0; l <= nh; l++) d->gp.off[l] = (int64_t)w_off(l);
     d->gp.off[nh + 1] = (int64_t)total_params(nh);
     for (int l = nh; l >= 0; l--) {
         const int O = lout(l, nh), I = lin(l);
-        const bf16_t *dzl = (l == nh) ? d->dzo : d->zs[l];
-        const bf16_t *hprev = (l == 0) ? d->h0 : d->hs[l - 1];
+        d->gp.part[l] = lpart_of[l] = pl;
+        d->gp.splits[l] = wgrad_splits(O, I, n);
+        pl += (size_t)d->gp.splits[l] * ((size_t)O * I + O);
+    }
+    // output layer, the hidden layers together, input layer
+    const int groups[3][2] = {{nh, nh}, {nh - 1, 1}, {0, 0}};   // layers hi .. lo of each launch
+    for (const auto &gr : groups) {
+        WgLayers L{};
+        int nl = 0;
+        for (int l = gr[0]; l >= gr[1]; l--, nl++) {
+            L.A[nl] = (l == nh) ? d->dzo : d->zs[l];
+            L.B[nl] = (l == 0) ? d->h0 : d->hs[l - 1];
+            L.C[nl] = lpart_of[l];
+        }
         int splits = 0;
-        if ((rc = wgrad(dzl, O, hprev, I, n, pl, splits, s))) return rc;
-        d->gp.part[l] = pl;
-        d->gp.splits[l] = splits;
-        pl += (size_t)splits * ((size_t)O * I + O);
+        if ((rc = wgrad(L, nl, lout(gr[0], nh), lin(gr[0]), n, splits, s))) return rc;
+        if (splits != d->gp.splits[gr[0]]) return fail(PROPS_EINVAL, "wgrad: split count mismatch");
     }
     return PROPS_OK;
 }

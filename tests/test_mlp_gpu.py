@@ -74,8 +74,9 @@ FWD_MAX, FWD_RMS = 5e-4, 1e-5
 # accumulated in FP32 on the matrix cores (and split over the batch); against the exact sum
 # its rounding is bounded by about K' u S, S the sum of the terms' magnitudes, u = 2^-24 and
 # K' the depth of the summation: the 16-term matrix-core steps of one batch split, then the
-# splits summed in order, at most 64 + 64 (hidden layers) or 32 + 128 (input and output
-# layers) = 160 at the batch of 65,536, so K' u < 2^-16.6 and 2^-16 S covers it.  Besides,
+# split sums (each lane of the reduction adds every fourth split, and two butterfly steps add
+# the four lanes): at most 128 + 10 (hidden layers, 32 splits) or 32 + 34 (input and output
+# layers, 128 splits) at the batch of 65,536, so K' u < 2^-16.8 and 2^-16 S covers it.  Besides,
 # both factors of a term are bf16 values rounded from FP32 results (the back-propagated dz
 # from FP32 sums, the activation h from the FP32 pre-activation) that the oracle computes
 # exactly, so either can land on the other side of a bf16 rounding boundary: a flip of one
