@@ -1316,34 +1316,43 @@ struct WgOperand {
 // b % 8; the mapping gives every XCD whole batch splits (all tiles of split z on XCD z % 8),
 // so the tiles that share an operand run side by side and read it through one L2.
 //
-// Layers of one shape share a launch: workgroup b works on layer b / per_layer (per_layer a
-// multiple of 8, so the XCD mapping within each layer is unchanged), and the three hidden
-// layers' GEMMs fill the machine together instead of each ending on its own tail.
-struct WgLayers {
+// One launch covers every layer: the hidden layers (one shape), then the input and the output
+// layer.  Within a shape group, workgroup b works on layer b / per_layer (per_layer a
+// multiple of 8, so the XCD mapping within each layer is unchanged); the groups' block ranges
+// follow each other, the long hidden-layer workgroups first, so the layers fill the machine
+// together instead of each launch ending on its own tail.
+struct WgGroup {
     const bf16_t *A[MAX_HIDDEN];
     const bf16_t *B[MAX_HIDDEN];
     float *C[MAX_HIDDEN];   // partials of split z at C + z strideC, the bias row right after
+    int per_layer, end;     // workgroups per layer; the group's block range ends at `end`
+    int lda, M, ldb, N, K, kchunk, tiles_x, tiles_y, ldc;
+    int64_t strideC;
+};
+struct WgLaunch {
+    WgGroup g[3];           // hidden layers, input layer, output layer
 };
 
 template <int TM, int TN, int WAVES_M, bool AT, bool BT, int DEPTH>
-__global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgLayers L, int per_layer, int lda, int M, int ldb, int N,
-                                                          int K, int kchunk, int tiles_x, int tiles_y, int ldc,
-                                                          int64_t strideC)
+__device__ __forceinline__ void wgrad_tile(const WgGroup &G, int b, unsigned *lds)
 {
-    const int layer = blockIdx.x / per_layer;
-    const bf16_t *A = L.A[layer], *B = L.B[layer];
-    float *C = L.C[layer], *Cb = C + (int64_t)M * ldc;
+    const int per_layer = G.per_layer, lda = G.lda, M = G.M, ldb = G.ldb, N = G.N, K = G.K;
+    const int kchunk = G.kchunk, tiles_x = G.tiles_x, tiles_y = G.tiles_y, ldc = G.ldc;
+    const int64_t strideC = G.strideC;
+    const int layer = b / per_layer;
+    const bf16_t *A = G.A[layer], *B = G.B[layer];
+    float *C = G.C[layer], *Cb = C + (int64_t)M * ldc;
     constexpr int WAVES_N = 4 / WAVES_M;
     constexpr int BM = TM / WAVES_M / 32, BN = TN / WAVES_N / 32;
     static_assert(BM >= 1 && BN >= 1, "each wave holds at least one 32 x 32 block");
     constexpr int SA = 4 * (TM + KW_PAD), SB = 4 * (TN + KW_PAD);   // dwords per LDS row (8 k)
-    __shared__ __attribute__((aligned(16))) unsigned As[2][4 * SA];
-    __shared__ __attribute__((aligned(16))) unsigned Bs[2][4 * SB];
+    unsigned(*As)[4 * SA] = reinterpret_cast<unsigned(*)[4 * SA]>(lds);
+    unsigned(*Bs)[4 * SB] = reinterpret_cast<unsigned(*)[4 * SB]>(lds + 2 * 4 * SA);
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w / WAVES_N, wn = w % WAVES_N;
     const int h = lane >> 5, r = lane & 31;
     const int ntile = tiles_x * tiles_y;
-    const int bid = blockIdx.x - layer * per_layer, slot = bid >> 3;
+    const int bid = b - layer * per_layer, slot = bid >> 3;
     const int tile = slot % ntile, split = (slot / ntile) * 8 + (bid & 7);
     const int bx = tile % tiles_x, by = tile / tiles_x;
     const int m0 = by * TM, n0 = bx * TN;
@@ -1454,8 +1463,18 @@ __global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgLayers L, int per_lay
             }
 }
 
-// dW = dz^T h for the layer shapes of the network: (256, 256) on 128 x 128 tiles, (256, 32)
-// (input layer) on 128 x 32 tiles, (16, 256) (output layer) on 32 x 128 tiles.
+// the three tile shapes: hidden layers 128 x 128 (2 x 2 waves), input layer 128 x 32 (4 x 1),
+// output layer 32 x 128 (1 x 4); LDS for the largest (two buffers of A and B rows)
+constexpr int WG_LDS_DWORDS = 2 * 4 * 4 * (128 + KW_PAD) * 2;
+__global__ __launch_bounds__(256) void gemm_wgrad_kernel(WgLaunch P)
+{
+    __shared__ __attribute__((aligned(16))) unsigned lds[WG_LDS_DWORDS];
+    const int b = blockIdx.x;
+    if (b < P.g[0].end) wgrad_tile<128, 128, 2, true, true, WG_DEPTH>(P.g[0], b, lds);
+    else if (b < P.g[1].end) wgrad_tile<128, 32, 4, true, false, WG_DEPTH>(P.g[1], b - P.g[0].end, lds);
+    else wgrad_tile<32, 128, 1, false, true, WG_DEPTH>(P.g[2], b - P.g[1].end, lds);
+}
+
 }  // namespace props
 
 using namespace props;
@@ -1612,42 +1631,28 @@ static int launch_fwd(bool train, const FwdArgs &a, hipStream_t s)
 // (16, 256) (output layer) on 32 x 128 tiles in SPLIT_IO splits.  Split z writes its W
 // partials at part + z (O I + O) and its bias partials right after them, so one ordered
 // reduction gives W and b, which are adjacent in the master.
-template <int TM, int TN, int WAVES_M, bool AT, bool BT, int DEPTH>
-static void launch_wgrad(const WgLayers &L, int nl, int O, int I, int n, int nsplit, int &splits, hipStream_t s)
-{
-    const int kchunk = ((n + nsplit - 1) / nsplit + 31) / 32 * 32;
-    splits = (n + kchunk - 1) / kchunk;
-    const int tiles_x = (I + TN - 1) / TN, tiles_y = (O + TM - 1) / TM;
-    const int per_layer = tiles_x * tiles_y * ((splits + 7) / 8 * 8);
-    const int64_t stride = (int64_t)O * I + O;
-    hipLaunchKernelGGL((gemm_wgrad_kernel<TM, TN, WAVES_M, AT, BT, DEPTH>), dim3(per_layer * nl), dim3(256), 0, s, L,
-                       per_layer, O, O, I, I, n, kchunk, tiles_x, tiles_y, I, stride);
-}
+static int wgrad_nsplit(int O, int I) { return (O % 128 == 0 && I % 128 == 0) ? SPLIT_HID : SPLIT_IO; }
 
-// nl layers of one shape O x I in one launch (dz of layer j in L.A[j], its inputs in L.B[j],
-// its partials at L.C[j])
-static int wgrad(const WgLayers &L, int nl, int O, int I, int n, int &splits, hipStream_t s)
-{
-    // hidden layers: both operands in the saved-array layout; layer 0: dz saved, the inputs
-    // row-major [n][32]; output layer: dz row-major [n][16], h saved
-    if (O % 128 == 0 && I % 128 == 0)
-        launch_wgrad<128, 128, 2, true, true, WG_DEPTH>(L, nl, O, I, n, SPLIT_HID, splits, s);
-    else if (O % 128 == 0 && I == 32)
-        launch_wgrad<128, 32, 4, true, false, WG_DEPTH>(L, nl, O, I, n, SPLIT_IO, splits, s);
-    else if (O <= 32 && O % 8 == 0 && I % 128 == 0)
-        launch_wgrad<32, 128, 1, false, true, WG_DEPTH>(L, nl, O, I, n, SPLIT_IO, splits, s);
-    else
-        return fail(PROPS_EINVAL, "wgrad: unsupported layer shape %d x %d", O, I);
-    PROPS_HIP_TRY(hipGetLastError());
-    return PROPS_OK;
-}
-
-// the number of batch splits wgrad uses for a layer of O x I on n rows
+// the number of batch splits of a layer of O x I on n rows
 static int wgrad_splits(int O, int I, int n)
 {
-    const int nsplit = (O % 128 == 0 && I % 128 == 0) ? SPLIT_HID : SPLIT_IO;
+    const int nsplit = wgrad_nsplit(O, I);
     const int kchunk = ((n + nsplit - 1) / nsplit + 31) / 32 * 32;
     return (n + kchunk - 1) / kchunk;
+}
+
+// the shape group of nl layers of O x I (tiles TM x TN) whose block range starts at `start`
+static void wgrad_group(WgGroup &G, int nl, int O, int I, int TM, int TN, int n, int start)
+{
+    const int nsplit = wgrad_nsplit(O, I);
+    G.kchunk = ((n + nsplit - 1) / nsplit + 31) / 32 * 32;
+    const int splits = (n + G.kchunk - 1) / G.kchunk;
+    G.tiles_x = (I + TN - 1) / TN;
+    G.tiles_y = (O + TM - 1) / TM;
+    G.per_layer = G.tiles_x * G.tiles_y * ((splits + 7) / 8 * 8);
+    G.end = start + G.per_layer * nl;
+    G.lda = O, G.M = O, G.ldb = I, G.N = I, G.K = n, G.ldc = I;
+    G.strideC = (int64_t)O * I + O;
 }
 
 // The training set as rows of SAMPLE_FLOATS floats (inputs, targets, zeros): the epoch
@@ -1743,20 +1748,27 @@ static int fwd_bwd(props_dnn_s *d, const float *XY, int64_t nx, uint64_t pa, uin
         d->gp.splits[l] = wgrad_splits(O, I, n);
         pl += (size_t)d->gp.splits[l] * ((size_t)O * I + O);
     }
-    // output layer, the hidden layers together, input layer
-    const int groups[3][2] = {{nh, nh}, {nh - 1, 1}, {0, 0}};   // layers hi .. lo of each launch
-    for (const auto &gr : groups) {
-        WgLayers L{};
-        int nl = 0;
-        for (int l = gr[0]; l >= gr[1]; l--, nl++) {
-            L.A[nl] = (l == nh) ? d->dzo : d->zs[l];
-            L.B[nl] = (l == 0) ? d->h0 : d->hs[l - 1];
-            L.C[nl] = lpart_of[l];
-        }
-        int splits = 0;
-        if ((rc = wgrad(L, nl, lout(gr[0], nh), lin(gr[0]), n, splits, s))) return rc;
-        if (splits != d->gp.splits[gr[0]]) return fail(PROPS_EINVAL, "wgrad: split count mismatch");
+    // one launch: the hidden layers (both operands in the saved-array layout), the input layer
+    // (dz saved, the inputs row-major [n][32]), the output layer (dz row-major [n][16], h saved)
+    WgLaunch P{};
+    for (int l = nh - 1, j = 0; l >= 1; l--, j++) {
+        P.g[0].A[j] = d->zs[l];
+        P.g[0].B[j] = d->hs[l - 1];
+        P.g[0].C[j] = lpart_of[l];
     }
+    wgrad_group(P.g[0], nh - 1, HID, HID, 128, 128, n, 0);
+    P.g[1].A[0] = d->zs[0];
+    P.g[1].B[0] = d->h0;
+    P.g[1].C[0] = lpart_of[0];
+    wgrad_group(P.g[1], 1, HID, IN_PAD, 128, 32, n, P.g[0].end);
+    P.g[2].A[0] = d->dzo;
+    P.g[2].B[0] = d->hs[nh - 1];
+    P.g[2].C[0] = lpart_of[nh];
+    wgrad_group(P.g[2], 1, OUT_PAD, HID, 32, 128, n, P.g[1].end);
+    static_assert(IN_PAD == 32 && OUT_PAD <= 32 && OUT_PAD % 8 == 0 && HID % 128 == 0,
+                  "the three tile shapes of gemm_wgrad_kernel");
+    hipLaunchKernelGGL(gemm_wgrad_kernel, dim3(P.g[2].end), dim3(256), 0, s, P);
+    PROPS_HIP_TRY(hipGetLastError());
     return PROPS_OK;
 }
 
