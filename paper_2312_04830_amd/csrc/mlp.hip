@@ -15,20 +15,20 @@
 // touches the bias.  GELU (tanh form, hardware exp2 and reciprocal) is applied in FP32 on
 // the accumulators, then packed to bf16 with v_cvt_pk_bf16_f32 (round to nearest even).
 //
-// Weight streaming: two independent 4-wave workgroups per CU, each with a ring of four
-// 32-row weight slots in LDS (67.6 KB).  Every tile of 128 cells walks the same sequence of
-// weight blocks (layer 0 whole, then the hidden layers' 32-row output blocks, then the output
-// layer); slots are filled a pair at a time with global_load_lds, one pair ahead of the one
-// being used, so staging overlaps the matrix-core work and the two workgroups of a CU, in
-// unrelated phases, fill each other's barrier and GELU-only stretches.
+// Weight streaming: one persistent 8-wave workgroup per CU (two waves per SIMD) walks 256-cell
+// tiles; every tile walks the same sequence of weight blocks (the hidden layers' 32-row output
+// blocks, the output layer, then the next tile's layer 0), staged a pair of blocks at a time
+// with global_load_lds into a ring of three slot pairs in LDS (101 KB), two pairs ahead of the
+// one in use, so staging overlaps the matrix-core work.
 //
-// Backward: dH = dZ W with the GELU derivative fused in the epilogue (128 x 256 tiles on the
-// 32x32x16 MFMA, W kept transposed so both operands are contiguous along K), dW = dZ^T H on
-// the 32x32x16 MFMA with both operands k-major (split over the batch with a fixed-order
-// reduction: training is deterministic and resumable bit for bit) and the bias gradient as
-// the column sums of dZ in the same pass, Adam on FP32 master weights.  The forward keeps
-// bf16 copies of pre-activations and activations for the backward, and writes the output
-// layer's L1 gradient directly.
+// Backward: dz of every hidden layer in one fused pass (mlp_bwd_kernel: per tile, dz of a layer
+// is (dz of the next) x W with the GELU derivative at the saved bf16 z, kept in registers from
+// layer to layer like the forward's activations, the transposed weights streamed through the
+// same kind of ring); dW = dz^T h on the 32x32x16 MFMA with both operands k-major, split over
+// the batch with a fixed-order reduction (training is deterministic and resumable bit for
+// bit), the bias gradient as dz^T times ones in the same pass; Adam on FP32 master weights.
+// The forward keeps bf16 copies of pre-activations and activations for the backward, and
+// writes the output layer's L1 gradient directly.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
