@@ -75,12 +75,16 @@ def log_flags(mask):
 
 
 def transform_outputs(Y, lo, hi, log_outputs=LOG_OUTPUTS):
-    """Raw outputs [n, 6] -> targets in [0, 1] (log first for the flagged outputs)."""
+    """Raw outputs [n, 6] -> targets in [0, 1] (log first for the flagged outputs).  A target
+    with an empty range (constant in the training data) scales to 0, like a constant input
+    feature: the network then learns 0, which maps back to that constant."""
     T = np.array(Y, dtype=np.float64, copy=True)
     for j, lg in enumerate(log_outputs):
         if lg:
             T[:, j] = np.log(T[:, j])
-    return (T - lo) / (hi - lo)
+    rng = np.asarray(hi, dtype=np.float64) - np.asarray(lo, dtype=np.float64)
+    safe = np.where(rng > 0, rng, 1.0)
+    return np.where(rng > 0, (T - lo) / safe, 0.0)
 
 
 def untransform_outputs(S, lo, hi, log_outputs=LOG_OUTPUTS):

@@ -140,18 +140,21 @@ def test_forward_matches_bf16_oracle_several_tiles_with_fallback(props, orc, sp8
         assert err.max() < MIXED_BAR, (k, err.max())
 
 
-@pytest.mark.parametrize("mask,n", [(0x35, 65536), (0x35, 65536 - 77), (0x3F, 8192), (0x00, 8192)])
+@pytest.mark.parametrize("mask,n", [(0x35, 65536), (0x35, 65536 - 77), (0x3F, 8192), (0x00, 8192), (0x35, 33), (0x35, 1)])
 def test_gradient_matches_bf16_oracle_elementwise(props, orc, sp8, mask, n):
     """The L1 gradient on the scaled targets, every weight and bias element against the
     bf16-emulating oracle, at the training batch of 65,536 (every weight-gradient GEMM at its
     full split count and depth; 77 rows short of it, the last split of every layer ends in a
     partial 32-row step) for the default log outputs (rho, cp, mu, lambda), and for networks
-    that log-transform all or none of their outputs."""
-    X, L = labelled_states(orc, sp8, n, seed=32)
+    that log-transform all or none of their outputs; and on 33 rows and a single row (one
+    split of one partial step, the other workgroups of each XCD's split group idle; the boxes
+    are then fitted on 256 rows, the first n of which are the batch)."""
+    X, L = labelled_states(orc, sp8, max(n, 256), seed=32)
     if mask == 0x3F:
         L = np.abs(L) + 1.0                       # every target positive
     flags = omlp.log_flags(mask)
     ilo, ihi, olo, ohi = omlp.fit_scalers(X.T, L.T, flags)
+    X, L = np.ascontiguousarray(X[:, :n]), np.ascontiguousarray(L[:, :n])
     params = rounded_params(omlp.init_params(np.random.default_rng(6)))
     net = props.Network(seed=2)
     net.set_log_outputs(mask)

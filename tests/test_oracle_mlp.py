@@ -102,6 +102,20 @@ def test_output_transform_round_trip():
 
 # ------------------------------------------------------------------ training: optimizer, schedule, sample order
 
+def test_constant_target_scales_to_zero_and_maps_back():
+    """A target constant over the training data (empty range) scales to 0, as a constant
+    input feature does, and 0 maps back to that constant; the other targets are unaffected."""
+    rng = np.random.default_rng(3)
+    Y = np.exp(rng.uniform(-1.0, 1.0, (5, 6)))
+    Y[:, 2] = 4.25
+    flags = mlp.log_flags(0x35)
+    lo, hi = mlp.fit_scalers(np.zeros((5, 10)), Y, flags)[2:]
+    assert lo[2] == hi[2]
+    S = mlp.transform_outputs(Y, lo, hi, flags)
+    assert np.all(np.isfinite(S)) and np.all(S[:, 2] == 0.0)
+    assert np.allclose(mlp.untransform_outputs(S, lo, hi, flags), Y, rtol=1e-14, atol=0)
+
+
 def test_splitmix64_reproduces_the_published_outputs():
     import json
     import os
