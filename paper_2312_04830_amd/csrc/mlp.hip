@@ -1225,12 +1225,11 @@ template <int W, bool SAVED>
 struct WgOperand {
     static constexpr int CG = SAVED ? W / 4 : W / 8;   // column groups
     static constexpr int NITEM = 8 * CG;
-    static constexpr int NLOAD = SAVED ? 2 : 4;
     static_assert(NITEM <= 256, "one item per thread");
     const bf16_t *base;   // item's first load at step 0 (saved) or its column (row-major)
     int rp, cg;
     bool live;            // item index below NITEM
-    __device__ WgOperand(const bf16_t *X, int ld, int c0, int ncol, int kbeg, int t)
+    __device__ WgOperand(const bf16_t *X, int c0, int ncol, int kbeg, int t)
     {
         live = t < NITEM;
         const int q = live ? t : 0;
@@ -1246,7 +1245,6 @@ struct WgOperand {
             const int col = c0 + 8 * cg;
             base = X + (col < ncol ? col : 0);   // columns past the operand read its first ones
         }
-        (void)ld;
     }
     // loads of step j (clamped to the last step je); rows past kend of a row-major operand
     // read row kend - 1
@@ -1361,8 +1359,8 @@ __device__ __forceinline__ void wgrad_tile(const WgGroup &G, int b, unsigned *ld
     const int kend = min(K, kbeg + kchunk);
     const int nsteps = kend > kbeg ? (kend - kbeg + 31) / 32 : 0;
     const int jlast = max(nsteps - 1, 0);
-    const WgOperand<TM, AT> opA(A, lda, m0, M, kbeg, t);
-    const WgOperand<TN, BT> opB(B, ldb, n0, N, kbeg, t);
+    const WgOperand<TM, AT> opA(A, m0, M, kbeg, t);
+    const WgOperand<TN, BT> opB(B, n0, N, kbeg, t);
 
     f32x16 acc[BM][BN];
 #pragma unroll
