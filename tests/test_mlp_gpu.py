@@ -291,6 +291,30 @@ def test_training_fits_the_box_of_the_log_targets(props):
     assert np.array_equal(ilo, X.astype(np.float64).min(1)) and np.array_equal(ihi, X.astype(np.float64).max(1))
 
 
+def test_training_and_gradient_calls_free_their_sample_rows(props):
+    """train_dnn and the gradient entry point copy the set into 64-byte sample rows and free
+    the copy before they return: repeated calls leave the device's free memory where it was
+    (within one copy)."""
+    import torch
+    rng = np.random.default_rng(41)
+    n = 1 << 17
+    X = rng.uniform(0, 1, (10, n)).astype(np.float32)
+    Yl = np.vstack([1 + X[0], X[1], 1 + X[2], X[3], 1 + X[4], 1 + X[5]]).astype(np.float32)
+    Xd, Yd = dev(X), dev(Yl)
+    net = props.Network(seed=4)
+    net.train(Xd, Yd, n, epochs=1, batch=65536, seed=1)   # scratch of the handle allocated here
+    net.grad(Xd, Yd, 4096)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(3):
+        net.train(Xd, Yd, n, epochs=1, batch=65536, seed=1, fit_scalers=False)
+        net.grad(Xd, Yd, 4096)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    print(f"[mlp sample rows] free memory before {free0 / 2**20:.1f} MiB, after {free1 / 2**20:.1f} MiB", flush=True)
+    assert abs(free1 - free0) < n * 64
+
+
 def test_training_resume_is_bitwise(props, tmp_path):
     """2 epochs + save/load + 2 epochs == 4 epochs in one go (weights, bit for bit)."""
     rng = np.random.default_rng(40)
